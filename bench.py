@@ -1,0 +1,158 @@
+"""Benchmark: solves/s of the plain FP64 single-period solve on one MI355X.
+
+Workload: single-period portfolio problems (paper eq. 1-3) with n = 5000 assets,
+k = 60 factors, m = 80 exposure rows (20 sector + 60 factor-loading rows), d = 1.5,
+seeds 1..10 of the synthetic market generator; solved to relative KKT <= 1e-6.
+One step = one solve of each of the 10 instances (inputs resident on the GPU before
+the timed region).  Prints one JSON line.
+
+Roofline: the dominant kernel is the persistent solve kernel (one launch per solve).
+Algorithmic bytes per PDHG iteration follow the streaming model
+    B_iter = 2 (m+k) n w + n (4P + 5T' + 3) w,   w = 8 bytes,
+i.e. the constraint rows read once for K^T y and once for K x, plus the per-asset
+vectors; achieved = iterations x B_iter / kernel time, measured per launch with HIP
+events on the solve stream.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "solves/s to 1e-6 rel KKT (n=5000; T=20); batched/FP32 vs plain; HBM % peak"
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--config", type=int, default=1)
+    ap.add_argument("--tol", type=float, default=1e-6)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--cpu-max-iter", type=int, default=40000)
+    ap.add_argument("--workgroups", type=int, default=0)
+    return ap.parse_args()
+
+
+def algorithmic_bytes_per_iter(n, k, m, P, Tp, w=8):
+    return 2 * (m + k) * n * w + n * (4 * P + 5 * Tp + 3) * w
+
+
+def cpu_baseline(inst, tol, max_iter):
+    """The oracle's first-order stage (averaged PDHG) to the same relative KKT, on one
+    instance; the active-set polish is excluded."""
+    from oracle.problem import normalize
+    from oracle.pdhg import pdhg
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max([d.get("num_threads", 1) for d in threadpool_info()] + [1])
+    except Exception:  # pragma: no cover
+        cores = os.cpu_count() or 1
+    pb = normalize(inst)
+    t0 = time.perf_counter()
+    r = pdhg(pb, tol=tol, max_iter=max_iter)
+    dt = time.perf_counter() - t0
+    return {"value": (1.0 / dt) if r.rel_kkt <= tol else 0.0, "unit": "solves/s", "cores": int(cores),
+            "kind": "oracle",
+            "sample": (f"1 instance (seed {inst['seed']}) of the same workload; oracle averaged PDHG to rel KKT "
+                       f"{tol:g} ({r.iters} iterations, reached {r.rel_kkt:.2e}, {dt:.1f} s); polish excluded")}
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}), flush=True)
+        print("bench.py: only --gpus 1 is supported (single-GPU solver; see DESIGN.md for sharding)",
+              file=sys.stderr)
+        sys.exit(2)
+    import torch
+    import paper_2604_22625_amd as ff
+    from synth import make_config, CONFIGS
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    cfg = CONFIGS[a.config]
+    seeds = list(cfg["seeds"])
+    dev = torch.device("cuda", 0)
+    insts = [make_config(a.config, seed=sd) for sd in seeds]
+    keys = ("alpha", "F", "Omega", "delta", "s", "q", "A", "L", "U", "w0", "w_target")
+    dev_insts = []
+    for inst in insts:
+        d = dict(inst)
+        for kk in keys:
+            if d.get(kk) is not None:
+                d[kk] = torch.as_tensor(d[kk], dtype=torch.float64, device=dev).contiguous()
+        dev_insts.append(d)
+    n, k, m = cfg["n"], cfg["k"], cfg["m"]
+    T = cfg.get("T", 0)
+    P = 1 if T == 0 else T - 1
+    Tp = 1 if T == 0 else T
+    outs = [torch.empty((P, n), dtype=torch.float64, device=dev) for _ in insts]
+    torch.cuda.synchronize()
+
+    def step(record):
+        for d, W in zip(dev_insts, outs):
+            _, info = ff.solve_instance(d, tol=a.tol, out=W, workgroups=a.workgroups)
+            if record is not None:
+                record.append(info)
+
+    for _ in range(a.warmup):
+        step(None)
+    torch.cuda.synchronize()
+    infos = []
+    t0 = time.perf_counter()
+    for _ in range(a.steps):
+        step(infos)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    solves = len(infos)
+    value = solves / dt
+    iters = np.array([i.iters for i in infos], dtype=np.float64)
+    kms = np.array([i.ms_iter for i in infos])
+    sms = np.array([i.ms_setup for i in infos])
+    bpi = algorithmic_bytes_per_iter(n, k, m, P, Tp)
+    achieved = float((iters * bpi).sum() / (kms.sum() * 1e-3) / 1e9)
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": dt * 1e3 / a.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"single-period portfolio solve, n={n} k={k} m={m} (sector + factor rows), d=1.5, "
+                               f"seeds {seeds[0]}-{seeds[-1]}, plain FP64, to rel KKT {a.tol:g}",
+                   "n": n, "k": k, "m": m, "T": T, "instances_per_step": len(insts), "tol": a.tol},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None},
+        "iters_mean": float(iters.mean()),
+        "kernel_ms_mean": float(kms.mean()),
+        "setup_ms_mean": float(sms.mean()),
+        "us_per_iter": float(kms.sum() * 1e3 / iters.sum()),
+        "rel_kkt_max": float(max(i.rel_kkt for i in infos)),
+        "status_all_ok": bool(all(i.status == 0 for i in infos)),
+        "bytes_per_iter": bpi,
+    }
+    if not a.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(insts[0], a.tol, a.cpu_max_iter)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,147 @@
+/*
+ * ffolio.h - C interface of the MI355X (gfx950) first-order portfolio solver.
+ *
+ * The library solves the two models of "FlashFolio: A GPU-Accelerated Solver for
+ * Portfolio Optimization" (Jiang, Lu, Peng, Yang; arXiv 2604.22625):
+ *
+ *   single-period (Section 2.1, eq. 1-3):
+ *     max_w  GMV a^T w - l1 GMV^2 w^T S w - l2 GMV s^T|w - w0| - l3 GMV q^T|w - w0|^d
+ *     s.t.   L <= A w <= U,   ||w||_1 <= 1
+ *
+ *   multi-period (Section 2.2, eq. 4-6), decisions w_1..w_{T-1}, w_0 and w_T given:
+ *     max    sum_{t=1..T} GMV a_t^T w_t - l1 GMV^2 (w_t - w_T)^T S (w_t - w_T)
+ *                         - l2 GMV s_t^T|w_t - w_{t-1}| - l3 GMV q_t^T|w_t - w_{t-1}|^d
+ *     s.t.   L <= A w_t <= U,  ||w_t||_1 <= 1   for t = 1..T-1
+ *
+ * with the factor risk model S = F Omega F^T + diag(delta^2) (Section 3.2).  The
+ * paper states the problems but not its iteration; this library runs a restarted,
+ * reflected Halpern primal-dual hybrid gradient method on the splitting
+ *   g(W) = sum_t [-a_t^T w_t + g1 sum_i delta_i^2 (w_ti - c_i)^2 + I{||w_t||_1 <= 1}],
+ *   h    = I_[L,U](A w_t) + g1 ||F_c^T (w_t - c)||^2 + sum_t cost_t(u_t),
+ * with g1 = l1 GMV, F_c = F chol(Omega), c = 0 or w_T, and trades u_t = w_t - w_{t-1}.
+ * Every step of that iteration runs in HIP kernels on the device.
+ *
+ * Conventions for every entry point:
+ *  - All array arguments are DEVICE pointers to contiguous row-major float64 data,
+ *    owned by the caller.  The library never frees or retains them beyond the call.
+ *  - `stream` is a hipStream_t (NULL = the null stream).  Work is enqueued on it; the
+ *    call returns after the solve has finished (it reads the final status back).
+ *  - On FFO_EINVAL nothing has been launched and the outputs are untouched.
+ *  - The library keeps a per-device workspace cache (grown on demand, freed by
+ *    ffo_release or at process exit).  Calls on different host threads must use
+ *    different streams; calls that overlap on one device share no state.
+ *  - ffo_last_error() returns a thread-local message for the last non-OK status.
+ */
+#ifndef FFOLIO_H
+#define FFOLIO_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  FFO_OK = 0,
+  FFO_EINVAL = 1,          /* bad size, pointer or scalar; nothing launched            */
+  FFO_ENOMEM = 2,          /* device workspace allocation failed                      */
+  FFO_EDEVICE = 3,         /* a HIP call or a device-side consistency check failed    */
+  FFO_NOT_CONVERGED = 4,   /* max_iter reached; outputs hold the last iterate         */
+  FFO_NUMERIC = 5,         /* NaN/Inf met in an FP64 check; outputs hold the last
+                              finite restart point                                    */
+  FFO_INFEASIBLE = 6,      /* reserved: dual iterates diverge (infeasible bounds)     */
+  FFO_TIMEOUT = 7          /* time_limit_s reached; outputs hold the last iterate     */
+} ffo_status;
+
+typedef enum {
+  FFO_FP64 = 0,            /* every vector and matrix in float64                      */
+  FFO_FP32 = 1,            /* iterates and matrix in float32; checks, restarts and the
+                              KKT residual accumulated in float64                     */
+  FFO_FP32_BF16K = 2       /* as FP32, with the constraint matrix in bfloat16        */
+} ffo_precision;
+
+typedef struct {
+  double tol_rel_kkt;      /* stop when the relative KKT error <= tol (default 1e-6)  */
+  int64_t max_iter;        /* iteration cap (default 1000000)                          */
+  double time_limit_s;     /* wall-clock cap per solve (default 360, paper Sec. 4.1)  */
+  int32_t check_every;     /* iterations between FP64 checks (default 64)             */
+  int32_t precision;       /* ffo_precision (default FFO_FP64)                        */
+  double restart_suff;     /* restart when residual <= suff * residual at restart (0.2) */
+  double restart_nec;      /* ... or <= nec * that and no longer decreasing (0.8)     */
+  double restart_art;      /* ... or the epoch is >= art * total iterations (0.36)    */
+  double reflection;       /* rho of the reflected Halpern step, in [0, 1] (1.0)      */
+  int32_t workgroups;      /* workgroups of the persistent solve kernel, 0 = auto     */
+  int32_t verbose;         /* nonzero: print per-check progress to stderr             */
+} ffo_options;
+
+typedef struct {
+  int32_t status;          /* ffo_status of the solve                                  */
+  int64_t iters;           /* PDHG iterations run                                      */
+  int64_t restarts;        /* restarts taken                                           */
+  double rel_kkt;          /* max(rel_pri, rel_dual, rel_gap) at the returned point    */
+  double rel_pri;          /* ||A W - clip(A W, L, U)|| / (1 + ||clip(A W, L, U)||)    */
+  double rel_dual;         /* distance of Y to the conjugate's domain / (1 + ||Y||)   */
+  double rel_gap;          /* |Phi - Psi| / (|Phi| + |Psi|)                            */
+  double fixed_point_res;  /* ||z - T(z)|| in the PDHG metric at the last check        */
+  double primal_obj;       /* Phi(W) = -(paper objective)/GMV, without the multi-period
+                              constant a_T^T w_T                                       */
+  double dual_obj;         /* Psi(Y), the closed-form dual of the splitting            */
+  double omega;            /* final primal weight                                      */
+  double ms_setup;         /* setup time (scaling, factorisation), milliseconds        */
+  double ms_iter;          /* iteration time, milliseconds                             */
+} ffo_info;
+
+/* Fill `opt` with the defaults listed above. */
+void ffo_default_options(ffo_options* opt);
+
+/*
+ * Solve one single-period (T == 0) or multi-period (T >= 2) instance.
+ *
+ * Sizes: n >= 1 assets, k >= 0 factors, m >= 0 exposure rows; P = 1 if T == 0 else
+ * T-1 decision periods; T' = 1 if T == 0 else T trades.
+ *   alpha    [P][n]    expected returns a_t (paper eq. 1 / eq. 4)
+ *   F        [n][k]    factor loadings (the paper's beta, Section 3.2)
+ *   Omega    [k][k]    factor covariance, symmetric positive semidefinite
+ *   delta    [n]       specific volatilities, S = F Omega F^T + diag(delta^2)
+ *   s, q     [T'][n]   spread and impact coefficients, >= 0 (eq. 1 / eq. 4)
+ *   d                  impact exponent, 1 < d <= 2 (Section 2.1)
+ *   A        [m][n]    exposure matrix; L, U [m] its bounds (+-inf allowed, L <= U)
+ *   w0       [n]       initial portfolio
+ *   GMV > 0, lambda1, lambda2, lambda3 >= 0   (lambda1 > 0 and delta > 0 required)
+ *   w_target [n]       terminal portfolio w_T; must be NULL iff T == 0
+ *   opt                options (NULL = defaults)
+ *   stream             hipStream_t
+ * Outputs (caller-allocated device memory):
+ *   w_out    [P][n]    the solution W
+ *   y_out    optional, [P*m + P*k + T'*n]: the dual point (y_A [P][m], y_F [P][k],
+ *            y_C [T'][n]) of the splitting in the header comment, so that the dual
+ *            objective can be evaluated independently.  y_F is expressed in the basis
+ *            F_c = F C with C the lower-triangular Cholesky factor of Omega (when Omega
+ *            is only semidefinite: C = V diag(sqrt(max(lambda, 0))) from a Jacobi
+ *            eigendecomposition Omega = V diag(lambda) V^T).  NULL to skip
+ *   info     host pointer, filled on every status except FFO_EINVAL
+ * Returns FFO_OK when the relative KKT error reached opt->tol_rel_kkt.
+ */
+ffo_status ffo_solve(int64_t n, int64_t k, int64_t m, int64_t T,
+                     const double* alpha, const double* F, const double* Omega,
+                     const double* delta, const double* s, const double* q, double d,
+                     const double* A, const double* L, const double* U, const double* w0,
+                     double GMV, double lambda1, double lambda2, double lambda3,
+                     const double* w_target, const ffo_options* opt, void* stream,
+                     double* w_out, double* y_out, ffo_info* info);
+
+/* Thread-local description of the last non-OK status ("" if none). */
+const char* ffo_last_error(void);
+
+/* Free the cached device workspaces of every device.  Safe to call at any time when
+ * no solve is running. */
+void ffo_release(void);
+
+/* Library version string. */
+const char* ffo_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FFOLIO_H */

@@ -78,8 +78,12 @@ class Problem:
         return self.T > 0
 
 
-def normalize(inst: dict) -> Problem:
-    """Scale the paper's maximisation (eq. 1 / eq. 4) to the minimisation form Phi."""
+def normalize(inst: dict, factor: np.ndarray | None = None) -> Problem:
+    """Scale the paper's maximisation (eq. 1 / eq. 4) to the minimisation form Phi.
+
+    ``factor``: optional k x k matrix C with C C^T = Omega fixing the coordinates of the
+    factor dual y_F (G = F C); default: the eigendecomposition of Omega.  Phi, W* and
+    Psi's value do not depend on this choice, only the meaning of y_F does."""
     T = int(inst.get("T", 0) or 0)
     alpha = np.atleast_2d(np.asarray(inst["alpha"], dtype=np.float64))
     n = alpha.shape[1]
@@ -113,7 +117,13 @@ def normalize(inst: dict) -> Problem:
     else:
         wT = None
         c = np.zeros(n)
-    G = F @ risk_factor(Omega) if k > 0 else np.zeros((n, 0))
+    if k > 0 and factor is not None:
+        C = np.asarray(factor, dtype=np.float64).reshape(k, k)
+        if not np.allclose(C @ C.T, 0.5 * (Omega + Omega.T), rtol=1e-10, atol=1e-14 * max(1.0, np.abs(Omega).max())):
+            raise ValueError("factor does not satisfy C C^T = Omega")
+    else:
+        C = risk_factor(Omega) if k > 0 else None
+    G = F @ C if k > 0 else np.zeros((n, 0))
     return Problem(n=n, k=k, m=m, T=T, P=P, Tp=Tp, alpha=alpha, F=F, Omega=Omega, G=G,
                    delta2=delta * delta, ca=g2 * s, cb=g3 * q, d=d, A=A, L=L, U=U, w0=w0,
                    wT=wT, c=c, g1=g1, g2=g2, g3=g3, GMV=GMV)

@@ -1,0 +1,193 @@
+"""MI355X (gfx950) first-order solver for the FlashFolio portfolio models (arXiv 2604.22625).
+
+Thin Python binding over the C library ``libffolio.so`` (include/ffolio.h).  This module
+only marshals arguments: every step of the solve runs in the library's HIP kernels.
+PyTorch provides device memory and the current HIP stream.  There is no CPU fallback:
+if the library or a GPU is missing, the calls raise.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass, asdict
+
+import numpy as np
+
+__all__ = ["solve", "solve_instance", "Info", "FolioError", "lib", "LIB_PATH", "STATUS"]
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libffolio.so")
+
+STATUS = {0: "OK", 1: "EINVAL", 2: "ENOMEM", 3: "EDEVICE", 4: "NOT_CONVERGED", 5: "NUMERIC",
+          6: "INFEASIBLE", 7: "TIMEOUT"}
+
+
+class FolioError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"ffolio status {status} ({STATUS.get(status, '?')}): {msg}")
+        self.status = status
+
+
+class _Options(ctypes.Structure):
+    _fields_ = [("tol_rel_kkt", ctypes.c_double), ("max_iter", ctypes.c_int64),
+                ("time_limit_s", ctypes.c_double), ("check_every", ctypes.c_int32),
+                ("precision", ctypes.c_int32), ("restart_suff", ctypes.c_double),
+                ("restart_nec", ctypes.c_double), ("restart_art", ctypes.c_double),
+                ("reflection", ctypes.c_double), ("workgroups", ctypes.c_int32),
+                ("verbose", ctypes.c_int32)]
+
+
+class _Info(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("iters", ctypes.c_int64), ("restarts", ctypes.c_int64),
+                ("rel_kkt", ctypes.c_double), ("rel_pri", ctypes.c_double), ("rel_dual", ctypes.c_double),
+                ("rel_gap", ctypes.c_double), ("fixed_point_res", ctypes.c_double),
+                ("primal_obj", ctypes.c_double), ("dual_obj", ctypes.c_double), ("omega", ctypes.c_double),
+                ("ms_setup", ctypes.c_double), ("ms_iter", ctypes.c_double)]
+
+
+@dataclass
+class Info:
+    status: int
+    iters: int
+    restarts: int
+    rel_kkt: float
+    rel_pri: float
+    rel_dual: float
+    rel_gap: float
+    fixed_point_res: float
+    primal_obj: float
+    dual_obj: float
+    omega: float
+    ms_setup: float
+    ms_iter: float
+
+    def as_dict(self) -> dict:
+        return asdict(self)
+
+
+_lib = None
+_P = ctypes.c_void_p
+_D = ctypes.c_double
+_I64 = ctypes.c_int64
+
+
+def lib() -> ctypes.CDLL:
+    """Load libffolio.so (built in-tree by paper_2604_22625_amd.build)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2604_22625_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        L.ffo_default_options.argtypes = [ctypes.POINTER(_Options)]
+        L.ffo_default_options.restype = None
+        L.ffo_solve.argtypes = [_I64, _I64, _I64, _I64, _P, _P, _P, _P, _P, _P, _D, _P, _P, _P, _P,
+                                _D, _D, _D, _D, _P, ctypes.POINTER(_Options), _P, _P, _P,
+                                ctypes.POINTER(_Info)]
+        L.ffo_solve.restype = ctypes.c_int
+        L.ffo_last_error.argtypes = []
+        L.ffo_last_error.restype = ctypes.c_char_p
+        L.ffo_release.argtypes = []
+        L.ffo_release.restype = None
+        L.ffo_version.argtypes = []
+        L.ffo_version.restype = ctypes.c_char_p
+        _lib = L
+    return _lib
+
+
+def default_options() -> _Options:
+    o = _Options()
+    lib().ffo_default_options(ctypes.byref(o))
+    return o
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _dev_f64(x, device):
+    """Contiguous float64 tensor on `device` (None passes through)."""
+    if x is None:
+        return None
+    torch = _torch()
+    if not isinstance(x, torch.Tensor):
+        x = torch.as_tensor(np.asarray(x, dtype=np.float64))
+    return x.to(device=device, dtype=torch.float64).contiguous()
+
+
+def _ptr(t):
+    return ctypes.c_void_p(0 if t is None else t.data_ptr())
+
+
+def solve(alpha, F, Omega, delta, s, q, d, A, L, U, w0, GMV, lambda1, lambda2, lambda3,
+          w_target=None, *, tol: float = 1e-6, max_iter: int = 1_000_000, time_limit_s: float = 360.0,
+          check_every: int = 64, restart=(0.2, 0.8, 0.36), reflection: float = 1.0,
+          workgroups: int = 0, verbose: bool = False, return_dual: bool = False,
+          raise_on_failure: bool = True, device=None, stream=None, out=None):
+    """Solve one single-period (w_target is None) or multi-period instance on the GPU.
+
+    Arrays follow include/ffolio.h: alpha [P][n] (P = 1 or T-1), F [n][k], Omega [k][k],
+    delta [n], s and q [T'][n] (T' = 1 or T), A [m][n], L and U [m], w0 and w_target [n].
+    Returns (W [P][n] float64 CUDA tensor, Info) or (W, Info, (yA, yF, yC)) with
+    ``return_dual``.  Non-OK statuses raise FolioError unless ``raise_on_failure`` is
+    False (NOT_CONVERGED/TIMEOUT/NUMERIC still fill W).
+    """
+    torch = _torch()
+    if not torch.cuda.is_available():
+        raise FolioError(3, "no GPU visible to PyTorch: the solver has no CPU path")
+    dev = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
+    a = _dev_f64(alpha, dev)
+    if a.dim() == 1:
+        a = a[None, :]
+    n = a.shape[1]
+    T = 0 if w_target is None else a.shape[0] + 1
+    Fd = _dev_f64(F, dev).reshape(n, -1)
+    k = Fd.shape[1]
+    Od = _dev_f64(Omega, dev).reshape(k, k) if k else _dev_f64(np.zeros((0, 0)), dev)
+    Ad = _dev_f64(A, dev)
+    Ad = Ad.reshape(-1, n) if Ad is not None and Ad.numel() else _dev_f64(np.zeros((0, n)), dev)
+    m = Ad.shape[0]
+    sd = _dev_f64(s, dev).reshape(-1, n)
+    qd = _dev_f64(q, dev).reshape(-1, n)
+    Ld = _dev_f64(L, dev).reshape(m) if m else _dev_f64(np.zeros(0), dev)
+    Ud = _dev_f64(U, dev).reshape(m) if m else _dev_f64(np.zeros(0), dev)
+    dd = _dev_f64(delta, dev).reshape(n)
+    w0d = _dev_f64(w0, dev).reshape(n)
+    wTd = _dev_f64(w_target, dev).reshape(n) if w_target is not None else None
+    P = 1 if T == 0 else T - 1
+    Tp = 1 if T == 0 else T
+    W = out if out is not None else torch.empty((P, n), dtype=torch.float64, device=dev)
+    Y = torch.empty(P * m + P * k + Tp * n, dtype=torch.float64, device=dev) if return_dual else None
+    o = default_options()
+    o.tol_rel_kkt = float(tol)
+    o.max_iter = int(max_iter)
+    o.time_limit_s = float(time_limit_s)
+    o.check_every = int(check_every)
+    o.restart_suff, o.restart_nec, o.restart_art = (float(v) for v in restart)
+    o.reflection = float(reflection)
+    o.workgroups = int(workgroups)
+    o.verbose = int(bool(verbose))
+    info = _Info()
+    st = torch.cuda.current_stream(dev) if stream is None else stream
+    with torch.cuda.device(dev):
+        rc = lib().ffo_solve(n, k, m, T, _ptr(a), _ptr(Fd if k else None), _ptr(Od if k else None), _ptr(dd),
+                             _ptr(sd), _ptr(qd), float(d), _ptr(Ad if m else None), _ptr(Ld if m else None),
+                             _ptr(Ud if m else None), _ptr(w0d), float(GMV), float(lambda1), float(lambda2),
+                             float(lambda3), _ptr(wTd), ctypes.byref(o), ctypes.c_void_p(st.cuda_stream),
+                             _ptr(W), _ptr(Y), ctypes.byref(info))
+    inf = Info(**{f[0]: getattr(info, f[0]) for f in _Info._fields_})
+    if rc == 1 or (rc in (2, 3)) or (rc != 0 and raise_on_failure):
+        raise FolioError(rc, lib().ffo_last_error().decode())
+    if return_dual:
+        yA = Y[:P * m].reshape(P, m)
+        yF = Y[P * m:P * m + P * k].reshape(P, k)
+        yC = Y[P * m + P * k:].reshape(Tp, n)
+        return W, inf, (yA, yF, yC)
+    return W, inf
+
+
+def solve_instance(inst: dict, **kw):
+    """Solve an instance dict in the layout of ``synth`` (keys alpha, F, Omega, ...)."""
+    T = int(inst.get("T", 0) or 0)
+    return solve(inst["alpha"], inst["F"], inst["Omega"], inst["delta"], inst["s"], inst["q"], inst["d"],
+                 inst["A"], inst["L"], inst["U"], inst["w0"], inst["GMV"], inst["lambda1"], inst["lambda2"],
+                 inst["lambda3"], inst.get("w_target") if T else None, **kw)

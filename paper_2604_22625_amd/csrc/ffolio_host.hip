@@ -1,0 +1,414 @@
+// Host side of the C interface declared in include/ffolio.h.
+//
+// ffo_solve: validate sizes/pointers/scalars on the host (FFO_EINVAL before any HIP
+// call), factor Omega = C C^T on the host (Cholesky, or a Jacobi eigendecomposition
+// when Omega is only semidefinite), assemble and scale the constraint rows with the
+// setup kernels, run the persistent solve kernel, and read back status and info.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/ffolio.h"
+#include "internal.h"
+
+namespace {
+
+thread_local std::string g_err;
+
+ffo_status fail(ffo_status st, const std::string& msg) {
+  g_err = msg;
+  return st;
+}
+
+#define HIPCHK(call)                                                                      \
+  do {                                                                                    \
+    hipError_t e_ = (call);                                                               \
+    if (e_ != hipSuccess) return fail(FFO_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+struct Workspace {
+  void* base = nullptr;
+  size_t bytes = 0;
+  void* host = nullptr;      // pinned host staging
+  size_t host_bytes = 0;
+  hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
+};
+
+std::mutex g_mu;
+std::map<std::pair<int, void*>, Workspace> g_ws;
+
+// Grow-only device workspace for (device, stream).
+ffo_status get_workspace(int dev, void* stream, size_t bytes, size_t host_bytes, Workspace** out) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  Workspace& w = g_ws[{dev, stream}];
+  if (w.bytes < bytes) {
+    if (w.base) hipFree(w.base);
+    w.base = nullptr;
+    w.bytes = 0;
+    if (hipMalloc(&w.base, bytes) != hipSuccess) return fail(FFO_ENOMEM, "hipMalloc of the solver workspace failed");
+    w.bytes = bytes;
+  }
+  if (w.host_bytes < host_bytes) {
+    if (w.host) hipHostFree(w.host);
+    w.host = nullptr;
+    w.host_bytes = 0;
+    if (hipHostMalloc(&w.host, host_bytes, hipHostMallocDefault) != hipSuccess)
+      return fail(FFO_ENOMEM, "hipHostMalloc of the staging buffer failed");
+    w.host_bytes = host_bytes;
+  }
+  for (auto& e : w.ev)
+    if (!e && hipEventCreate(&e) != hipSuccess) return fail(FFO_EDEVICE, "hipEventCreate failed");
+  *out = &w;
+  return FFO_OK;
+}
+
+// C with C C^T = Om (k x k, row-major).  Cholesky first; if a pivot is not positive,
+// cyclic Jacobi eigendecomposition and C = V diag(sqrt(max(lambda, 0))).  Returns false
+// if Om is not symmetric or has an eigenvalue below -1e-10 * max|lambda|.
+bool factor_omega(int k, const double* Om, double* C) {
+  double amax = 0.0;
+  for (int i = 0; i < k * k; ++i) {
+    if (!std::isfinite(Om[i])) return false;
+    amax = std::max(amax, std::fabs(Om[i]));
+  }
+  for (int i = 0; i < k; ++i)
+    for (int j = 0; j < i; ++j)
+      if (std::fabs(Om[i * k + j] - Om[j * k + i]) > 1e-12 * std::max(1.0, amax)) return false;
+  std::vector<double> Lc(k * k, 0.0);
+  bool ok = true;
+  for (int j = 0; j < k && ok; ++j) {
+    double d = Om[j * k + j];
+    for (int p = 0; p < j; ++p) d -= Lc[j * k + p] * Lc[j * k + p];
+    if (!(d > 1e-14 * std::max(amax, 1e-300))) { ok = false; break; }
+    const double r = std::sqrt(d);
+    Lc[j * k + j] = r;
+    for (int i = j + 1; i < k; ++i) {
+      double v = Om[i * k + j];
+      for (int p = 0; p < j; ++p) v -= Lc[i * k + p] * Lc[j * k + p];
+      Lc[i * k + j] = v / r;
+    }
+  }
+  if (ok) {
+    std::copy(Lc.begin(), Lc.end(), C);
+    return true;
+  }
+  // Jacobi eigendecomposition
+  std::vector<double> a(Om, Om + k * k), v(k * k, 0.0);
+  for (int i = 0; i < k; ++i) v[i * k + i] = 1.0;
+  for (int sweep = 0; sweep < 100; ++sweep) {
+    double off = 0.0;
+    for (int i = 0; i < k; ++i)
+      for (int j = i + 1; j < k; ++j) off += a[i * k + j] * a[i * k + j];
+    if (off <= 1e-30 * std::max(amax * amax, 1e-300)) break;
+    for (int p = 0; p < k; ++p)
+      for (int q = p + 1; q < k; ++q) {
+        const double apq = a[p * k + q];
+        if (std::fabs(apq) < 1e-300) continue;
+        const double theta = (a[q * k + q] - a[p * k + p]) / (2.0 * apq);
+        const double t = (theta >= 0 ? 1.0 : -1.0) / (std::fabs(theta) + std::sqrt(theta * theta + 1.0));
+        const double c = 1.0 / std::sqrt(t * t + 1.0), s = t * c;
+        for (int r = 0; r < k; ++r) {
+          const double arp = a[r * k + p], arq = a[r * k + q];
+          a[r * k + p] = c * arp - s * arq;
+          a[r * k + q] = s * arp + c * arq;
+        }
+        for (int r = 0; r < k; ++r) {
+          const double apr = a[p * k + r], aqr = a[q * k + r];
+          a[p * k + r] = c * apr - s * aqr;
+          a[q * k + r] = s * apr + c * aqr;
+        }
+        for (int r = 0; r < k; ++r) {
+          const double vrp = v[r * k + p], vrq = v[r * k + q];
+          v[r * k + p] = c * vrp - s * vrq;
+          v[r * k + q] = s * vrp + c * vrq;
+        }
+      }
+  }
+  double lmax = 0.0;
+  for (int i = 0; i < k; ++i) lmax = std::max(lmax, std::fabs(a[i * k + i]));
+  for (int i = 0; i < k; ++i)
+    if (a[i * k + i] < -1e-10 * std::max(lmax, 1e-300)) return false;
+  for (int r = 0; r < k; ++r)
+    for (int j = 0; j < k; ++j) C[r * k + j] = v[r * k + j] * std::sqrt(std::max(a[j * k + j], 0.0));
+  return true;
+}
+
+// Elementwise device checks of the array values (finite data, delta > 0, s, q >= 0,
+// L <= U); flag[0] receives a bit mask of the failures.
+__global__ void k_validate(int64_t n, int64_t Pn, int64_t Tpn, int64_t nk, int64_t m, const double* alpha,
+                           const double* F, const double* delta, const double* s, const double* q,
+                           const double* L, const double* U, const double* w0, const double* wT,
+                           int* flag) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  int bad = 0;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < Pn; e += stride)
+    if (!isfinite(alpha[e])) bad |= 1;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < nk; e += stride)
+    if (!isfinite(F[e])) bad |= 2;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n; e += stride) {
+    if (!(delta[e] > 0.0) || !isfinite(delta[e])) bad |= 4;
+    if (!isfinite(w0[e])) bad |= 8;
+    if (wT && !isfinite(wT[e])) bad |= 8;
+  }
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < Tpn; e += stride)
+    if (!(s[e] >= 0.0) || !(q[e] >= 0.0) || !isfinite(s[e]) || !isfinite(q[e])) bad |= 16;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < m; e += stride)
+    if (!(L[e] <= U[e]) || isnan(L[e]) || isnan(U[e]) || L[e] == INFINITY || U[e] == -INFINITY) bad |= 32;
+  if (bad) atomicOr(flag, bad);
+}
+
+size_t align_up(size_t x) { return (x + 255) / 256 * 256; }
+
+}  // namespace
+
+extern "C" {
+
+void ffo_default_options(ffo_options* o) {
+  if (!o) return;
+  o->tol_rel_kkt = 1e-6;
+  o->max_iter = 1000000;
+  o->time_limit_s = 360.0;
+  o->check_every = 64;
+  o->precision = FFO_FP64;
+  o->restart_suff = 0.2;
+  o->restart_nec = 0.8;
+  o->restart_art = 0.36;
+  o->reflection = 1.0;
+  o->workgroups = 0;
+  o->verbose = 0;
+}
+
+const char* ffo_last_error(void) { return g_err.c_str(); }
+
+const char* ffo_version(void) { return "ffolio 0.1 (gfx950)"; }
+
+void ffo_release(void) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  for (auto& kv : g_ws) {
+    if (kv.second.base) hipFree(kv.second.base);
+    if (kv.second.host) hipHostFree(kv.second.host);
+    for (auto& e : kv.second.ev)
+      if (e) hipEventDestroy(e);
+  }
+  g_ws.clear();
+}
+
+ffo_status ffo_solve(int64_t n, int64_t k, int64_t m, int64_t T, const double* alpha, const double* F,
+                     const double* Omega, const double* delta, const double* s, const double* q, double d,
+                     const double* A, const double* L, const double* U, const double* w0, double GMV,
+                     double lambda1, double lambda2, double lambda3, const double* w_target,
+                     const ffo_options* opt_in, void* stream, double* w_out, double* y_out, ffo_info* info) {
+  g_err.clear();
+  ffo_options opt;
+  ffo_default_options(&opt);
+  if (opt_in) opt = *opt_in;
+  // ---- host-only validation (no device work before this point) ----
+  if (n < 1) return fail(FFO_EINVAL, "n must be >= 1");
+  if (k < 0 || k > 128) return fail(FFO_EINVAL, "k must lie in [0, 128]");
+  if (m < 0 || m > 4096) return fail(FFO_EINVAL, "m must lie in [0, 4096]");
+  if (!(T == 0 || T >= 2)) return fail(FFO_EINVAL, "T must be 0 (single-period) or >= 2");
+  if (T > 4096) return fail(FFO_EINVAL, "T must be <= 4096");
+  const int64_t P = T == 0 ? 1 : T - 1, Tp = T == 0 ? 1 : T;
+  if (n * Tp > (int64_t)1 << 30) return fail(FFO_EINVAL, "n * T too large");
+  if (!alpha || !delta || !s || !q || !w0 || !w_out) return fail(FFO_EINVAL, "null array pointer");
+  if (k > 0 && (!F || !Omega)) return fail(FFO_EINVAL, "F and Omega must be non-null when k > 0");
+  if (m > 0 && (!A || !L || !U)) return fail(FFO_EINVAL, "A, L and U must be non-null when m > 0");
+  if ((T == 0) != (w_target == nullptr)) return fail(FFO_EINVAL, "w_target must be NULL iff T == 0");
+  if (!(d > 1.0 && d <= 2.0)) return fail(FFO_EINVAL, "d must lie in (1, 2]");
+  if (!(GMV > 0.0) || !std::isfinite(GMV)) return fail(FFO_EINVAL, "GMV must be positive and finite");
+  if (!(lambda1 > 0.0) || !std::isfinite(lambda1)) return fail(FFO_EINVAL, "lambda1 must be positive and finite");
+  if (!(lambda2 >= 0.0) || !(lambda3 >= 0.0) || !std::isfinite(lambda2) || !std::isfinite(lambda3))
+    return fail(FFO_EINVAL, "lambda2 and lambda3 must be nonnegative and finite");
+  if (!(opt.tol_rel_kkt > 0.0)) return fail(FFO_EINVAL, "tol_rel_kkt must be positive");
+  if (opt.max_iter < 1) return fail(FFO_EINVAL, "max_iter must be >= 1");
+  if (opt.check_every < 1) return fail(FFO_EINVAL, "check_every must be >= 1");
+  if (!(opt.time_limit_s > 0.0)) return fail(FFO_EINVAL, "time_limit_s must be positive");
+  if (!(opt.reflection >= 0.0 && opt.reflection <= 1.0)) return fail(FFO_EINVAL, "reflection must lie in [0, 1]");
+  if (opt.precision != FFO_FP64) return fail(FFO_EINVAL, "only FFO_FP64 is available in ffo_solve");
+  if (opt.workgroups < 0 || opt.workgroups > 4096) return fail(FFO_EINVAL, "workgroups must lie in [0, 4096]");
+
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  hipDeviceProp_t prop;
+  HIPCHK(hipGetDeviceProperties(&prop, dev));
+  int wall_khz = 0;
+  if (hipDeviceGetAttribute(&wall_khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess || wall_khz <= 0)
+    wall_khz = 100000;
+
+  // ---- sizes and launch shape ----
+  const int nr = (int)(m + k);
+  const int ldk = (int)((n + 63) / 64 * 64);
+  ffo::DevProblem p{};
+  p.n = (int)n; p.k = (int)k; p.m = (int)m; p.P = (int)P; p.Tp = (int)Tp; p.nr = nr;
+  p.multi = T > 0 ? 1 : 0; p.ldk = ldk;
+  const int cus = std::max(1, prop.multiProcessorCount);
+  int nwg = opt.workgroups > 0 ? opt.workgroups : (int)std::min<int64_t>(cus, (n + 63) / 64);
+  nwg = std::max(1, std::min<int>(nwg, (int)n));
+  nwg = std::min(nwg, cus);  // one workgroup per compute unit keeps the cooperative grid resident
+  const int nw = (int)((n + nwg - 1) / nwg);
+  nwg = (int)((n + nw - 1) / nw);
+  ffo::DevControl c{};
+  c.tol = opt.tol_rel_kkt; c.time_limit_s = opt.time_limit_s;
+  c.r_suff = opt.restart_suff; c.r_nec = opt.restart_nec; c.r_art = opt.restart_art;
+  c.rho = opt.reflection; c.eta_safety = 0.95; c.max_iter = opt.max_iter;
+  c.check_every = opt.check_every; c.xmode = ffo::XM_ATOMIC; c.nwg = nwg; c.npow = 40;
+  c.verbose = opt.verbose; c.nw = nw; c.spin_limit = 1u << 26; c.wall_hz = (double)wall_khz * 1e3;
+  if (const char* e = std::getenv("FFO_XMODE")) c.xmode = std::atoi(e) ? ffo::XM_GATHER : ffo::XM_ATOMIC;
+  c.vmax = ffo::solve_vmax(p);
+  c.spec = P == 1 ? 1 : 0;
+  if (const char* e = std::getenv("FFO_SPEC")) c.spec = std::atoi(e) ? 1 : 0;
+  // LDS placement: constraint slice and per-asset state in LDS when they fit, in that
+  // order of preference (state first: it is touched in every phase).
+  const size_t lds_cap = (size_t)std::min<size_t>(prop.sharedMemPerBlock, 160 * 1024);
+  size_t lds = 0;
+  {
+    const int order[4][2] = {{1, 1}, {0, 1}, {1, 0}, {0, 0}};
+    bool placed = false;
+    for (const auto& o : order) {
+      c.lds_k = o[0];
+      c.lds_state = o[1];
+      lds = ffo::solve_lds_bytes(p, c);
+      if (lds <= lds_cap) { placed = true; break; }
+    }
+    if (!placed) return fail(FFO_EINVAL, "problem too large for the per-workgroup working set (reduce m + k or T)");
+  }
+  // ---- workspace layout ----
+  const size_t Pn = (size_t)P * n, Tpn = (size_t)Tp * n;
+  size_t off = 0;
+  auto carve = [&](size_t cnt, size_t elt) { const size_t o = off; off = align_up(off + cnt * elt); return o; };
+  const size_t oK = carve((size_t)std::max(nr, 1) * ldk, 8), odr = carve(std::max(nr, 1), 8), odc = carve(n, 8);
+  const size_t odrC = carve(Tpn, 8), oar = carve(n, 8), ocv = carve(n, 8), oca = carve(Tpn, 8), ocb = carve(Tpn, 8);
+  const size_t obF = carve(std::max<int64_t>(k, 1), 8), ocr = carve(1, 8), oC = carve(std::max<int64_t>(k * k, 1), 8);
+  size_t ost[7];
+  for (auto& o : ost) o = carve(Pn, 8);
+  size_t osc[4];
+  for (auto& o : osc) o = carve(Tpn, 8);
+  const size_t nxbuf = (size_t)std::max(2 * nwg, 3) * c.vmax;
+  const size_t oxb = carve(nxbuf, 8), oxm = carve((size_t)2 * nwg * P, 8), obar = carve(1, 8);
+  const size_t oinfo = carve(ffo::INFO_LEN, 8), ostat = carve(1, 4), oflag = carve(1, 4);
+  const size_t total = off;
+  const size_t host_bytes = align_up((size_t)std::max<int64_t>(k * k, 1) * 8) * 2 + 4096;
+
+  Workspace* ws = nullptr;
+  if (ffo_status st = get_workspace(dev, stream, total, host_bytes, &ws)) return st;
+  char* B = (char*)ws->base;
+  auto D = [&](size_t o) { return (double*)(B + o); };
+  hipStream_t hs = (hipStream_t)stream;
+  double* hOm = (double*)ws->host;
+  double* hC = hOm + align_up((size_t)std::max<int64_t>(k * k, 1) * 8) / 8;
+  int* hflag = (int*)(hC + align_up((size_t)std::max<int64_t>(k * k, 1) * 8) / 8);
+
+  HIPCHK(hipEventRecord(ws->ev[0], hs));
+  // ---- value validation on the device + Omega to the host (one synchronisation) ----
+  HIPCHK(hipMemsetAsync(B + oflag, 0, 4, hs));
+  hipLaunchKernelGGL(k_validate, dim3(64), dim3(256), 0, hs, n, (int64_t)Pn, (int64_t)Tpn, n * k, m, alpha, F,
+                     delta, s, q, L, U, w0, w_target, (int*)(B + oflag));
+  HIPCHK(hipGetLastError());
+  if (k > 0) HIPCHK(hipMemcpyAsync(hOm, Omega, (size_t)k * k * 8, hipMemcpyDeviceToHost, hs));
+  HIPCHK(hipMemcpyAsync(hflag, B + oflag, 4, hipMemcpyDeviceToHost, hs));
+  HIPCHK(hipStreamSynchronize(hs));
+  if (*hflag) {
+    std::string why;
+    if (*hflag & 1) why += " alpha not finite;";
+    if (*hflag & 2) why += " F not finite;";
+    if (*hflag & 4) why += " delta must be positive and finite;";
+    if (*hflag & 8) why += " w0/w_target not finite;";
+    if (*hflag & 16) why += " s and q must be nonnegative and finite;";
+    if (*hflag & 32) why += " need L <= U (no NaN, L < +inf, U > -inf);";
+    return fail(FFO_EINVAL, "invalid input values:" + why);
+  }
+  if (k > 0 && !factor_omega((int)k, hOm, hC)) return fail(FFO_EINVAL, "Omega must be symmetric positive semidefinite");
+  if (k > 0) HIPCHK(hipMemcpyAsync(D(oC), hC, (size_t)k * k * 8, hipMemcpyHostToDevice, hs));
+
+  // ---- setup kernels ----
+  const double g1 = lambda1 * GMV, g2 = lambda2, g3 = lambda3;
+  if (ffo::launch_setup(n, k, m, P, Tp, ldk, F, D(oC), A, delta, s, q, w_target, g1, g2, g3, D(oK), D(odr),
+                        D(odc), D(odrC), D(oar), D(ocv), D(oca), D(ocb), D(obF), D(ocr), stream))
+    return fail(FFO_EDEVICE, "setup kernel launch failed");
+  p.K = D(oK); p.dr = D(odr); p.dc = D(odc); p.drC = D(odrC); p.alpha = alpha; p.arisk = D(oar);
+  p.cvec = D(ocv); p.ca = D(oca); p.cb = D(ocb); p.w0 = w0; p.wT = w_target; p.L = L; p.U = U;
+  p.bF = D(obF); p.g1 = g1; p.d = d;
+  p.crisk = D(ocr);
+
+  ffo::DevState sv{};
+  sv.xs = D(ost[0]); sv.x0s = D(ost[1]); sv.Txs = D(ost[2]); sv.xL = D(ost[3]);
+  sv.bb = D(ost[4]); sv.aa = D(ost[5]); sv.vpow = D(ost[6]);
+  sv.ysC = D(osc[0]); sv.ys0C = D(osc[1]); sv.TysC = D(osc[2]); sv.ysCL = D(osc[3]);
+  sv.xbuf = D(oxb); sv.xmax = D(oxm); sv.bar = (unsigned long long*)(B + obar);
+  sv.info = D(oinfo); sv.status = (int32_t*)(B + ostat); sv.w_out = w_out; sv.y_out = y_out;
+  HIPCHK(hipMemsetAsync(B + oxb, 0, nxbuf * 8, hs));
+  HIPCHK(hipMemsetAsync(B + obar, 0, 8, hs));
+  HIPCHK(hipMemsetAsync(B + oinfo, 0, ffo::INFO_LEN * 8, hs));
+  HIPCHK(hipMemsetAsync(B + ostat, 0xff, 4, hs));
+  HIPCHK(hipEventRecord(ws->ev[1], hs));
+  if (int e = ffo::launch_solve(p, sv, c, stream, lds))
+    return fail(FFO_EDEVICE, std::string("cooperative launch of the solve kernel failed: ") +
+                                 hipGetErrorString((hipError_t)e));
+  HIPCHK(hipEventRecord(ws->ev[2], hs));
+  double hinfo[ffo::INFO_LEN];
+  int32_t hstat = -1;
+  HIPCHK(hipMemcpyAsync(hOm, B + oinfo, ffo::INFO_LEN * 8, hipMemcpyDeviceToHost, hs));
+  HIPCHK(hipMemcpyAsync(hflag, B + ostat, 4, hipMemcpyDeviceToHost, hs));
+  HIPCHK(hipStreamSynchronize(hs));
+  std::memcpy(hinfo, hOm, sizeof(hinfo));
+  hstat = *hflag;
+  float ms_setup = 0.f, ms_iter = 0.f;
+  hipEventElapsedTime(&ms_setup, ws->ev[0], ws->ev[1]);
+  hipEventElapsedTime(&ms_iter, ws->ev[1], ws->ev[2]);
+  ffo_status st;
+  switch (hstat) {
+    case ffo::DS_OK: st = FFO_OK; break;
+    case ffo::DS_NOT_CONVERGED: st = FFO_NOT_CONVERGED; g_err = "iteration limit reached"; break;
+    case ffo::DS_NUMERIC: st = FFO_NUMERIC; g_err = "NaN or Inf in an FP64 check"; break;
+    case ffo::DS_TIMEOUT: st = FFO_TIMEOUT; g_err = "time limit reached"; break;
+    default: st = FFO_EDEVICE; g_err = "solve kernel ended without a result (bounded wait expired)"; break;
+  }
+  if (info) {
+    info->status = st;
+    info->iters = (int64_t)hinfo[ffo::IX_ITERS];
+    info->restarts = (int64_t)hinfo[ffo::IX_RESTARTS];
+    info->rel_kkt = hinfo[ffo::IX_RELKKT];
+    info->rel_pri = hinfo[ffo::IX_RELPRI];
+    info->rel_dual = hinfo[ffo::IX_RELDUAL];
+    info->rel_gap = hinfo[ffo::IX_RELGAP];
+    info->fixed_point_res = hinfo[ffo::IX_FPR];
+    info->primal_obj = hinfo[ffo::IX_POBJ];
+    info->dual_obj = hinfo[ffo::IX_DOBJ];
+    info->omega = hinfo[ffo::IX_OMEGA];
+    info->ms_setup = ms_setup;
+    info->ms_iter = ms_iter;
+  }
+  if (opt.verbose)
+    std::fprintf(stderr,
+                 "[ffo] status %d iters %.0f restarts %.0f spec_miss %.0f ms_rounds %.0f exchanges %.0f checks %.0f "
+                 "normK %.4f nwg %d nw %d lds_k %d lds_state %d spec %d | t_power %.3f ms t_iter %.3f ms "
+                 "t_check %.3f ms t_wait(wg0) %.3f ms\n",
+                 (int)st, hinfo[ffo::IX_ITERS], hinfo[ffo::IX_RESTARTS], hinfo[ffo::IX_SPEC_MISS],
+                 hinfo[ffo::IX_MS_ROUNDS], hinfo[ffo::IX_EXCHANGES], hinfo[ffo::IX_CHECKS], hinfo[ffo::IX_NORMK], nwg,
+                 nw, c.lds_k, c.lds_state, c.spec, hinfo[ffo::IX_T_POWER] * 1e3, hinfo[ffo::IX_T_ITER] * 1e3,
+                 hinfo[ffo::IX_T_CHECK] * 1e3, hinfo[ffo::IX_T_WAIT] * 1e3);
+  return st;
+}
+
+// Extra diagnostics of the last solve on this thread's (device, stream): not part of the
+// stable interface; used by the benchmark to report exchanges and speculation misses.
+int ffo_debug_last_info(void* stream, double* out16) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 1;
+  std::lock_guard<std::mutex> lk(g_mu);
+  auto it = g_ws.find({dev, stream});
+  if (it == g_ws.end() || !it->second.host) return 1;
+  std::memcpy(out16, it->second.host, ffo::INFO_LEN * sizeof(double));
+  return 0;
+}
+
+}  // extern "C"

@@ -1,0 +1,88 @@
+// Internal structures shared by the host library and the solve kernels.
+// Not part of the public C interface (see include/ffolio.h).
+#pragma once
+#include <stdint.h>
+
+namespace ffo {
+
+// Exchange buffer modes of the persistent kernel.
+enum XMode : int32_t { XM_ATOMIC = 0, XM_GATHER = 1 };
+
+// Status codes written by the device (mirror ffo_status).
+enum DevStatus : int32_t {
+  DS_RUNNING = -1, DS_OK = 0, DS_NOT_CONVERGED = 4, DS_NUMERIC = 5, DS_TIMEOUT = 7,
+  DS_BARRIER = 100  // a bounded wait expired (device consistency failure)
+};
+
+// Problem in scaled form (every pointer is device memory).
+//   K~ = diag(dr) [A; G^T] diag(dc)   rows 0..m-1 exposure, m..m+k-1 factor (G = F C)
+//   trade rows (per asset) carry drC[t][i] * dc[i] * (+-1)
+struct DevProblem {
+  int32_t n, k, m, P, Tp, nr, multi, ldk;
+  const double* K;      // [nr][ldk] scaled constraint rows
+  const double* dr;     // [nr]
+  const double* dc;     // [n]
+  const double* drC;    // [Tp][n]
+  const double* alpha;  // [P][n]
+  const double* arisk;  // [n]  2 g1 delta^2
+  const double* cvec;   // [n]  risk centre (0 or w_T)
+  const double* ca;     // [Tp][n] g2 s
+  const double* cb;     // [Tp][n] g3 q
+  const double* w0;     // [n]
+  const double* wT;     // [n] (multi-period) or nullptr
+  const double* L;      // [m]
+  const double* U;      // [m]
+  const double* bF;     // [k] G^T c (unscaled)
+  const double* crisk;  // [1] g1 * sum_i delta_i^2 c_i^2
+  double g1, d;
+};
+
+// Per-(t,i) state arrays (device memory, each workgroup touches only its own assets).
+struct DevState {
+  double *xs, *x0s, *Txs, *xL;        // [P][n] iterate, Halpern anchor, T(z), last restart
+  double *ysC, *ys0C, *TysC, *ysCL;   // [Tp][n] trade duals, same roles
+  double *bb, *aa;                    // [P][n] prox inputs b and a of the current step
+  double *vpow;                       // [P][n] power-iteration vector, later scratch
+  double *xbuf;                       // exchange buffer (see kernel)
+  double *xmax;                       // [2][nwg][P] per-workgroup maxima (parity-buffered)
+  unsigned long long* bar;            // barrier counter (zeroed by the host)
+  double* info;                       // [INFO_LEN] result record written by workgroup 0
+  int32_t* status;                    // [1]
+  double* w_out;                      // [P][n] unscaled solution
+  double* y_out;                      // optional dual output
+};
+
+struct DevControl {
+  double tol, time_limit_s, r_suff, r_nec, r_art, rho, eta_safety;
+  int64_t max_iter;
+  int32_t check_every, xmode, nwg, vmax, npow, verbose;
+  int32_t lds_k;        // 1 if the constraint slice is staged in LDS
+  int32_t lds_state;    // 1 if the per-asset state lives in LDS (else device memory)
+  int32_t spec;         // 1: one speculative exchange per iteration; 0: two-phase
+  int32_t nw;           // assets per workgroup (max)
+  uint32_t spin_limit;
+  double wall_hz;       // rate of the device wall clock
+};
+
+enum InfoIdx {
+  IX_ITERS = 0, IX_RESTARTS, IX_RELKKT, IX_RELPRI, IX_RELDUAL, IX_RELGAP, IX_FPR, IX_POBJ,
+  IX_DOBJ, IX_OMEGA, IX_ETA, IX_NORMK, IX_SPEC_MISS, IX_EXCHANGES, IX_CHECKS, IX_T_WAIT,
+  IX_T_ITER, IX_T_CHECK, IX_T_POWER, IX_MS_ROUNDS, INFO_LEN = 24
+};
+
+// Launch the persistent solve kernel (defined in solve_kernel.hip).
+int launch_solve(const DevProblem& p, const DevState& s, const DevControl& c, void* stream,
+                 size_t lds_bytes);
+size_t solve_lds_bytes(const DevProblem& p, const DevControl& c);
+size_t solve_state_doubles(const DevProblem& p, int nw);
+int solve_vmax(const DevProblem& p);
+
+// Setup kernels (setup_kernels.hip).
+int launch_setup(int64_t n, int64_t k, int64_t m, int64_t P, int64_t Tp, int ldk,
+                 const double* F, const double* Cfac, const double* A, const double* delta,
+                 const double* s, const double* q, const double* wT, double g1, double g2,
+                 double g3, double* Kbuf, double* dr, double* dc, double* drC, double* arisk,
+                 double* cvec, double* ca, double* cb, double* bF, double* crisk_dev,
+                 void* stream);
+
+}  // namespace ffo

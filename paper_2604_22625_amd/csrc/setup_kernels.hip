@@ -1,0 +1,131 @@
+// Setup kernels: assemble the scaled constraint rows and the elementwise data of the
+// splitting (exposure rows A, factor rows G^T with G = F C, C C^T = Omega; trade rows).
+//
+// Scaling is diagonal (Pock & Chambolle 2011, alpha = 1): with row sums r_j and column
+// sums c_i of |K| over the stacked operator (exposure, factor and trade rows),
+// dr = 1/sqrt(r), dc = 1/sqrt(c) and K~ = diag(dr) K diag(dc).  Trade rows have unit
+// entries, so their row sums are 1 (single-period, first and last multi-period trade)
+// or 2, and every column gains 1 (single-period) or 2 (multi-period).
+#include <hip/hip_runtime.h>
+#include "internal.h"
+
+namespace ffo {
+
+namespace {
+
+constexpr int TB = 256;
+
+// K[j][i] for j < m from A, for j = m + l from (F C)[i][l]; also the column sums.
+__global__ __launch_bounds__(TB) void k_build(int n, int k, int m, int ldk, int tradecol,
+                                              const double* __restrict__ F, const double* __restrict__ C,
+                                              const double* __restrict__ A, double* __restrict__ K,
+                                              double* __restrict__ dc) {
+  extern __shared__ double sC[];  // k*k
+  for (int e = threadIdx.x; e < k * k; e += TB) sC[e] = C[e];
+  __syncthreads();
+  const int i = blockIdx.x * TB + threadIdx.x;
+  if (i >= n) return;
+  double cs = (double)tradecol;
+  for (int j = 0; j < m; ++j) {
+    const double a = A[(size_t)j * n + i];
+    K[(size_t)j * ldk + i] = a;
+    cs += fabs(a);
+  }
+  for (int l = 0; l < k; ++l) {
+    double g = 0.0;
+    for (int jj = 0; jj < k; ++jj) g = fma(F[(size_t)i * k + jj], sC[jj * k + l], g);
+    K[(size_t)(m + l) * ldk + i] = g;
+    cs += fabs(g);
+  }
+  dc[i] = 1.0 / sqrt(cs);
+}
+
+// One block per constraint row: row sum of |K| -> dr; factor rows also give bF = G^T c.
+// Block nr computes crisk = g1 sum delta^2 c^2.
+__global__ __launch_bounds__(TB) void k_rows(int n, int nr, int m, int ldk, const double* __restrict__ K,
+                                             const double* __restrict__ cvec, const double* __restrict__ delta,
+                                             double g1, double* __restrict__ dr, double* __restrict__ bF,
+                                             double* __restrict__ crisk) {
+  __shared__ double s1[TB], s2[TB];
+  const int j = blockIdx.x;
+  double a = 0.0, b = 0.0;
+  if (j < nr) {
+    for (int i = threadIdx.x; i < n; i += TB) {
+      const double v = K[(size_t)j * ldk + i];
+      a += fabs(v);
+      b = fma(v, cvec[i], b);
+    }
+  } else {
+    for (int i = threadIdx.x; i < n; i += TB) a = fma(delta[i] * delta[i], cvec[i] * cvec[i], a);
+  }
+  s1[threadIdx.x] = a;
+  s2[threadIdx.x] = b;
+  __syncthreads();
+  for (int w = TB / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w) {
+      s1[threadIdx.x] += s1[threadIdx.x + w];
+      s2[threadIdx.x] += s2[threadIdx.x + w];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    if (j < nr) {
+      dr[j] = s1[0] > 0.0 ? 1.0 / sqrt(s1[0]) : 1.0;
+      if (j >= m) bF[j - m] = s2[0];
+    } else {
+      crisk[0] = g1 * s1[0];
+    }
+  }
+}
+
+__global__ __launch_bounds__(TB) void k_scale(int n, int nr, int ldk, double* __restrict__ K,
+                                              const double* __restrict__ dr, const double* __restrict__ dc) {
+  const int i = blockIdx.x * TB + threadIdx.x;
+  const int j = blockIdx.y;
+  if (i >= ldk || j >= nr) return;
+  if (i < n) K[(size_t)j * ldk + i] *= dr[j] * dc[i];
+  else K[(size_t)j * ldk + i] = 0.0;
+}
+
+__global__ __launch_bounds__(TB) void k_elem(int n, int P, int Tp, int multi, const double* __restrict__ delta,
+                                             const double* __restrict__ s, const double* __restrict__ q,
+                                             const double* __restrict__ wT, double g1, double g2, double g3,
+                                             double* __restrict__ drC, double* __restrict__ arisk,
+                                             double* __restrict__ cvec, double* __restrict__ ca,
+                                             double* __restrict__ cb) {
+  const int i = blockIdx.x * TB + threadIdx.x;
+  if (i >= n) return;
+  arisk[i] = 2.0 * g1 * delta[i] * delta[i];
+  cvec[i] = multi ? wT[i] : 0.0;
+  for (int t = 0; t < Tp; ++t) {
+    const size_t e = (size_t)t * n + i;
+    ca[e] = g2 * s[e];
+    cb[e] = g3 * q[e];
+    // trade row t touches w_{t-1} and w_t: two unit entries except at the ends
+    drC[e] = (!multi || t == 0 || t == P) ? 1.0 : 0.70710678118654752440;
+  }
+}
+
+}  // namespace
+
+int launch_setup(int64_t n, int64_t k, int64_t m, int64_t P, int64_t Tp, int ldk, const double* F,
+                 const double* Cfac, const double* A, const double* delta, const double* s,
+                 const double* q, const double* wT, double g1, double g2, double g3, double* Kbuf,
+                 double* dr, double* dc, double* drC, double* arisk, double* cvec, double* ca,
+                 double* cb, double* bF, double* crisk_dev, void* stream) {
+  hipStream_t st = (hipStream_t)stream;
+  const int multi = Tp > 1 ? 1 : 0;
+  const int nb = (int)((n + TB - 1) / TB);
+  hipLaunchKernelGGL(k_elem, dim3(nb), dim3(TB), 0, st, (int)n, (int)P, (int)Tp, multi, delta, s, q, wT, g1,
+                     g2, g3, drC, arisk, cvec, ca, cb);
+  hipLaunchKernelGGL(k_build, dim3(nb), dim3(TB), (size_t)(k * k) * sizeof(double), st, (int)n, (int)k,
+                     (int)m, ldk, multi ? 2 : 1, F, Cfac, A, Kbuf, dc);
+  const int nr = (int)(m + k);
+  hipLaunchKernelGGL(k_rows, dim3(nr + 1), dim3(TB), 0, st, (int)n, nr, (int)m, ldk, Kbuf, cvec, delta, g1,
+                     dr, bF, crisk_dev);
+  if (nr > 0)
+    hipLaunchKernelGGL(k_scale, dim3((ldk + TB - 1) / TB, nr), dim3(TB), 0, st, (int)n, nr, ldk, Kbuf, dr, dc);
+  return hipGetLastError() == hipSuccess ? 0 : 1;
+}
+
+}  // namespace ffo

@@ -1,0 +1,92 @@
+"""C-ABI checks that need no GPU: the library loads, exports every declared entry point,
+and rejects invalid sizes, pointers and scalars with FFO_EINVAL before any device work."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_2604_22625_amd as ff
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    txt = open(os.path.join(ROOT, "include", "ffolio.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(ffo_[a-z_]+)\s*\(", txt)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = ff.lib()
+    names = _declared()
+    assert "ffo_solve" in names and "ffo_default_options" in names
+    for name in names:
+        assert hasattr(lib, name), name
+
+
+def test_default_options():
+    o = ff.default_options()
+    assert o.tol_rel_kkt == 1e-6 and o.check_every == 64 and o.time_limit_s == 360.0
+    assert (o.restart_suff, o.restart_nec, o.restart_art) == (0.2, 0.8, 0.36)
+    assert o.reflection == 1.0 and o.precision == 0
+
+
+def _call(**over):
+    """ffo_solve with fake (never dereferenced) pointers; invalid arguments must be
+    rejected by the host-side checks before any pointer is touched."""
+    fake = ctypes.c_void_p(0x1000)
+    args = dict(n=10, k=2, m=1, T=0, alpha=fake, F=fake, Omega=fake, delta=fake, s=fake, q=fake, d=1.5,
+                A=fake, L=fake, U=fake, w0=fake, GMV=1e9, l1=1e-9, l2=1.0, l3=1.0, wT=None, w_out=fake)
+    args.update(over)
+    info = ff._Info()
+    lib = ff.lib()
+    rc = lib.ffo_solve(args["n"], args["k"], args["m"], args["T"], args["alpha"], args["F"], args["Omega"],
+                       args["delta"], args["s"], args["q"], args["d"], args["A"], args["L"], args["U"],
+                       args["w0"], args["GMV"], args["l1"], args["l2"], args["l3"], args["wT"], None, None,
+                       args["w_out"], None, ctypes.byref(info))
+    return rc, lib.ffo_last_error().decode()
+
+
+@pytest.mark.parametrize("over,needle", [
+    (dict(n=0), "n must"),
+    (dict(k=-1), "k must"),
+    (dict(k=129), "k must"),
+    (dict(m=-2), "m must"),
+    (dict(T=1), "T must"),
+    (dict(T=3), "w_target"),
+    (dict(wT=ctypes.c_void_p(0x2000)), "w_target"),
+    (dict(alpha=None), "null"),
+    (dict(w_out=None), "null"),
+    (dict(F=None), "F and Omega"),
+    (dict(A=None), "A, L and U"),
+    (dict(d=1.0), "d must"),
+    (dict(d=2.5), "d must"),
+    (dict(d=float("nan")), "d must"),
+    (dict(GMV=0.0), "GMV"),
+    (dict(GMV=float("inf")), "GMV"),
+    (dict(l1=0.0), "lambda1"),
+    (dict(l2=-1.0), "lambda2"),
+    (dict(l3=float("nan")), "lambda2 and lambda3"),
+])
+def test_invalid_arguments_rejected_on_host(over, needle):
+    rc, msg = _call(**over)
+    assert rc == 1, (rc, msg)
+    assert needle in msg
+
+
+def test_invalid_options_rejected_on_host():
+    lib = ff.lib()
+    fake = ctypes.c_void_p(0x1000)
+    for field, val in (("tol_rel_kkt", 0.0), ("max_iter", 0), ("check_every", 0), ("reflection", 1.5),
+                       ("precision", 7), ("time_limit_s", -1.0)):
+        o = ff.default_options()
+        setattr(o, field, val)
+        info = ff._Info()
+        rc = lib.ffo_solve(10, 2, 1, 0, fake, fake, fake, fake, fake, fake, 1.5, fake, fake, fake, fake, 1e9,
+                           1e-9, 1.0, 1.0, None, ctypes.byref(o), None, fake, None, ctypes.byref(info))
+        assert rc == 1, field
+
+
+def test_version_string():
+    assert b"gfx950" in ff.lib().ffo_version()
