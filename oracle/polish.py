@@ -395,7 +395,7 @@ def certify_dual(pb: Problem, W, yA, yF, yC):
     return po, do, gap, bound
 
 
-def polish(pb: Problem, W, yA, yF, yC, eps=(1e-7, 1e-6, 1e-5, 1e-8, 1e-4, 1e-9)) -> PolishResult:
+def polish(pb: Problem, W, yA, yF, yC, eps=(1e-7, 1e-6, 1e-5, 1e-8, 1e-4, 1e-9, 1e-10, 1e-11)) -> PolishResult:
     if pb.g1 <= 0 or float(pb.delta2.min(initial=1.0)) <= 0:
         return PolishResult(False, None, None, None, None, np.inf, np.inf, 0,
                             "polish needs g1 > 0 and delta > 0")
