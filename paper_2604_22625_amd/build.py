@@ -34,6 +34,9 @@ def flags() -> list[str]:
 def build(verbose: bool = False) -> str:
     srcs = [os.path.join(CSRC, s) for s in SOURCES]
     tmp = LIB + ".tmp"
+    # a failed build must not leave an older library behind to be loaded by mistake
+    if os.path.exists(LIB):
+        os.remove(LIB)
     cmd = [hipcc()] + flags() + ["-o", tmp] + srcs
     if verbose:
         print(" ".join(cmd), flush=True)

@@ -293,7 +293,7 @@ ffo_status ffo_solve(int64_t n, int64_t k, int64_t m, int64_t T, const double* a
   size_t osc[4];
   for (auto& o : osc) o = carve(Tpn, 8);
   const size_t nxbuf = (size_t)std::max(2 * nwg, 3) * c.vmax;
-  const size_t oxb = carve(nxbuf, 8), oxm = carve((size_t)2 * nwg * P, 8), obar = carve(1, 8);
+  const size_t oxb = carve(nxbuf, 8), obar = carve(1, 8);
   const size_t oinfo = carve(ffo::INFO_LEN, 8), ostat = carve(1, 4), oflag = carve(1, 4);
   const size_t total = off;
   const size_t host_bytes = align_up((size_t)std::max<int64_t>(k * k, 1) * 8) * 2 + 4096;
@@ -343,7 +343,7 @@ ffo_status ffo_solve(int64_t n, int64_t k, int64_t m, int64_t T, const double* a
   sv.xs = D(ost[0]); sv.x0s = D(ost[1]); sv.Txs = D(ost[2]); sv.xL = D(ost[3]);
   sv.bb = D(ost[4]); sv.aa = D(ost[5]); sv.vpow = D(ost[6]);
   sv.ysC = D(osc[0]); sv.ys0C = D(osc[1]); sv.TysC = D(osc[2]); sv.ysCL = D(osc[3]);
-  sv.xbuf = D(oxb); sv.xmax = D(oxm); sv.bar = (unsigned long long*)(B + obar);
+  sv.xbuf = D(oxb); sv.bar = (unsigned long long*)(B + obar);
   sv.info = D(oinfo); sv.status = (int32_t*)(B + ostat); sv.w_out = w_out; sv.y_out = y_out;
   HIPCHK(hipMemsetAsync(B + oxb, 0, nxbuf * 8, hs));
   HIPCHK(hipMemsetAsync(B + obar, 0, 8, hs));
@@ -391,11 +391,15 @@ ffo_status ffo_solve(int64_t n, int64_t k, int64_t m, int64_t T, const double* a
     std::fprintf(stderr,
                  "[ffo] status %d iters %.0f restarts %.0f spec_miss %.0f ms_rounds %.0f exchanges %.0f checks %.0f "
                  "normK %.4f nwg %d nw %d lds_k %d lds_state %d spec %d | t_power %.3f ms t_iter %.3f ms "
-                 "t_check %.3f ms t_wait(wg0) %.3f ms\n",
+                 "t_check %.3f ms t_wait(wg0) %.3f ms | A %.3f B %.3f C %.3f D %.3f pre %.3f read %.3f ms "
+                 "| B1 %.3f B2 %.3f B3 %.3f ms\n",
                  (int)st, hinfo[ffo::IX_ITERS], hinfo[ffo::IX_RESTARTS], hinfo[ffo::IX_SPEC_MISS],
                  hinfo[ffo::IX_MS_ROUNDS], hinfo[ffo::IX_EXCHANGES], hinfo[ffo::IX_CHECKS], hinfo[ffo::IX_NORMK], nwg,
                  nw, c.lds_k, c.lds_state, c.spec, hinfo[ffo::IX_T_POWER] * 1e3, hinfo[ffo::IX_T_ITER] * 1e3,
-                 hinfo[ffo::IX_T_CHECK] * 1e3, hinfo[ffo::IX_T_WAIT] * 1e3);
+                 hinfo[ffo::IX_T_CHECK] * 1e3, hinfo[ffo::IX_T_WAIT] * 1e3, hinfo[ffo::IX_T_PHA] * 1e3,
+                 hinfo[ffo::IX_T_PHB] * 1e3, hinfo[ffo::IX_T_PHC] * 1e3, hinfo[ffo::IX_T_PHD] * 1e3,
+                 hinfo[ffo::IX_T_PRE] * 1e3, hinfo[ffo::IX_T_READ] * 1e3, hinfo[ffo::IX_T_B1] * 1e3,
+                 hinfo[ffo::IX_T_B2] * 1e3, hinfo[ffo::IX_T_B3] * 1e3);
   return st;
 }
 

