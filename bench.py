@@ -11,7 +11,10 @@ Algorithmic bytes per PDHG iteration follow the streaming model
     B_iter = 2 (m+k) n w + n (4P + 5T' + 3) w,   w = 8 bytes,
 i.e. the constraint rows read once for K^T y and once for K x, plus the per-asset
 vectors; achieved = iterations x B_iter / kernel time, measured per launch with HIP
-events on the solve stream.
+events recorded by the library on the solve stream around the kernel launch.
+traffic = hardware bytes per launch (rocprofv3 FETCH_SIZE and WRITE_SIZE, scaled by a
+known-size copy; stored in profiles/) / the same kernel time, in GB/s; null when the
+kernel sources differ from the ones the counters were taken on.
 """
 from __future__ import annotations
 
@@ -29,6 +32,35 @@ if ROOT not in sys.path:
 
 METRIC = "solves/s to 1e-6 rel KKT (n=5000; T=20); batched/FP32 vs plain; HBM % peak"
 HBM_PEAK_GBS = 8000.0
+COUNTERS = os.path.join(ROOT, "profiles", "k_solve_n5000_fp64.md")
+KERNEL_SOURCES = ["solve_kernel.hip", "setup_kernels.hip", "ffolio_host.hip", "internal.h"]
+
+
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2604_22625_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def counter_bytes_per_launch():
+    """Scaled FETCH_SIZE + WRITE_SIZE bytes per solve launch from the committed profile, or
+    None when the kernel sources have changed since the counters were taken."""
+    try:
+        kv = {}
+        with open(COUNTERS) as fh:
+            for line in fh:
+                if " = " in line:
+                    k, v = line.strip().split(" = ", 1)
+                    kv[k.strip()] = v.strip()
+        if kv.get("source_sha256") != kernel_source_hash():
+            return None
+        return 1024.0 * (float(kv["fetch_kib_per_dispatch"]) * float(kv["fetch_scale"])
+                         + float(kv["write_kib_per_dispatch"]) * float(kv["write_scale"]))
+    except (OSError, KeyError, ValueError):
+        return None
 
 
 def parse():
@@ -123,6 +155,8 @@ def main():
     sms = np.array([i.ms_setup for i in infos])
     bpi = algorithmic_bytes_per_iter(n, k, m, P, Tp)
     achieved = float((iters * bpi).sum() / (kms.sum() * 1e-3) / 1e9)
+    tb = counter_bytes_per_launch() if a.config == 1 else None
+    traffic = None if tb is None else float(tb / (kms.mean() * 1e-3) / 1e9)
     out = {
         "metric": METRIC,
         "value": value,
@@ -140,7 +174,7 @@ def main():
                                f"seeds {seeds[0]}-{seeds[-1]}, plain FP64, to rel KKT {a.tol:g}",
                    "n": n, "k": k, "m": m, "T": T, "instances_per_step": len(insts), "tol": a.tol},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None},
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic},
         "iters_mean": float(iters.mean()),
         "kernel_ms_mean": float(kms.mean()),
         "setup_ms_mean": float(sms.mean()),

@@ -71,7 +71,7 @@ typedef struct {
   double restart_art;      /* ... or the epoch is >= art * total iterations (0.36)    */
   double reflection;       /* rho of the reflected Halpern step, in [0, 1] (1.0)      */
   int32_t workgroups;      /* workgroups of the persistent solve kernel, 0 = auto     */
-  int32_t verbose;         /* nonzero: print per-check progress to stderr             */
+  int32_t verbose;         /* 1: one summary line per solve to stderr; 2: also per-check progress (device printf) */
 } ffo_options;
 
 typedef struct {

@@ -42,13 +42,17 @@
 namespace ffo {
 namespace {
 
-constexpr int TB = 256;
+#ifndef FFO_TB
+#define FFO_TB 256
+#endif
+constexpr int TB = FFO_TB;       // threads per workgroup (one workgroup per CU)
 constexpr int NWAVE = TB / 64;
 constexpr int MSC = 32;          // multisection candidates per round
 constexpr int MS_ROUNDS = 40;
 constexpr int NC = 8;            // bracket candidates per period
 constexpr int STW = 2 + 3 * NC;  // published statistics per period
-constexpr int RED_OUT = 256, RED_MAX = 320, RED_GMAX = 328, RED_LEN = 336;
+constexpr int RED_OUT = TB, RED_MAX = TB + 64, RED_LEN = TB + 64 + 16;
+static_assert(TB == 256 || TB == 512, "workgroup size");
 
 __device__ __forceinline__ double ldd(const double* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -85,6 +89,12 @@ __device__ __forceinline__ double max8(double x) {
   return fmax(x, dpp<DPP_HALF_MIRROR>(x));
 }
 __device__ __forceinline__ double max16(double x) { x = max8(x); return fmax(x, dpp<DPP_MIRROR>(x)); }
+template <int L>
+__device__ __forceinline__ double sum_lanes(double x) {
+  static_assert(L == 8 || L == 16, "lane group");
+  if constexpr (L == 8) return sum8(x);
+  else return sum16(x);
+}
 __device__ __forceinline__ double lane_of(double x, int l) {
   const unsigned long long u = (unsigned long long)__double_as_longlong(x);
   const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)u, l);
@@ -456,12 +466,13 @@ __device__ void period_stats(Ctx& c, const ldbl* absb, const ldbl* inva, int nw,
 //   0 = multisection needed, root in the central pair (breakpoints inside it),
 //   3 = multisection needed, root outside the central pair.
 // For 0 and 3, lo/hi receive a bracket with S(lo) >= 1 >= S(hi).
+// Called by a whole wave (uniform arguments; the candidate tests use one lane each).
 __device__ int bracket_decide(const ldbl* st, double cen, double hw, double& lo, double& hi, double& mu) {
   const double S0 = st[0], maxb = st[1];
   if (S0 <= 1.0) { mu = 0.0; return (cen + hw <= 0.0) ? 1 : 2; }
-  int qs = -1;
-  for (int q = 0; q < NC; ++q)
-    if (st[2 + 3 * q] >= 1.0) qs = q;
+  const int lane = threadIdx.x & 63;
+  const unsigned long long ge = __ballot(lane < NC && st[2 + 3 * (lane < NC ? lane : 0)] >= 1.0);
+  const int qs = ge ? 63 - __clzll((long long)ge) : -1;   // S is non-increasing: {q : S(c_q) >= 1} = [0, qs]
   double a, b;
   if (qs < 0) { a = 0.0; b = cand(cen, hw, 0); }
   else if (qs == NC - 1) { a = cand(cen, hw, NC - 1); b = maxb; }
@@ -477,11 +488,11 @@ __device__ int bracket_decide(const ldbl* st, double cen, double hw, double& lo,
 }
 
 // Multisection for the periods with need[t] != 0 (caller synchronised; S(lo) >= 1 >= S(hi)):
-// MSC candidates per round, eight lanes per candidate.  absb/inva as in period_stats.
+// MSC candidates per round, TB / MSC lanes per candidate.  absb/inva as in period_stats.
 __device__ bool multisect(Ctx& c, int P, const ldbl* absb, const ldbl* inva, int nw, lint* need, ldbl* lo,
                           ldbl* hi, ldbl* mu, lint* rounds_out) {
-  static_assert(MSC * 8 == TB, "one candidate per eight lanes");
-  const int q = c.tid >> 3, sub = c.tid & 7;
+  constexpr int MSL = TB / MSC;   // lanes per candidate
+  const int q = c.tid / MSL, sub = c.tid % MSL;
   for (int round = 0; round < MS_ROUNDS; ++round) {
     int any = 0;
     for (int t = 0; t < P; ++t) any |= need[t];
@@ -491,11 +502,11 @@ __device__ bool multisect(Ctx& c, int P, const ldbl* absb, const ldbl* inva, int
       if (!need[t]) continue;
       const double cq = lo[t] + (hi[t] - lo[t]) * (double)q / (double)(MSC - 1);
       double S = 0.0, A0 = 0.0, N = 0.0;
-      for (int li = sub; li < c.nwa; li += 8) {
+      for (int li = sub; li < c.nwa; li += MSL) {
         const double ab = absb[t * nw + li];
         if (ab > cq) { const double ia = inva[t * nw + li]; S = fma(ab - cq, ia, S); A0 += ia; N += 1.0; }
       }
-      S = sum8(S); A0 = sum8(A0); N = sum8(N);
+      S = sum_lanes<MSL>(S); A0 = sum_lanes<MSL>(A0); N = sum_lanes<MSL>(N);
       if (sub == 0) {
         const int e = t * MSC + q;
         put(c, 3 * e + 0, S);
@@ -504,25 +515,25 @@ __device__ bool multisect(Ctx& c, int P, const ldbl* absb, const ldbl* inva, int
       }
     }
     if (!xsync(c, 3 * P * MSC)) return false;
-    if (c.tid == 0) {
-      for (int t = 0; t < P; ++t) {
+    {
+      const int lane = c.tid & 63, wave = c.tid >> 6;
+      for (int t = wave; t < P; t += NWAVE) {   // one wave per period
         if (!need[t]) continue;
         const ldbl* T0 = c.tot + 3 * t * MSC;
-        int qs = 0;
-        for (int k = 0; k < MSC; ++k)
-          if (T0[3 * k] >= 1.0) qs = k;
-        const double cq = lo[t] + (hi[t] - lo[t]) * (double)qs / (double)(MSC - 1);
-        if (qs == MSC - 1) { mu[t] = hi[t]; need[t] = 0; continue; }
-        const double cn = lo[t] + (hi[t] - lo[t]) * (double)(qs + 1) / (double)(MSC - 1);
-        const bool linear = T0[3 * qs + 2] == T0[3 * (qs + 1) + 2];
+        const unsigned long long ge = __ballot(lane < MSC && T0[3 * (lane < MSC ? lane : 0)] >= 1.0);
+        const int qs = ge ? 63 - __clzll((long long)ge) : 0;
+        const double l = lo[t], h = hi[t];
+        const double cq = l + (h - l) * (double)qs / (double)(MSC - 1);
+        const double cn = l + (h - l) * (double)(qs + 1) / (double)(MSC - 1);
+        const bool top = qs == MSC - 1;
+        const bool linear = !top && T0[3 * qs + 2] == T0[3 * (qs + 1) + 2];
         const bool tiny = (cn - cq) <= 4.0 * 2.220446049250313e-16 * fabs(cn);
-        if (linear || tiny || round == MS_ROUNDS - 1) {
-          const double m_ = T0[3 * qs + 1] > 0.0 ? cq + (T0[3 * qs] - 1.0) / T0[3 * qs + 1] : cq;
-          mu[t] = fmin(fmax(m_, cq), cn);
-          need[t] = 0;
-        } else {
-          lo[t] = cq;
-          hi[t] = cn;
+        const double m_ = T0[3 * qs + 1] > 0.0 ? cq + (T0[3 * qs] - 1.0) / T0[3 * qs + 1] : cq;
+        __builtin_amdgcn_wave_barrier();
+        if (lane == 0) {
+          if (top) { mu[t] = h; need[t] = 0; }
+          else if (linear || tiny || round == MS_ROUNDS - 1) { mu[t] = fmin(fmax(m_, cq), cn); need[t] = 0; }
+          else { lo[t] = cq; hi[t] = cn; }
         }
       }
     }
@@ -551,7 +562,7 @@ __device__ __forceinline__ void next_bracket(double mu, double mprev, double w, 
 // ---------------------------------------------------------------------------------
 struct Scal {   // uniform scalars kept in LDS (identical in every workgroup)
   double omega, eta, r0, rprev;
-  long long it, kk, restarts, spec_miss, checks;
+  long long it, kk, restarts, spec_miss, checks, miss_in, miss_out;
   int done, status, restart, ms_rounds;
 };
 
@@ -578,7 +589,7 @@ __global__ __launch_bounds__(TB) void k_solve(DevProblem p, DevState s, DevContr
   c.t_wait = 0;
   c.t_pre = 0;
   c.t_read = 0;
-  long long t_phA = 0, t_phB = 0, t_phC = 0, t_phD = 0, t_b1 = 0, t_b2 = 0, t_b3 = 0;
+  long long t_phA = 0, t_phB = 0, t_phC = 0, t_phD = 0, t_b1 = 0, t_b2 = 0, t_b3 = 0, t_b1s = 0;
 
   // LDS layout (doubles); must match solve_lds_bytes
   ldbl* ptr = lds;
@@ -633,7 +644,9 @@ __global__ __launch_bounds__(TB) void k_solve(DevProblem p, DevState s, DevContr
   }
   __attribute__((address_space(3))) Scal* sc = (__attribute__((address_space(3))) Scal*)ptr;
   ptr += (sizeof(Scal) + 7) / 8;
-  lint* iflag = (lint*)ptr; ptr += 1;
+  lint* iflag = (lint*)ptr; ptr += 2;       // [0] exchange status, [1] fallback, [2] miss, [3] spare
+  lint* fbflag = iflag + 1;
+  lint* msflag = iflag + 2;
   lint* need = (lint*)ptr;
   c.tot = tot;
   c.red = red;
@@ -666,8 +679,11 @@ __global__ __launch_bounds__(TB) void k_solve(DevProblem p, DevState s, DevContr
   for (int e = c.tid; e < P * nr; e += TB) { ys[e] = 0.0; ys0[e] = 0.0; Tys[e] = 0.0; ysL[e] = 0.0; Kx[e] = 0.0; }
   if (c.tid == 0) {
     sc->omega = 1.0; sc->it = 0; sc->kk = 0; sc->restarts = 0; sc->spec_miss = 0; sc->checks = 0;
+    sc->miss_in = 0; sc->miss_out = 0;
     sc->r0 = -1.0; sc->rprev = INFINITY; sc->done = 0; sc->status = DS_RUNNING; sc->restart = 0;
     sc->ms_rounds = 0;
+    fbflag[0] = 0;
+    msflag[0] = 0;
     for (int t = 0; t < P; ++t) {
       cen[t] = 0.0; hw[t] = 0.0; lo[t] = 0.0; hi[t] = 0.0; mu[t] = 0.0; mpv[t] = 0.0; wid[t] = 1e-3;
       dcen[t] = 0.0; dhw[t] = 0.0; dlo[t] = 0.0; dhi[t] = 0.0; dmu[t] = 0.0; dmp[t] = 0.0; dwd[t] = 1e-3;
@@ -768,6 +784,7 @@ __global__ __launch_bounds__(TB) void k_solve(DevProblem p, DevState s, DevContr
       const int oP1 = STW * P, oP2 = oP1 + P * nr;
       const int VE1 = ctl.spec ? oP2 + P * nr : STW * P;
       period_stats(c, xv3, xv4, nw, cen, hw, 0);
+      t_b1s += wall_clock64() - tb0;
       if (ctl.spec) {
         // affine pieces at hi: P1 = K~ (2 xhat_s(hi) - xs), P2 = K~ d xhat_s / d mu
         for (int e = c.tid; e < P * c.nwa; e += TB) {
@@ -790,30 +807,40 @@ __global__ __launch_bounds__(TB) void k_solve(DevProblem p, DevState s, DevContr
       c.mx_hi = STW * P;
       if (!xsync(c, VE1)) goto barrier_fail;
       const long long tb2 = wall_clock64();
-      if (c.tid == 0) {
-        int anyfb = 0, anymiss = 0;
-        for (int t = 0; t < P; ++t) {
+      {
+        const int lane = c.tid & 63, wave = c.tid >> 6;
+        for (int t = wave; t < P; t += NWAVE) {   // one wave per period
           double l = 0.0, h = 0.0, m_ = 0.0;
           const int r = bracket_decide(tot + STW * t, cen[t], hw[t], l, h, m_);
-          wid[t] = adapt_width(r, wid[t]);
-          mpv[t] = mu[t];
-          if (r == 1) {
-            mu[t] = m_;
-            need[t] = 0;
-          } else if (r == 2 || r == 4) {
-            mu[t] = m_;
-            need[t] = 0;
-            anyfb = 1;
-          } else {
-            lo[t] = l; hi[t] = h;
-            need[t] = 1;
-            anyfb = 1;
-            anymiss = 1;
+          if (lane == 0) {
+            wid[t] = adapt_width(r, wid[t]);
+            mpv[t] = mu[t];
+            if (r == 1) {
+              mu[t] = m_;
+              need[t] = 0;
+            } else if (r == 2 || r == 4) {
+              mu[t] = m_;
+              need[t] = 0;
+              __hip_atomic_fetch_or(fbflag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            } else {
+              lo[t] = l; hi[t] = h;
+              need[t] = 1;
+              __hip_atomic_fetch_or(fbflag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+              __hip_atomic_fetch_or(msflag, r == 0 ? 1 : 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            }
           }
         }
+      }
+      __syncthreads();
+      if (c.tid == 0) {
+        const int anyfb = *fbflag, anymiss = *msflag;
         // speculative mode recomputes K~ xbar after any miss; two-phase always does
         *iflag = ctl.spec ? anyfb : 1;
         if (anymiss || (ctl.spec && anyfb)) sc->spec_miss++;
+        if (anymiss & 1) sc->miss_in++;
+        if (anymiss & 2) sc->miss_out++;
+        *fbflag = 0;
+        *msflag = 0;
       }
       __syncthreads();
       const long long tb3 = wall_clock64();
@@ -842,8 +869,7 @@ __global__ __launch_bounds__(TB) void k_solve(DevProblem p, DevState s, DevContr
         for (int e = c.tid; e < P * nr; e += TB) Kx[e] = tot[e];
         __syncthreads();
       }
-      if (c.tid == 0)
-        for (int t = 0; t < P; ++t) next_bracket(mu[t], mpv[t], wid[t], cen[t], hw[t]);
+      for (int t = c.tid; t < P; t += TB) next_bracket(mu[t], mpv[t], wid[t], cen[t], hw[t]);
       __syncthreads();
       t_b3 += wall_clock64() - tb3;
     }
@@ -997,22 +1023,27 @@ __global__ __launch_bounds__(TB) void k_solve(DevProblem p, DevState s, DevContr
         pres2 += ex * ex;
       }
       __syncthreads();
-      if (c.tid == 0) {
-        int anyd = 0;
-        for (int t = 0; t < P; ++t) {
+      {
+        const int lane = c.tid & 63, wave = c.tid >> 6;
+        for (int t = wave; t < P; t += NWAVE) {   // one wave per period
           double l = 0.0, h = 0.0, m_ = 0.0;
           const int r = bracket_decide(tot + oD + STW * t, dcen[t], dhw[t], l, h, m_);
-          dwd[t] = adapt_width(r, dwd[t]);
-          dmp[t] = dmu[t];
-          if (r == 1 || r == 2 || r == 4) { dmu[t] = m_; need[t] = 0; }
-          else { dlo[t] = l; dhi[t] = h; need[t] = 1; anyd = 1; }
+          if (lane == 0) {
+            dwd[t] = adapt_width(r, dwd[t]);
+            dmp[t] = dmu[t];
+            if (r == 1 || r == 2 || r == 4) { dmu[t] = m_; need[t] = 0; }
+            else {
+              dlo[t] = l; dhi[t] = h; need[t] = 1;
+              __hip_atomic_fetch_or(fbflag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            }
+          }
         }
-        *iflag = anyd;
       }
       __syncthreads();
+      if (c.tid == 0) { *iflag = *fbflag; *fbflag = 0; }
+      __syncthreads();
       if (*iflag && !multisect(c, P, xv3, xv4, nw, need, dlo, dhi, dmu, &sc->ms_rounds)) goto barrier_fail;
-      if (c.tid == 0)
-        for (int t = 0; t < P; ++t) next_bracket(dmu[t], dmp[t], dwd[t], dcen[t], dhw[t]);
+      for (int t = c.tid; t < P; t += TB) next_bracket(dmu[t], dmp[t], dwd[t], dcen[t], dhw[t]);
       __syncthreads();
       // C2: inner value sum (a'/2 w^2 - b' w), w = sign(b') max(|b'| - mu', 0) / a'
       {
@@ -1041,7 +1072,7 @@ __global__ __launch_bounds__(TB) void k_solve(DevProblem p, DevState s, DevContr
         if (c.wg == 0) {
           s.info[IX_RELKKT] = relkkt; s.info[IX_RELPRI] = rel_pri; s.info[IX_RELDUAL] = rel_dual;
           s.info[IX_RELGAP] = rel_gap; s.info[IX_FPR] = fpr; s.info[IX_POBJ] = phi; s.info[IX_DOBJ] = psi;
-          if (ctl.verbose)
+          if (ctl.verbose >= 2)
             printf("[ffo] it %lld kkt %.3e pri %.3e gap %.3e fpr %.3e omega %.3e restarts %lld miss %lld\n",
                    sc->it + 1, relkkt, rel_pri, rel_gap, fpr, omega, sc->restarts, sc->spec_miss);
         }
@@ -1158,6 +1189,9 @@ __global__ __launch_bounds__(TB) void k_solve(DevProblem p, DevState s, DevContr
     s.info[IX_T_B1] = (double)t_b1 / ctl.wall_hz;
     s.info[IX_T_B2] = (double)t_b2 / ctl.wall_hz;
     s.info[IX_T_B3] = (double)t_b3 / ctl.wall_hz;
+    s.info[IX_T_B1S] = (double)t_b1s / ctl.wall_hz;
+    s.info[IX_MISS_IN] = (double)sc->miss_in;
+    s.info[IX_MISS_OUT] = (double)sc->miss_out;
     s.status[0] = sc->status;
   }
   return;
@@ -1189,7 +1223,7 @@ size_t solve_lds_bytes(const DevProblem& p, const DevControl& c) {
   if (c.lds_k) d += nr * (nw | 1);
   d += 5 * P * nr + 4 * P * nw + (size_t)c.vmax + RED_LEN + 14 * P;
   if (c.lds_state) d += solve_state_doubles(p, c.nw);
-  d += (sizeof(Scal) + 7) / 8 + 1 + (P + 1) / 2 + 1;
+  d += (sizeof(Scal) + 7) / 8 + 2 + (P + 1) / 2 + 1;
   return d * sizeof(double);
 }
 
