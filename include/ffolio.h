@@ -55,9 +55,13 @@ typedef enum {
 
 typedef enum {
   FFO_FP64 = 0,            /* every vector and matrix in float64                      */
-  FFO_FP32 = 1,            /* iterates and matrix in float32; checks, restarts and the
-                              KKT residual accumulated in float64                     */
-  FFO_FP32_BF16K = 2       /* as FP32, with the constraint matrix in bfloat16        */
+  FFO_FP32 = 1,            /* per-asset iterates stored in float32 as offsets from their
+                              float64 restart anchors; the scaled constraint slice and
+                              per-asset data copies in float32; every reduction, the
+                              budget multipliers, checks, restarts and the KKT residual
+                              in float64 against the float64 inputs                  */
+  FFO_FP32_BF16K = 2       /* batched solver only: as FP32, constraint matrix in bfloat16
+                              (ffo_solve returns FFO_EINVAL)                          */
 } ffo_precision;
 
 typedef struct {

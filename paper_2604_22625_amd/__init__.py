@@ -118,10 +118,13 @@ def _ptr(t):
     return ctypes.c_void_p(0 if t is None else t.data_ptr())
 
 
+PRECISION = {"fp64": 0, "fp32": 1, "fp32_bf16k": 2}
+
+
 def solve(alpha, F, Omega, delta, s, q, d, A, L, U, w0, GMV, lambda1, lambda2, lambda3,
           w_target=None, *, tol: float = 1e-6, max_iter: int = 1_000_000, time_limit_s: float = 360.0,
           check_every: int = 64, restart=(0.2, 0.8, 0.36), reflection: float = 1.0,
-          workgroups: int = 0, verbose: bool = False, return_dual: bool = False,
+          workgroups: int = 0, verbose: int = 0, return_dual: bool = False, precision="fp64",
           raise_on_failure: bool = True, device=None, stream=None, out=None):
     """Solve one single-period (w_target is None) or multi-period instance on the GPU.
 
@@ -129,7 +132,8 @@ def solve(alpha, F, Omega, delta, s, q, d, A, L, U, w0, GMV, lambda1, lambda2, l
     delta [n], s and q [T'][n] (T' = 1 or T), A [m][n], L and U [m], w0 and w_target [n].
     Returns (W [P][n] float64 CUDA tensor, Info) or (W, Info, (yA, yF, yC)) with
     ``return_dual``.  Non-OK statuses raise FolioError unless ``raise_on_failure`` is
-    False (NOT_CONVERGED/TIMEOUT/NUMERIC still fill W).
+    False (NOT_CONVERGED/TIMEOUT/NUMERIC still fill W).  ``precision`` is "fp64" or
+    "fp32" (float32 iterates and matrix copies, float64 reductions and checks).
     """
     torch = _torch()
     if not torch.cuda.is_available():
@@ -165,7 +169,8 @@ def solve(alpha, F, Omega, delta, s, q, d, A, L, U, w0, GMV, lambda1, lambda2, l
     o.restart_suff, o.restart_nec, o.restart_art = (float(v) for v in restart)
     o.reflection = float(reflection)
     o.workgroups = int(workgroups)
-    o.verbose = int(bool(verbose))
+    o.verbose = int(verbose)
+    o.precision = PRECISION[precision] if isinstance(precision, str) else int(precision)
     info = _Info()
     st = torch.cuda.current_stream(dev) if stream is None else stream
     with torch.cuda.device(dev):

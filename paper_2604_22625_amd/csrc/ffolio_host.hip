@@ -233,7 +233,8 @@ ffo_status ffo_solve(int64_t n, int64_t k, int64_t m, int64_t T, const double* a
   if (opt.check_every < 1) return fail(FFO_EINVAL, "check_every must be >= 1");
   if (!(opt.time_limit_s > 0.0)) return fail(FFO_EINVAL, "time_limit_s must be positive");
   if (!(opt.reflection >= 0.0 && opt.reflection <= 1.0)) return fail(FFO_EINVAL, "reflection must lie in [0, 1]");
-  if (opt.precision != FFO_FP64) return fail(FFO_EINVAL, "only FFO_FP64 is available in ffo_solve");
+  if (opt.precision != FFO_FP64 && opt.precision != FFO_FP32)
+    return fail(FFO_EINVAL, "ffo_solve takes FFO_FP64 or FFO_FP32");
   if (opt.workgroups < 0 || opt.workgroups > 4096) return fail(FFO_EINVAL, "workgroups must lie in [0, 4096]");
 
   int dev = 0;
@@ -262,6 +263,7 @@ ffo_status ffo_solve(int64_t n, int64_t k, int64_t m, int64_t T, const double* a
   c.rho = opt.reflection; c.eta_safety = 0.95; c.max_iter = opt.max_iter;
   c.check_every = opt.check_every; c.xmode = ffo::XM_ATOMIC; c.nwg = nwg; c.npow = 40;
   c.verbose = opt.verbose; c.nw = nw; c.spin_limit = 1u << 26; c.wall_hz = (double)wall_khz * 1e3;
+  c.prec = opt.precision == FFO_FP32 ? ffo::PREC_FP32 : ffo::PREC_FP64;
   if (const char* e = std::getenv("FFO_XMODE")) c.xmode = std::atoi(e) ? ffo::XM_GATHER : ffo::XM_ATOMIC;
   c.vmax = ffo::solve_vmax(p);
   c.spec = P == 1 ? 1 : 0;
@@ -288,9 +290,9 @@ ffo_status ffo_solve(int64_t n, int64_t k, int64_t m, int64_t T, const double* a
   const size_t oK = carve((size_t)std::max(nr, 1) * ldk, 8), odr = carve(std::max(nr, 1), 8), odc = carve(n, 8);
   const size_t odrC = carve(Tpn, 8), oar = carve(n, 8), ocv = carve(n, 8), oca = carve(Tpn, 8), ocb = carve(Tpn, 8);
   const size_t obF = carve(std::max<int64_t>(k, 1), 8), ocr = carve(1, 8), oC = carve(std::max<int64_t>(k * k, 1), 8);
-  size_t ost[7];
+  size_t ost[6];
   for (auto& o : ost) o = carve(Pn, 8);
-  size_t osc[4];
+  size_t osc[3];
   for (auto& o : osc) o = carve(Tpn, 8);
   const size_t nxbuf = (size_t)std::max(2 * nwg, 3) * c.vmax;
   const size_t oxb = carve(nxbuf, 8), obar = carve(1, 8);
@@ -340,9 +342,9 @@ ffo_status ffo_solve(int64_t n, int64_t k, int64_t m, int64_t T, const double* a
   p.crisk = D(ocr);
 
   ffo::DevState sv{};
-  sv.xs = D(ost[0]); sv.x0s = D(ost[1]); sv.Txs = D(ost[2]); sv.xL = D(ost[3]);
-  sv.bb = D(ost[4]); sv.aa = D(ost[5]); sv.vpow = D(ost[6]);
-  sv.ysC = D(osc[0]); sv.ys0C = D(osc[1]); sv.TysC = D(osc[2]); sv.ysCL = D(osc[3]);
+  sv.xs = D(ost[0]); sv.x0s = D(ost[1]); sv.Txs = D(ost[2]);
+  sv.bb = D(ost[3]); sv.aa = D(ost[4]); sv.vpow = D(ost[5]);
+  sv.ysC = D(osc[0]); sv.ys0C = D(osc[1]); sv.TysC = D(osc[2]);
   sv.xbuf = D(oxb); sv.bar = (unsigned long long*)(B + obar);
   sv.info = D(oinfo); sv.status = (int32_t*)(B + ostat); sv.w_out = w_out; sv.y_out = y_out;
   HIPCHK(hipMemsetAsync(B + oxb, 0, nxbuf * 8, hs));

@@ -39,8 +39,10 @@ struct DevProblem {
 
 // Per-(t,i) state arrays (device memory, each workgroup touches only its own assets).
 struct DevState {
-  double *xs, *x0s, *Txs, *xL;        // [P][n] iterate, Halpern anchor, T(z), last restart
-  double *ysC, *ys0C, *TysC, *ysCL;   // [Tp][n] trade duals, same roles
+  double *xs, *x0s, *Txs;             // [P][n] iterate, Halpern anchor (= last restart point), T(z)
+  double *ysC, *ys0C, *TysC;          // [Tp][n] trade duals, same roles
+                                      // (xs, Txs, ysC, TysC hold float offsets from the anchor
+                                      //  in the FP32 form)
   double *bb, *aa;                    // [P][n] prox inputs b and a of the current step
   double *vpow;                       // [P][n] power-iteration vector, later scratch
   double *xbuf;                       // exchange buffer (see kernel)
@@ -59,9 +61,12 @@ struct DevControl {
   int32_t lds_state;    // 1 if the per-asset state lives in LDS (else device memory)
   int32_t spec;         // 1: one speculative exchange per iteration; 0: two-phase
   int32_t nw;           // assets per workgroup (max)
+  int32_t prec;         // PREC_FP64 or PREC_FP32: stored type of the iterates and LDS copies
   uint32_t spin_limit;
   double wall_hz;       // rate of the device wall clock
 };
+
+enum Prec { PREC_FP64 = 0, PREC_FP32 = 1 };
 
 enum InfoIdx {
   IX_ITERS = 0, IX_RESTARTS, IX_RELKKT, IX_RELPRI, IX_RELDUAL, IX_RELGAP, IX_FPR, IX_POBJ,
@@ -74,7 +79,6 @@ enum InfoIdx {
 int launch_solve(const DevProblem& p, const DevState& s, const DevControl& c, void* stream,
                  size_t lds_bytes);
 size_t solve_lds_bytes(const DevProblem& p, const DevControl& c);
-size_t solve_state_doubles(const DevProblem& p, int nw);
 int solve_vmax(const DevProblem& p);
 
 // Setup kernels (setup_kernels.hip).

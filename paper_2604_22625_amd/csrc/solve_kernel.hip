@@ -115,12 +115,14 @@ __device__ __forceinline__ double wave_max(double x) {
 // instead of generic (flat) memory instructions.
 typedef __attribute__((address_space(3))) double ldbl;
 typedef __attribute__((address_space(3))) int lint;
+template <class R>
+using lds_t = __attribute__((address_space(3))) R;
 
 // Per-(t, li) array view: element (t, li) at b[t * ld + off + li]; SL selects LDS
-// (true) or device memory (false) at compile time.
-template <bool SL>
+// (true) or device memory (false) at compile time, R the stored type.
+template <bool SL, class R = double>
 struct Arr {
-  using P = typename std::conditional<SL, ldbl*, double*>::type;
+  using P = typename std::conditional<SL, lds_t<R>*, R*>::type;
   P b;
   int ld, off;
   __device__ __forceinline__ auto& operator()(int t, int li) const { return b[(size_t)t * ld + off + li]; }
@@ -253,21 +255,46 @@ __device__ double wg_max(const Ctx& c, double x) {
 // ---------------------------------------------------------------------------------
 // Per-workgroup problem and state views
 // ---------------------------------------------------------------------------------
-template <bool KL, bool SL>
+// A per-asset iterate: the value itself (R = double) or a float offset from the FP64
+// restart anchor z0 (R = float).  Offsets keep the rounding of each stored update
+// proportional to the distance moved since the last restart, not to the size of the
+// iterate (rounding errors that do not shrink would accumulate through the Halpern
+// anchoring).
+template <bool SL, class R>
+struct Iter {
+  static constexpr bool OFF = !std::is_same<R, double>::value;
+  Arr<SL, double> z0;
+  Arr<SL, R> d;
+  __device__ __forceinline__ double operator()(int t, int li) const {
+    if constexpr (OFF) return z0(t, li) + (double)d(t, li);
+    else return d(t, li);
+  }
+  __device__ __forceinline__ void set(int t, int li, double v) const {
+    if constexpr (OFF) d(t, li) = (R)(v - z0(t, li));
+    else d(t, li) = v;
+  }
+};
+
+// R: stored type of the per-asset iterates and of the LDS copies (double in the FP64
+// form, float in the FP32 form); every expression evaluates in double.
+template <bool KL, bool SL, class R = double>
 struct S {
+  using RC = typename std::conditional<SL, R, double>::type;   // constants: LDS copies or FP64 inputs
   const DevProblem* p;
-  const ldbl* Kl;       // LDS slice [nr][ldl] (KL) ...
+  const lds_t<R>* Kl;   // LDS slice [nr][ldl] (KL) ...
   const double* Kg;     // ... or the scaled rows in device memory
   int nw, ldl, i0;
-  // state
-  Arr<SL> xs, x0s, Txs, xL, bb, aa, xb;     // [P]
-  Arr<SL> ysC, ys0C, TysC, ysCL;            // [Tp]
+  // state: anchors and per-iteration scratch in FP64, iterates through Iter views
+  Arr<SL, double> x0s, bb, aa, xb;          // [P] anchor, prox input b, 1/a, xbar
+  Iter<SL, R> xs, Txs;                      // [P]
+  Arr<SL, double> ys0C;                     // [Tp]
+  Iter<SL, R> ysC, TysC;                    // [Tp]
   // constants
-  Arr<SL> alpha;                            // [P]
-  Arr<SL> ca, cb, drC;                      // [Tp]
-  Arr<SL> dc, arisk, cvec, w0, wT;          // [1]
+  Arr<SL, RC> alpha;                        // [P]
+  Arr<SL, RC> ca, cb, drC;                  // [Tp]
+  Arr<SL, RC> dc, arisk, cvec, w0, wT;      // [1]
   __device__ __forceinline__ double Kat(int j, int li) const {
-    if constexpr (KL) return Kl[j * ldl + li];
+    if constexpr (KL) return (double)Kl[j * ldl + li];
     else return Kg[(size_t)j * p->ldk + i0 + li];
   }
 };
@@ -568,7 +595,11 @@ struct Scal {   // uniform scalars kept in LDS (identical in every workgroup)
 
 extern __shared__ double g_lds[];
 
-template <bool KL, bool SL>
+// Doubles of LDS taken by `count` elements of type R (every array starts 8-byte aligned).
+template <class R>
+__host__ __device__ constexpr size_t lds_doubles(size_t count) { return (count * sizeof(R) + 7) / 8; }
+
+template <bool KL, bool SL, class R>
 __global__ __launch_bounds__(TB) void k_solve(DevProblem p, DevState s, DevControl ctl) {
   ldbl* lds = (ldbl*)g_lds;
   const int P = p.P, nr = p.nr, n = p.n, Tp = p.Tp, nw = ctl.nw;
@@ -593,13 +624,12 @@ __global__ __launch_bounds__(TB) void k_solve(DevProblem p, DevState s, DevContr
 
   // LDS layout (doubles); must match solve_lds_bytes
   ldbl* ptr = lds;
-  ldbl* Kl = nullptr;
+  lds_t<R>* Kl = nullptr;
   const int ldl = nw | 1;   // odd row stride: row-parallel reads spread over the LDS banks
-  if (KL) { Kl = ptr; ptr += (size_t)nr * ldl; }
+  if (KL) { Kl = (lds_t<R>*)ptr; ptr += lds_doubles<R>((size_t)nr * ldl); }
   ldbl* ys = ptr;   ptr += P * nr;
-  ldbl* ys0 = ptr;  ptr += P * nr;
+  ldbl* ys0 = ptr;  ptr += P * nr;          // anchor (= last restart point)
   ldbl* Tys = ptr;  ptr += P * nr;
-  ldbl* ysL = ptr;  ptr += P * nr;
   ldbl* Kx = ptr;   ptr += P * nr;          // K~ xbar rows (exchanged)
   ldbl* xv1 = ptr;  ptr += P * nw;          // staging
   ldbl* xv2 = ptr;  ptr += P * nw;          // staging
@@ -621,27 +651,55 @@ __global__ __launch_bounds__(TB) void k_solve(DevProblem p, DevState s, DevContr
   ldbl* dmu = ptr;  ptr += P;
   ldbl* dmp = ptr;  ptr += P;
   ldbl* dwd = ptr;  ptr += P;
-  S<KL, SL> V;
+  using SV = S<KL, SL, R>;
+  SV V;
   V.p = &p;
   V.nw = nw;
   V.ldl = ldl;
   V.i0 = c.i0;
   if constexpr (SL) {
-    auto take = [&](int rows) { Arr<SL> r{ptr, nw, 0}; ptr += (size_t)rows * nw; return r; };
-    V.xs = take(P); V.x0s = take(P); V.Txs = take(P); V.xL = take(P); V.bb = take(P); V.aa = take(P);
-    V.xb = take(P);
-    V.ysC = take(Tp); V.ys0C = take(Tp); V.TysC = take(Tp); V.ysCL = take(Tp);
-    V.alpha = take(P); V.ca = take(Tp); V.cb = take(Tp); V.drC = take(Tp);
-    V.dc = take(1); V.arisk = take(1); V.cvec = take(1); V.w0 = take(1); V.wT = take(1);
+    auto take = [&](auto tag, int rows) {
+      using E = decltype(tag);
+      Arr<SL, E> r{(lds_t<E>*)ptr, nw, 0};
+      ptr += lds_doubles<E>((size_t)rows * nw);
+      return r;
+    };
+    const double fd = 0.0;
+    const R fr = 0;
+    const typename SV::RC fc = 0;
+    V.x0s = take(fd, P); V.bb = take(fd, P); V.aa = take(fd, P); V.xb = take(fd, P);
+    V.xs = {V.x0s, take(fr, P)}; V.Txs = {V.x0s, take(fr, P)};
+    V.ys0C = take(fd, Tp);
+    V.ysC = {V.ys0C, take(fr, Tp)}; V.TysC = {V.ys0C, take(fr, Tp)};
+    V.alpha = take(fc, P); V.ca = take(fc, Tp); V.cb = take(fc, Tp); V.drC = take(fc, Tp);
+    V.dc = take(fc, 1); V.arisk = take(fc, 1); V.cvec = take(fc, 1); V.w0 = take(fc, 1); V.wT = take(fc, 1);
   } else {
-    auto g = [&](const double* b) { return Arr<SL>{(double*)b, n, c.i0}; };
-    V.xs = g(s.xs); V.x0s = g(s.x0s); V.Txs = g(s.Txs); V.xL = g(s.xL); V.bb = g(s.bb); V.aa = g(s.aa);
-    V.xb = g(s.vpow);
-    V.ysC = g(s.ysC); V.ys0C = g(s.ys0C); V.TysC = g(s.TysC); V.ysCL = g(s.ysCL);
+    // state buffers hold [P or Tp][n] elements (iterates of type R); constants are the
+    // FP64 inputs
+    auto gs = [&](const double* b) { return Arr<SL, R>{(R*)b, n, c.i0}; };
+    auto g = [&](const double* b) { return Arr<SL, double>{(double*)b, n, c.i0}; };
+    V.x0s = g(s.x0s); V.bb = g(s.bb); V.aa = g(s.aa); V.xb = g(s.vpow);
+    V.xs = {V.x0s, gs(s.xs)}; V.Txs = {V.x0s, gs(s.Txs)};
+    V.ys0C = g(s.ys0C);
+    V.ysC = {V.ys0C, gs(s.ysC)}; V.TysC = {V.ys0C, gs(s.TysC)};
     V.alpha = g(p.alpha); V.ca = g(p.ca); V.cb = g(p.cb); V.drC = g(p.drC);
     V.dc = g(p.dc); V.arisk = g(p.arisk); V.cvec = g(p.cvec); V.w0 = g(p.w0);
     V.wT = g(p.wT ? p.wT : p.w0);
   }
+  // FP64 view of the problem (device-memory rows and constants) for the checks of the
+  // FP32 form; the FP64 form checks with the same view it iterates with.
+  S<false, false, double> G;
+  {
+    auto g = [&](const double* b) { return Arr<false, double>{(double*)b, n, c.i0}; };
+    G.p = &p; G.Kl = nullptr; G.Kg = p.K; G.nw = nw; G.ldl = ldl; G.i0 = c.i0;
+    G.alpha = g(p.alpha); G.ca = g(p.ca); G.cb = g(p.cb); G.drC = g(p.drC);
+    G.dc = g(p.dc); G.arisk = g(p.arisk); G.cvec = g(p.cvec); G.w0 = g(p.w0);
+    G.wT = g(p.wT ? p.wT : p.w0);
+  }
+  auto& Vc = [&]() -> auto& {
+    if constexpr (std::is_same<R, double>::value) return V;
+    else return G;
+  }();
   __attribute__((address_space(3))) Scal* sc = (__attribute__((address_space(3))) Scal*)ptr;
   ptr += (sizeof(Scal) + 7) / 8;
   lint* iflag = (lint*)ptr; ptr += 2;       // [0] exchange status, [1] fallback, [2] miss, [3] spare
@@ -676,7 +734,7 @@ __global__ __launch_bounds__(TB) void k_solve(DevProblem p, DevState s, DevContr
       V.w0(0, li) = p.w0[i]; V.wT(0, li) = p.wT ? p.wT[i] : 0.0;
     }
   }
-  for (int e = c.tid; e < P * nr; e += TB) { ys[e] = 0.0; ys0[e] = 0.0; Tys[e] = 0.0; ysL[e] = 0.0; Kx[e] = 0.0; }
+  for (int e = c.tid; e < P * nr; e += TB) { ys[e] = 0.0; ys0[e] = 0.0; Tys[e] = 0.0; Kx[e] = 0.0; }
   if (c.tid == 0) {
     sc->omega = 1.0; sc->it = 0; sc->kk = 0; sc->restarts = 0; sc->spec_miss = 0; sc->checks = 0;
     sc->miss_in = 0; sc->miss_out = 0;
@@ -695,12 +753,12 @@ __global__ __launch_bounds__(TB) void k_solve(DevProblem p, DevState s, DevContr
   for (int e = c.tid; e < P * c.nwa; e += TB) {
     const int t = e / c.nwa, li = e % c.nwa, i = c.i0 + li;
     const double x = V.w0(0, li) / V.dc(0, li);
-    V.xs(t, li) = x; V.x0s(t, li) = x; V.xL(t, li) = x; V.Txs(t, li) = x;
+    V.x0s(t, li) = x; V.xs.set(t, li, x); V.Txs.set(t, li, x);
     V.xb(t, li) = 1.0 + 0.25 * (double)((i * 7919 + t * 104729) % 1000) / 1000.0;   // power vector
   }
   for (int e = c.tid; e < Tp * c.nwa; e += TB) {
     const int t = e / c.nwa, li = e % c.nwa;
-    V.ysC(t, li) = 0.0; V.ys0C(t, li) = 0.0; V.TysC(t, li) = 0.0; V.ysCL(t, li) = 0.0;
+    V.ys0C(t, li) = 0.0; V.ysC.set(t, li, 0.0); V.TysC.set(t, li, 0.0);
   }
   __syncthreads();
   const long long t_start = wall_clock64();
@@ -765,8 +823,8 @@ __global__ __launch_bounds__(TB) void k_solve(DevProblem p, DevState s, DevContr
     kty_all(c, V, ys, P, nr, nw, xv1);
     for (int e = c.tid; e < P * c.nwa; e += TB) {
       const int t = e / c.nwa, li = e % c.nwa;
-      const double R = xv1[t * nw + li] + kty_trade(V, V.ysC, t, li);
-      const double v = V.xs(t, li) - tau * R;
+      const double Ry = xv1[t * nw + li] + kty_trade(V, V.ysC, t, li);
+      const double v = V.xs(t, li) - tau * Ry;
       const double dci = V.dc(0, li);
       const double a = 1.0 / (tau * dci * dci) + V.arisk(0, li);
       const double b = v / (tau * dci) + V.alpha(t, li) + V.arisk(0, li) * V.cvec(0, li);
@@ -881,8 +939,8 @@ __global__ __launch_bounds__(TB) void k_solve(DevProblem p, DevState s, DevContr
       const int t = e / c.nwa, li = e % c.nwa;
       const double b = V.bb(t, li), ab = fabs(b);
       const double xh = ab > mu[t] ? sgn(b) * (ab - mu[t]) * V.aa(t, li) / V.dc(0, li) : 0.0;
-      V.Txs(t, li) = xh;
       V.xb(t, li) = 2.0 * xh - V.xs(t, li);
+      V.Txs.set(t, li, xh);
     }
     __syncthreads();
     for (int e = c.tid; e < Tp * c.nwa; e += TB) {
@@ -893,7 +951,7 @@ __global__ __launch_bounds__(TB) void k_solve(DevProblem p, DevState s, DevContr
       const double bc = trade_offset(V, t, li);
       const double z = vs / (sigma * drc) - bc;
       const double pr = prox_cost(z, 1.0 / (sigma * drc * drc), V.ca(t, li), V.cb(t, li), p.d);
-      V.TysC(t, li) = vs - sigma * drc * bc - sigma * drc * pr;
+      V.TysC.set(t, li, vs - sigma * drc * bc - sigma * drc * pr);
     }
     for (int e = c.tid; e < P * nr; e += TB) {
       const int j = e % nr;
@@ -919,26 +977,26 @@ __global__ __launch_bounds__(TB) void k_solve(DevProblem p, DevState s, DevContr
       double v[12] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
       for (int e = c.tid; e < P * c.nwa; e += TB) {
         const int t = e / c.nwa, li = e % c.nwa;
-        const double tx = V.Txs(t, li), dx = V.xs(t, li) - tx, dl = tx - V.xL(t, li);
+        const double tx = V.Txs(t, li), dx = V.xs(t, li) - tx, dl = tx - V.x0s(t, li);
         v[0] = fma(omega * dx, dx, v[0]);
         v[1] = fma(dl, dl, v[1]);
-        const double w = V.dc(0, li) * tx, wc = w - V.cvec(0, li);
-        v[3] += -V.alpha(t, li) * w + 0.5 * V.arisk(0, li) * wc * wc;
+        const double w = Vc.dc(0, li) * tx, wc = w - Vc.cvec(0, li);
+        v[3] += -Vc.alpha(t, li) * w + 0.5 * Vc.arisk(0, li) * wc * wc;
         if (!isfinite(tx)) v[9] += 1.0;
         xv1[t * nw + li] = tx;
       }
       for (int e = c.tid; e < Tp * c.nwa; e += TB) {
         const int t = e / c.nwa, li = e % c.nwa;
-        const double ty = V.TysC(t, li), dy = V.ysC(t, li) - ty, dl = ty - V.ysCL(t, li);
+        const double ty = V.TysC(t, li), dy = V.ysC(t, li) - ty, dl = ty - V.ys0C(t, li);
         v[0] = fma(dy / omega, dy, v[0]);
         v[2] = fma(dl, dl, v[2]);
-        const double au = fabs(trade_of(V, V.Txs, t, li));
-        const double ca = V.ca(t, li), cb = V.cb(t, li);
+        const double au = fabs(trade_of(Vc, V.Txs, t, li));
+        const double ca = Vc.ca(t, li), cb = Vc.cb(t, li);
         v[4] += ca * au + cb * pow(au, p.d);
-        const double yc = V.drC(t, li) * ty;   // unscaled trade dual
+        const double yc = Vc.drC(t, li) * ty;   // unscaled trade dual
         v[5] += conj_cost(yc, ca, cb, p.d);
-        if (t == 0) v[6] += yc * V.w0(0, li);
-        if (p.multi && t == P) v[6] -= yc * V.wT(0, li);
+        if (t == 0) v[6] += yc * Vc.w0(0, li);
+        if (p.multi && t == P) v[6] -= yc * Vc.wT(0, li);
         v[7] = fma(yc, yc, v[7]);
         if (cb <= 0.0 && fabs(yc) > ca) { const double ex = fabs(yc) - ca; v[10] = fma(ex, ex, v[10]); }
         if (!isfinite(ty)) v[9] += 1.0;
@@ -946,7 +1004,7 @@ __global__ __launch_bounds__(TB) void k_solve(DevProblem p, DevState s, DevContr
       if (c.wg == 0) {   // replicated row duals enter the sums once
         for (int e = c.tid; e < P * nr; e += TB) {
           const int j = e % nr;
-          const double dy = ys[e] - Tys[e], dl = Tys[e] - ysL[e];
+          const double dy = ys[e] - Tys[e], dl = Tys[e] - ys0[e];
           v[0] = fma(dy / omega, dy, v[0]);
           v[2] = fma(dl, dl, v[2]);
           const double yu = p.dr[j] * Tys[e];
@@ -967,23 +1025,22 @@ __global__ __launch_bounds__(TB) void k_solve(DevProblem p, DevState s, DevContr
         const int lane = c.tid & 63, wave = c.tid >> 6;
         for (int t = wave; t < P; t += NWAVE) {   // L1 norms of T(x), one wave per period
           double b = 0.0;
-          for (int li = lane; li < c.nwa; li += 64) b += fabs(V.dc(0, li) * xv1[t * nw + li]);
+          for (int li = lane; li < c.nwa; li += 64) b += fabs(Vc.dc(0, li) * xv1[t * nw + li]);
           b = wave_sum(b);
           if (lane == 0) put(c, oB + t, b);
         }
       }
-      rows_prod<1>(c, V, xv1, xv1, nw, P, nr, [&](int e, const double* a) { put(c, oR + e, a[0]); });
+      rows_prod<1>(c, Vc, xv1, xv1, nw, P, nr, [&](int e, const double* a) { put(c, oR + e, a[0]); });
       // dual inner problem: b' = alpha + arisk c - R' (signed, in bb), 1/a' in aa,
       // R' = unscaled K^T Y at T(y).
-      kty_all(c, V, Tys, P, nr, nw, xv2);
-      for (int e = c.tid; e < P * c.nwa; e += TB) {
+      kty_all(c, Vc, Tys, P, nr, nw, xv2);
+      for (int e = c.tid; e < P * c.nwa; e += TB) {   // xv2: signed b', xv3: |b'|, xv4: 1/a'
         const int t = e / c.nwa, li = e % c.nwa;
-        const double R = (xv2[t * nw + li] + kty_trade(V, V.TysC, t, li)) / V.dc(0, li);
-        const double b = V.alpha(t, li) + V.arisk(0, li) * V.cvec(0, li) - R;
-        V.bb(t, li) = b;
-        V.aa(t, li) = 1.0 / V.arisk(0, li);
+        const double Ry = (xv2[t * nw + li] + kty_trade(Vc, V.TysC, t, li)) / Vc.dc(0, li);
+        const double b = Vc.alpha(t, li) + Vc.arisk(0, li) * Vc.cvec(0, li) - Ry;
+        xv2[t * nw + li] = b;
         xv3[t * nw + li] = fabs(b);
-        xv4[t * nw + li] = 1.0 / V.arisk(0, li);
+        xv4[t * nw + li] = 1.0 / Vc.arisk(0, li);
       }
       __syncthreads();
       period_stats(c, xv3, xv4, nw, dcen, dhw, oD);
@@ -1050,7 +1107,7 @@ __global__ __launch_bounds__(TB) void k_solve(DevProblem p, DevState s, DevContr
         double iv[1] = {0.0};
         for (int e = c.tid; e < P * c.nwa; e += TB) {
           const int t = e / c.nwa, li = e % c.nwa;
-          const double b = V.bb(t, li), ab = fabs(b), ia = V.aa(t, li);
+          const double b = xv2[t * nw + li], ab = fabs(b), ia = xv4[t * nw + li];
           const double w = ab > dmu[t] ? sgn(b) * (ab - dmu[t]) * ia : 0.0;
           iv[0] += 0.5 * w * w / ia - b * w;
         }
@@ -1105,7 +1162,7 @@ __global__ __launch_bounds__(TB) void k_solve(DevProblem p, DevState s, DevContr
         const bool bad = sc->status == DS_NUMERIC;
         for (int e = c.tid; e < P * c.nwa; e += TB) {
           const int t = e / c.nwa, li = e % c.nwa;
-          s.w_out[(size_t)t * n + c.i0 + li] = V.dc(0, li) * (bad ? V.xL(t, li) : V.Txs(t, li));
+          s.w_out[(size_t)t * n + c.i0 + li] = Vc.dc(0, li) * (bad ? V.x0s(t, li) : V.Txs(t, li));
         }
         if (s.y_out) {
           double* yA = s.y_out;
@@ -1114,12 +1171,12 @@ __global__ __launch_bounds__(TB) void k_solve(DevProblem p, DevState s, DevContr
           if (c.wg == 0)
             for (int e = c.tid; e < P * nr; e += TB) {
               const int t = e / nr, j = e % nr;
-              const double yu = p.dr[j] * (bad ? ysL[e] : Tys[e]);
+              const double yu = p.dr[j] * (bad ? ys0[e] : Tys[e]);
               if (j < p.m) yA[(size_t)t * p.m + j] = yu; else yF[(size_t)t * p.k + (j - p.m)] = yu;
             }
           for (int e = c.tid; e < Tp * c.nwa; e += TB) {
             const int t = e / c.nwa, li = e % c.nwa;
-            yC[(size_t)t * n + c.i0 + li] = V.drC(t, li) * (bad ? V.ysCL(t, li) : V.TysC(t, li));
+            yC[(size_t)t * n + c.i0 + li] = Vc.drC(t, li) * (bad ? V.ys0C(t, li) : V.TysC(t, li));
           }
         }
         if (c.tid == 0) sc->it++;
@@ -1129,14 +1186,14 @@ __global__ __launch_bounds__(TB) void k_solve(DevProblem p, DevState s, DevContr
         for (int e = c.tid; e < P * c.nwa; e += TB) {
           const int t = e / c.nwa, li = e % c.nwa;
           const double x = V.Txs(t, li);
-          V.xs(t, li) = x; V.x0s(t, li) = x; V.xL(t, li) = x;
+          V.x0s(t, li) = x; V.xs.set(t, li, x); V.Txs.set(t, li, x);
         }
         for (int e = c.tid; e < Tp * c.nwa; e += TB) {
           const int t = e / c.nwa, li = e % c.nwa;
           const double y = V.TysC(t, li);
-          V.ysC(t, li) = y; V.ys0C(t, li) = y; V.ysCL(t, li) = y;
+          V.ys0C(t, li) = y; V.ysC.set(t, li, y); V.TysC.set(t, li, y);
         }
-        for (int e = c.tid; e < P * nr; e += TB) { const double y = Tys[e]; ys[e] = y; ys0[e] = y; ysL[e] = y; }
+        for (int e = c.tid; e < P * nr; e += TB) { const double y = Tys[e]; ys[e] = y; ys0[e] = y; }
         __syncthreads();
         if (c.tid == 0) { sc->kk = 0; sc->it++; }
         __syncthreads();
@@ -1151,11 +1208,11 @@ __global__ __launch_bounds__(TB) void k_solve(DevProblem p, DevState s, DevContr
       const double a1 = (kk + 1.0) / (kk + 2.0), a0 = 1.0 / (kk + 2.0), rho = ctl.rho;
       for (int e = c.tid; e < P * c.nwa; e += TB) {
         const int t = e / c.nwa, li = e % c.nwa;
-        V.xs(t, li) = a1 * ((1.0 + rho) * V.Txs(t, li) - rho * V.xs(t, li)) + a0 * V.x0s(t, li);
+        V.xs.set(t, li, a1 * ((1.0 + rho) * V.Txs(t, li) - rho * V.xs(t, li)) + a0 * V.x0s(t, li));
       }
       for (int e = c.tid; e < Tp * c.nwa; e += TB) {
         const int t = e / c.nwa, li = e % c.nwa;
-        V.ysC(t, li) = a1 * ((1.0 + rho) * V.TysC(t, li) - rho * V.ysC(t, li)) + a0 * V.ys0C(t, li);
+        V.ysC.set(t, li, a1 * ((1.0 + rho) * V.TysC(t, li) - rho * V.ysC(t, li)) + a0 * V.ys0C(t, li));
       }
       for (int e = c.tid; e < P * nr; e += TB) ys[e] = a1 * ((1.0 + rho) * Tys[e] - rho * ys[e]) + a0 * ys0[e];
       __syncthreads();
@@ -1212,25 +1269,34 @@ int solve_vmax(const DevProblem& p) {
   return (v + 63) / 64 * 64;
 }
 
-size_t solve_state_doubles(const DevProblem& p, int nw) {
-  const size_t P = p.P, Tp = p.Tp;
-  return (8 * P + 7 * Tp + 5) * (size_t)nw;
+// LDS doubles of the per-asset state (the arrays the kernel takes when it holds the
+// state in LDS, in the same order and rounding).
+template <class R>
+static size_t state_lds_doubles(size_t P, size_t Tp, size_t nw) {
+  return 4 * P * nw + 2 * lds_doubles<R>(P * nw) + Tp * nw + 2 * lds_doubles<R>(Tp * nw) +
+         lds_doubles<R>(P * nw) + 3 * lds_doubles<R>(Tp * nw) + 5 * lds_doubles<R>(nw);
 }
 
 size_t solve_lds_bytes(const DevProblem& p, const DevControl& c) {
-  const size_t P = p.P, nr = p.nr, nw = c.nw;
+  const size_t P = p.P, Tp = p.Tp, nr = p.nr, nw = c.nw;
+  const bool f32 = c.prec == PREC_FP32;
   size_t d = 0;
-  if (c.lds_k) d += nr * (nw | 1);
-  d += 5 * P * nr + 4 * P * nw + (size_t)c.vmax + RED_LEN + 14 * P;
-  if (c.lds_state) d += solve_state_doubles(p, c.nw);
+  if (c.lds_k) d += f32 ? lds_doubles<float>(nr * (nw | 1)) : lds_doubles<double>(nr * (nw | 1));
+  d += 4 * P * nr + 4 * P * nw + (size_t)c.vmax + RED_LEN + 14 * P;
+  if (c.lds_state) d += f32 ? state_lds_doubles<float>(P, Tp, nw) : state_lds_doubles<double>(P, Tp, nw);
   d += (sizeof(Scal) + 7) / 8 + 2 + (P + 1) / 2 + 1;
   return d * sizeof(double);
 }
 
 int launch_solve(const DevProblem& p, const DevState& s, const DevControl& c, void* stream, size_t lds) {
   void* args[] = {(void*)&p, (void*)&s, (void*)&c};
-  const void* fn = c.lds_k ? (c.lds_state ? (const void*)k_solve<true, true> : (const void*)k_solve<true, false>)
-                           : (c.lds_state ? (const void*)k_solve<false, true> : (const void*)k_solve<false, false>);
+  const void* fn;
+  if (c.prec == PREC_FP32)
+    fn = c.lds_k ? (c.lds_state ? (const void*)k_solve<true, true, float> : (const void*)k_solve<true, false, float>)
+                 : (c.lds_state ? (const void*)k_solve<false, true, float> : (const void*)k_solve<false, false, float>);
+  else
+    fn = c.lds_k ? (c.lds_state ? (const void*)k_solve<true, true, double> : (const void*)k_solve<true, false, double>)
+                 : (c.lds_state ? (const void*)k_solve<false, true, double> : (const void*)k_solve<false, false, double>);
   hipError_t e = hipLaunchCooperativeKernel(fn, dim3(c.nwg), dim3(TB), args, (unsigned int)lds, (hipStream_t)stream);
   return e == hipSuccess ? 0 : (int)e;
 }
