@@ -134,6 +134,31 @@ ffo_status ffo_solve(int64_t n, int64_t k, int64_t m, int64_t T,
                      const double* w_target, const ffo_options* opt, void* stream,
                      double* w_out, double* y_out, ffo_info* info);
 
+/*
+ * Batched form: B independent single-period instances (paper eq. 1-3) that share one
+ * asset universe of n_max assets; instance b uses assets [0, n_b[b]).  Shared (device):
+ *   F [n_max][k], Omega [k][k], delta [n_max], A [m][n_max]
+ * Packed per instance (device), instance b at [offs[b], offs[b+1]):
+ *   alpha, s, q, w0   [N], N = offs[B]          L, U   [B][m]
+ * Host: n_b [B] (1 <= n_b <= n_max), offs [B+1] (offs[0] = 0, running sum of n_b),
+ * infos [B] (one record per instance).  d, GMV, lambda1..3 as in ffo_solve (shared).
+ * Output (device): w_out [N], packed like alpha.
+ * Every instance runs the same restarted Halpern PDHG as ffo_solve, to its own relative
+ * KKT tolerance, on a team of workgroups sized to its asset count; all teams of a launch
+ * are resident at once and never wait for each other (batches larger than the resident
+ * grid run in several launches, largest instances first).  opt->precision: FFO_FP64 or
+ * FFO_FP32; opt->workgroups is ignored; statuses as in ffo_solve.
+ * Returns FFO_OK if every instance converged, else the most severe instance status
+ * (FFO_EDEVICE > FFO_NUMERIC > FFO_TIMEOUT > FFO_NOT_CONVERGED); infos[b].status holds
+ * each instance's own status.  FFO_EINVAL is returned before any device work.
+ */
+ffo_status ffo_solve_batched(int64_t B, const int64_t* n_b, int64_t n_max, int64_t k, int64_t m,
+                             const double* F, const double* Omega, const double* delta, const double* A,
+                             const int64_t* offs, const double* alpha, const double* s, const double* q,
+                             const double* w0, const double* L, const double* U, double d, double GMV,
+                             double lambda1, double lambda2, double lambda3, const ffo_options* opt,
+                             void* stream, double* w_out, ffo_info* infos);
+
 /* Thread-local description of the last non-OK status ("" if none). */
 const char* ffo_last_error(void);
 

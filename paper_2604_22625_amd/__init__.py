@@ -13,7 +13,7 @@ from dataclasses import dataclass, asdict
 
 import numpy as np
 
-__all__ = ["solve", "solve_instance", "Info", "FolioError", "lib", "LIB_PATH", "STATUS"]
+__all__ = ["solve", "solve_instance", "solve_batched", "Info", "FolioError", "lib", "LIB_PATH", "STATUS"]
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libffolio.so")
 
@@ -83,6 +83,9 @@ def lib() -> ctypes.CDLL:
                                 _D, _D, _D, _D, _P, ctypes.POINTER(_Options), _P, _P, _P,
                                 ctypes.POINTER(_Info)]
         L.ffo_solve.restype = ctypes.c_int
+        L.ffo_solve_batched.argtypes = [_I64, _P, _I64, _I64, _I64, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P,
+                                        _D, _D, _D, _D, _D, ctypes.POINTER(_Options), _P, _P, _P]
+        L.ffo_solve_batched.restype = ctypes.c_int
         L.ffo_last_error.argtypes = []
         L.ffo_last_error.restype = ctypes.c_char_p
         L.ffo_release.argtypes = []
@@ -196,3 +199,54 @@ def solve_instance(inst: dict, **kw):
     return solve(inst["alpha"], inst["F"], inst["Omega"], inst["delta"], inst["s"], inst["q"], inst["d"],
                  inst["A"], inst["L"], inst["U"], inst["w0"], inst["GMV"], inst["lambda1"], inst["lambda2"],
                  inst["lambda3"], inst.get("w_target") if T else None, **kw)
+
+
+def solve_batched(batch: dict, *, tol: float = 1e-6, max_iter: int = 1_000_000, time_limit_s: float = 360.0,
+                  check_every: int = 64, restart=(0.2, 0.8, 0.36), reflection: float = 1.0, verbose: int = 0,
+                  precision="fp64", raise_on_failure: bool = True, device=None, stream=None, out=None):
+    """Solve a batch of single-period instances on one shared universe (layout of
+    ``synth.make_batch``: n_b, offs, n_max, F, Omega, delta, A shared; alpha, s, q, w0
+    packed; L, U [B][m]).  Returns (w packed [N] float64 CUDA tensor, list of Info)."""
+    torch = _torch()
+    if not torch.cuda.is_available():
+        raise FolioError(3, "no GPU visible to PyTorch: the solver has no CPU path")
+    dev = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
+    n_b = np.ascontiguousarray(np.asarray(batch["n_b"], dtype=np.int64))
+    offs = np.ascontiguousarray(np.asarray(batch["offs"], dtype=np.int64))
+    B = int(n_b.shape[0])
+    n_max = int(batch["n_max"])
+    k = int(batch["k"])
+    m = int(batch["m"])
+    Fd = _dev_f64(batch["F"], dev).reshape(n_max, k) if k else None
+    Od = _dev_f64(batch["Omega"], dev).reshape(k, k) if k else None
+    dd = _dev_f64(batch["delta"], dev).reshape(n_max)
+    Ad = _dev_f64(batch["A"], dev).reshape(m, n_max) if m else None
+    a = _dev_f64(batch["alpha"], dev).reshape(-1)
+    sd = _dev_f64(batch["s"], dev).reshape(-1)
+    qd = _dev_f64(batch["q"], dev).reshape(-1)
+    w0d = _dev_f64(batch["w0"], dev).reshape(-1)
+    Ld = _dev_f64(batch["L"], dev).reshape(B, m) if m else None
+    Ud = _dev_f64(batch["U"], dev).reshape(B, m) if m else None
+    N = int(offs[-1])
+    W = out if out is not None else torch.empty(N, dtype=torch.float64, device=dev)
+    o = default_options()
+    o.tol_rel_kkt = float(tol)
+    o.max_iter = int(max_iter)
+    o.time_limit_s = float(time_limit_s)
+    o.check_every = int(check_every)
+    o.restart_suff, o.restart_nec, o.restart_art = (float(v) for v in restart)
+    o.reflection = float(reflection)
+    o.verbose = int(verbose)
+    o.precision = PRECISION[precision] if isinstance(precision, str) else int(precision)
+    infos = (_Info * B)()
+    st = torch.cuda.current_stream(dev) if stream is None else stream
+    with torch.cuda.device(dev):
+        rc = lib().ffo_solve_batched(B, n_b.ctypes.data_as(ctypes.c_void_p), n_max, k, m, _ptr(Fd), _ptr(Od),
+                                     _ptr(dd), _ptr(Ad), offs.ctypes.data_as(ctypes.c_void_p), _ptr(a), _ptr(sd),
+                                     _ptr(qd), _ptr(w0d), _ptr(Ld), _ptr(Ud), float(batch["d"]), float(batch["GMV"]),
+                                     float(batch["lambda1"]), float(batch["lambda2"]), float(batch["lambda3"]),
+                                     ctypes.byref(o), ctypes.c_void_p(st.cuda_stream), _ptr(W), infos)
+    out_infos = [Info(**{f[0]: getattr(i, f[0]) for f in _Info._fields_}) for i in infos]
+    if rc == 1 or (rc in (2, 3)) or (rc != 0 and raise_on_failure):
+        raise FolioError(rc, lib().ffo_last_error().decode())
+    return W, out_infos

@@ -15,6 +15,7 @@
 #include <map>
 #include <mutex>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "../../include/ffolio.h"
@@ -44,12 +45,12 @@ struct Workspace {
 };
 
 std::mutex g_mu;
-std::map<std::pair<int, void*>, Workspace> g_ws;
+std::map<std::tuple<int, void*, int>, Workspace> g_ws;
 
-// Grow-only device workspace for (device, stream).
-ffo_status get_workspace(int dev, void* stream, size_t bytes, size_t host_bytes, Workspace** out) {
+// Grow-only device workspace for (device, stream, kind); kind 0 = ffo_solve, 1 = batched.
+ffo_status get_workspace(int dev, void* stream, size_t bytes, size_t host_bytes, Workspace** out, int kind = 0) {
   std::lock_guard<std::mutex> lk(g_mu);
-  Workspace& w = g_ws[{dev, stream}];
+  Workspace& w = g_ws[std::make_tuple(dev, stream, kind)];
   if (w.bytes < bytes) {
     if (w.base) hipFree(w.base);
     w.base = nullptr;
@@ -156,7 +157,7 @@ __global__ void k_validate(int64_t n, int64_t Pn, int64_t Tpn, int64_t nk, int64
     if (!isfinite(F[e])) bad |= 2;
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n; e += stride) {
     if (!(delta[e] > 0.0) || !isfinite(delta[e])) bad |= 4;
-    if (!isfinite(w0[e])) bad |= 8;
+    if (w0 && !isfinite(w0[e])) bad |= 8;
     if (wT && !isfinite(wT[e])) bad |= 8;
   }
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < Tpn; e += stride)
@@ -166,7 +167,60 @@ __global__ void k_validate(int64_t n, int64_t Pn, int64_t Tpn, int64_t nk, int64
   if (bad) atomicOr(flag, bad);
 }
 
+// Packed per-instance vectors of the batched form: alpha, w0 finite; s, q >= 0 finite
+// (N entries); L <= U (Bm entries).
+__global__ void k_validate_packed(int64_t N, int64_t Bm, const double* alpha, const double* s, const double* q,
+                                  const double* w0, const double* L, const double* U, int* flag) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  int bad = 0;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < N; e += stride) {
+    if (!isfinite(alpha[e])) bad |= 1;
+    if (!isfinite(w0[e])) bad |= 8;
+    if (!(s[e] >= 0.0) || !(q[e] >= 0.0) || !isfinite(s[e]) || !isfinite(q[e])) bad |= 16;
+  }
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < Bm; e += stride)
+    if (!(L[e] <= U[e]) || isnan(L[e]) || isnan(U[e]) || L[e] == INFINITY || U[e] == -INFINITY) bad |= 32;
+  if (bad) atomicOr(flag, bad);
+}
+
 size_t align_up(size_t x) { return (x + 255) / 256 * 256; }
+
+std::string bad_values(int flag) {
+  std::string why;
+  if (flag & 1) why += " alpha not finite;";
+  if (flag & 2) why += " F not finite;";
+  if (flag & 4) why += " delta must be positive and finite;";
+  if (flag & 8) why += " w0/w_target not finite;";
+  if (flag & 16) why += " s and q must be nonnegative and finite;";
+  if (flag & 32) why += " need L <= U (no NaN, L < +inf, U > -inf);";
+  return "invalid input values:" + why;
+}
+
+void fill_info(ffo_info* info, ffo_status st, const double* hinfo, double ms_setup, double ms_iter) {
+  info->status = st;
+  info->iters = (int64_t)hinfo[ffo::IX_ITERS];
+  info->restarts = (int64_t)hinfo[ffo::IX_RESTARTS];
+  info->rel_kkt = hinfo[ffo::IX_RELKKT];
+  info->rel_pri = hinfo[ffo::IX_RELPRI];
+  info->rel_dual = hinfo[ffo::IX_RELDUAL];
+  info->rel_gap = hinfo[ffo::IX_RELGAP];
+  info->fixed_point_res = hinfo[ffo::IX_FPR];
+  info->primal_obj = hinfo[ffo::IX_POBJ];
+  info->dual_obj = hinfo[ffo::IX_DOBJ];
+  info->omega = hinfo[ffo::IX_OMEGA];
+  info->ms_setup = ms_setup;
+  info->ms_iter = ms_iter;
+}
+
+ffo_status status_of(int32_t hstat) {
+  switch (hstat) {
+    case ffo::DS_OK: return FFO_OK;
+    case ffo::DS_NOT_CONVERGED: return FFO_NOT_CONVERGED;
+    case ffo::DS_NUMERIC: return FFO_NUMERIC;
+    case ffo::DS_TIMEOUT: return FFO_TIMEOUT;
+    default: return FFO_EDEVICE;
+  }
+}
 
 }  // namespace
 
@@ -250,7 +304,7 @@ ffo_status ffo_solve(int64_t n, int64_t k, int64_t m, int64_t T, const double* a
   const int ldk = (int)((n + 63) / 64 * 64);
   ffo::DevProblem p{};
   p.n = (int)n; p.k = (int)k; p.m = (int)m; p.P = (int)P; p.Tp = (int)Tp; p.nr = nr;
-  p.multi = T > 0 ? 1 : 0; p.ldk = ldk;
+  p.multi = T > 0 ? 1 : 0; p.ldk = ldk; p.kscaled = 1;
   const int cus = std::max(1, prop.multiProcessorCount);
   int nwg = opt.workgroups > 0 ? opt.workgroups : (int)std::min<int64_t>(cus, (n + 63) / 64);
   nwg = std::max(1, std::min<int>(nwg, (int)n));
@@ -406,13 +460,272 @@ ffo_status ffo_solve(int64_t n, int64_t k, int64_t m, int64_t T, const double* a
   return st;
 }
 
+ffo_status ffo_solve_batched(int64_t B, const int64_t* n_b, int64_t n_max, int64_t k, int64_t m,
+                             const double* F, const double* Omega, const double* delta, const double* A,
+                             const int64_t* offs, const double* alpha, const double* s, const double* q,
+                             const double* w0, const double* L, const double* U, double d, double GMV,
+                             double lambda1, double lambda2, double lambda3, const ffo_options* opt_in,
+                             void* stream, double* w_out, ffo_info* infos) {
+  g_err.clear();
+  ffo_options opt;
+  ffo_default_options(&opt);
+  if (opt_in) opt = *opt_in;
+  // ---- host-only validation (no device work before this point) ----
+  if (B < 1 || B > (1 << 20)) return fail(FFO_EINVAL, "B must lie in [1, 2^20]");
+  if (!n_b || !offs || !infos) return fail(FFO_EINVAL, "null host array (n_b, offs or infos)");
+  if (n_max < 1 || n_max > (1 << 24)) return fail(FFO_EINVAL, "n_max must lie in [1, 2^24]");
+  if (k < 0 || k > 128) return fail(FFO_EINVAL, "k must lie in [0, 128]");
+  if (m < 0 || m > 4096) return fail(FFO_EINVAL, "m must lie in [0, 4096]");
+  if (offs[0] != 0) return fail(FFO_EINVAL, "offs[0] must be 0");
+  for (int64_t b = 0; b < B; ++b) {
+    if (n_b[b] < 1 || n_b[b] > n_max) return fail(FFO_EINVAL, "every n_b must lie in [1, n_max]");
+    if (offs[b + 1] - offs[b] != n_b[b]) return fail(FFO_EINVAL, "offs must be the running sum of n_b");
+  }
+  const int64_t N = offs[B];
+  if (N > ((int64_t)1 << 31)) return fail(FFO_EINVAL, "sum of n_b too large");
+  if (!alpha || !delta || !s || !q || !w0 || !w_out) return fail(FFO_EINVAL, "null array pointer");
+  if (k > 0 && (!F || !Omega)) return fail(FFO_EINVAL, "F and Omega are required when k > 0");
+  if (m > 0 && (!A || !L || !U)) return fail(FFO_EINVAL, "A, L and U are required when m > 0");
+  if (!(d > 1.0 && d <= 2.0)) return fail(FFO_EINVAL, "d must lie in (1, 2]");
+  if (!(GMV > 0.0) || !std::isfinite(GMV)) return fail(FFO_EINVAL, "GMV must be positive and finite");
+  if (!(lambda1 > 0.0) || !std::isfinite(lambda1)) return fail(FFO_EINVAL, "lambda1 must be positive and finite");
+  if (!(lambda2 >= 0.0) || !(lambda3 >= 0.0) || !std::isfinite(lambda2) || !std::isfinite(lambda3))
+    return fail(FFO_EINVAL, "lambda2 and lambda3 must be nonnegative and finite");
+  if (!(opt.tol_rel_kkt > 0.0)) return fail(FFO_EINVAL, "tol_rel_kkt must be positive");
+  if (opt.max_iter < 1) return fail(FFO_EINVAL, "max_iter must be >= 1");
+  if (opt.check_every < 1) return fail(FFO_EINVAL, "check_every must be >= 1");
+  if (!(opt.time_limit_s > 0.0)) return fail(FFO_EINVAL, "time_limit_s must be positive");
+  if (!(opt.reflection >= 0.0 && opt.reflection <= 1.0)) return fail(FFO_EINVAL, "reflection must lie in [0, 1]");
+  if (opt.precision != FFO_FP64 && opt.precision != FFO_FP32)
+    return fail(FFO_EINVAL, "ffo_solve_batched takes FFO_FP64 or FFO_FP32");
+
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  hipDeviceProp_t prop;
+  HIPCHK(hipGetDeviceProperties(&prop, dev));
+  int wall_khz = 0;
+  if (hipDeviceGetAttribute(&wall_khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess || wall_khz <= 0)
+    wall_khz = 100000;
+  const int cus = std::max(1, prop.multiProcessorCount);
+  const int nr = (int)(m + k);
+  const int ldk = (int)((n_max + 63) / 64 * 64);
+  const int prec = opt.precision == FFO_FP32 ? ffo::PREC_FP32 : ffo::PREC_FP64;
+
+  // ---- control and team sizing ----
+  ffo::DevProblem p0{};
+  p0.k = (int)k; p0.m = (int)m; p0.P = 1; p0.Tp = 1; p0.nr = nr; p0.multi = 0; p0.ldk = ldk; p0.kscaled = 0;
+  ffo::DevControl c0{};
+  c0.tol = opt.tol_rel_kkt; c0.time_limit_s = opt.time_limit_s;
+  c0.r_suff = opt.restart_suff; c0.r_nec = opt.restart_nec; c0.r_art = opt.restart_art;
+  c0.rho = opt.reflection; c0.eta_safety = 0.95; c0.max_iter = opt.max_iter; c0.check_every = opt.check_every;
+  c0.npow = 40; c0.verbose = opt.verbose; c0.spin_limit = 1u << 26; c0.wall_hz = (double)wall_khz * 1e3;
+  c0.prec = prec; c0.spec = 1; c0.lds_k = 0; c0.lds_state = 0;
+  c0.vmax = ffo::solve_vmax(p0);
+  const int NW_MAX = 2048;   // assets per workgroup at most (bounds the LDS staging)
+  const int NW_MIN = 256;    // extra workgroups only while a team keeps at least this many assets each
+  size_t lds_cap = 0;
+  {
+    ffo::DevProblem pp = p0;
+    ffo::DevControl cc = c0;
+    pp.n = NW_MAX; cc.nw = NW_MAX; cc.nwg = 1; cc.xmode = ffo::XM_LOCAL;
+    lds_cap = ffo::solve_lds_bytes(pp, cc);
+  }
+  if (lds_cap > std::min<size_t>(prop.sharedMemPerBlock, 160 * 1024))
+    return fail(FFO_EINVAL, "m + k too large for the batched working set");
+  const int occ = ffo::solve_batch_occupancy(0, 0, prec, lds_cap);
+  if (occ < 1) return fail(FFO_EDEVICE, "the batched solve kernel cannot be resident");
+  const int W = occ * cus;
+  // instances in decreasing size, cut into launches whose minimal teams fit the resident grid
+  std::vector<int64_t> order(B);
+  for (int64_t b = 0; b < B; ++b) order[b] = b;
+  std::stable_sort(order.begin(), order.end(), [&](int64_t a, int64_t b) { return n_b[a] > n_b[b]; });
+  std::vector<int> g(B, 1);
+  std::vector<std::pair<int64_t, int64_t>> chunks;   // [first, last) into order
+  {
+    int64_t first = 0, used = 0;
+    for (int64_t r = 0; r < B; ++r) {
+      const int64_t need = (n_b[order[r]] + NW_MAX - 1) / NW_MAX;
+      if (used + need > W && r > first) {
+        chunks.push_back({first, r});
+        first = r;
+        used = 0;
+      }
+      used += need;
+    }
+    chunks.push_back({first, B});
+  }
+  for (const auto& ch : chunks) {
+    int64_t used = 0;
+    for (int64_t r = ch.first; r < ch.second; ++r) {
+      g[order[r]] = (int)((n_b[order[r]] + NW_MAX - 1) / NW_MAX);
+      used += g[order[r]];
+    }
+    // spare workgroups go to the team with the most assets per workgroup
+    while (used < W) {
+      int64_t best = -1;
+      double bv = 0.0;
+      for (int64_t r = ch.first; r < ch.second; ++r) {
+        const int64_t b = order[r];
+        const double per = (double)n_b[b] / g[b];
+        if ((double)n_b[b] / (g[b] + 1) >= NW_MIN && per > bv) { bv = per; best = b; }
+      }
+      if (best < 0) break;
+      g[best]++;
+      used++;
+    }
+  }
+
+  // ---- workspace layout ----
+  size_t off = 0;
+  auto carve = [&](size_t cnt, size_t elt) { const size_t o = off; off = align_up(off + cnt * elt); return o; };
+  const size_t oK = carve((size_t)std::max(nr, 1) * ldk, 8), odc = carve(n_max, 8), odrC = carve(n_max, 8);
+  const size_t oar = carve(n_max, 8), ocv = carve(n_max, 8), obF = carve(std::max<int64_t>(k, 1), 8);
+  const size_t ocr = carve(1, 8), oC = carve(std::max<int64_t>(k * k, 1), 8), onb = carve(B, 8);
+  const size_t odrs = carve((size_t)B * std::max(nr, 1), 8), oca = carve(N, 8), ocb = carve(N, 8);
+  size_t ost[9];
+  for (auto& o : ost) o = carve(N, 8);
+  const size_t oxb = carve((size_t)B * 3 * c0.vmax, 8), obar = carve(B, 8);
+  const size_t oinfo = carve((size_t)B * ffo::INFO_LEN, 8), ostat = carve(B, 4), oflag = carve(1, 4);
+  const size_t oP = carve(B, sizeof(ffo::DevProblem)), oS = carve(B, sizeof(ffo::DevState));
+  const size_t oCt = carve(B, sizeof(ffo::DevControl)), oteam = carve(W, 4), orank = carve(W, 4);
+  const size_t total = off;
+  size_t hoff = 0;
+  auto hcarve = [&](size_t bytes) { const size_t o = hoff; hoff = align_up(hoff + bytes); return o; };
+  const size_t hOm_o = hcarve((size_t)std::max<int64_t>(k * k, 1) * 8), hC_o = hcarve((size_t)std::max<int64_t>(k * k, 1) * 8);
+  const size_t hflag_o = hcarve(4), hinfo_o = hcarve((size_t)B * ffo::INFO_LEN * 8), hstat_o = hcarve((size_t)B * 4);
+  const size_t hP_o = hcarve((size_t)B * sizeof(ffo::DevProblem)), hS_o = hcarve((size_t)B * sizeof(ffo::DevState));
+  const size_t hCt_o = hcarve((size_t)B * sizeof(ffo::DevControl)), hnb_o = hcarve((size_t)B * 8);
+  const size_t hteam_o = hcarve((size_t)W * 4 * chunks.size()), hrank_o = hcarve((size_t)W * 4 * chunks.size());
+  const size_t host_bytes = hoff;
+
+  Workspace* ws = nullptr;
+  if (ffo_status st = get_workspace(dev, stream, total, host_bytes, &ws, 1)) return st;
+  char* Bd = (char*)ws->base;
+  char* Hb = (char*)ws->host;
+  auto D = [&](size_t o) { return (double*)(Bd + o); };
+  hipStream_t hs = (hipStream_t)stream;
+  double* hOm = (double*)(Hb + hOm_o);
+  double* hC = (double*)(Hb + hC_o);
+  int* hflag = (int*)(Hb + hflag_o);
+
+  // ---- device value checks (one synchronisation, with the Omega copy) ----
+  HIPCHK(hipEventRecord(ws->ev[0], hs));
+  std::memcpy(Hb + hnb_o, n_b, (size_t)B * 8);
+  HIPCHK(hipMemcpyAsync(Bd + onb, Hb + hnb_o, (size_t)B * 8, hipMemcpyHostToDevice, hs));
+  HIPCHK(hipMemsetAsync(Bd + oflag, 0, 4, hs));
+  hipLaunchKernelGGL(k_validate, dim3(64), dim3(256), 0, hs, n_max, (int64_t)0, (int64_t)0, n_max * k, (int64_t)0,
+                     (const double*)nullptr, F, delta, (const double*)nullptr, (const double*)nullptr,
+                     (const double*)nullptr, (const double*)nullptr, (const double*)nullptr, (const double*)nullptr,
+                     (int*)(Bd + oflag));
+  hipLaunchKernelGGL(k_validate_packed, dim3(64), dim3(256), 0, hs, N, B * m, alpha, s, q, w0, L, U,
+                     (int*)(Bd + oflag));
+  HIPCHK(hipGetLastError());
+  if (k > 0) HIPCHK(hipMemcpyAsync(hOm, Omega, (size_t)k * k * 8, hipMemcpyDeviceToHost, hs));
+  HIPCHK(hipMemcpyAsync(hflag, Bd + oflag, 4, hipMemcpyDeviceToHost, hs));
+  HIPCHK(hipStreamSynchronize(hs));
+  if (*hflag) return fail(FFO_EINVAL, bad_values(*hflag));
+  if (k > 0 && !factor_omega((int)k, hOm, hC)) return fail(FFO_EINVAL, "Omega must be symmetric positive semidefinite");
+  if (k > 0) HIPCHK(hipMemcpyAsync(D(oC), hC, (size_t)k * k * 8, hipMemcpyHostToDevice, hs));
+
+  // ---- setup: shared rows and per-instance scales ----
+  const double g1 = lambda1 * GMV, g2 = lambda2, g3 = lambda3;
+  if (ffo::launch_setup_batch(B, (const int64_t*)(Bd + onb), n_max, k, m, ldk, F, D(oC), A, delta, N, s, q, g1, g2, g3,
+                              D(oK), D(odrs), D(odc), D(odrC), D(oar), D(ocv), D(oca), D(ocb), stream))
+    return fail(FFO_EDEVICE, "setup kernel launch failed");
+  HIPCHK(hipMemsetAsync(Bd + obF, 0, (size_t)std::max<int64_t>(k, 1) * 8, hs));
+  HIPCHK(hipMemsetAsync(Bd + ocr, 0, 8, hs));
+  HIPCHK(hipMemsetAsync(Bd + oxb, 0, (size_t)B * 3 * c0.vmax * 8, hs));
+  HIPCHK(hipMemsetAsync(Bd + obar, 0, (size_t)B * 8, hs));
+  HIPCHK(hipMemsetAsync(Bd + oinfo, 0, (size_t)B * ffo::INFO_LEN * 8, hs));
+  HIPCHK(hipMemsetAsync(Bd + ostat, 0xff, (size_t)B * 4, hs));
+
+  // ---- per-instance problem, state and control ----
+  ffo::DevProblem* hP = (ffo::DevProblem*)(Hb + hP_o);
+  ffo::DevState* hS = (ffo::DevState*)(Hb + hS_o);
+  ffo::DevControl* hCt = (ffo::DevControl*)(Hb + hCt_o);
+  for (int64_t b = 0; b < B; ++b) {
+    const int64_t o = offs[b];
+    ffo::DevProblem p = p0;
+    p.n = (int)n_b[b];
+    p.K = D(oK); p.dr = D(odrs) + (size_t)b * nr; p.dc = D(odc); p.drC = D(odrC); p.alpha = alpha + o;
+    p.arisk = D(oar); p.cvec = D(ocv); p.ca = D(oca) + o; p.cb = D(ocb) + o; p.w0 = w0 + o; p.wT = nullptr;
+    p.L = m ? L + (size_t)b * m : nullptr; p.U = m ? U + (size_t)b * m : nullptr;
+    p.bF = D(obF); p.crisk = D(ocr); p.g1 = g1; p.d = d;
+    hP[b] = p;
+    ffo::DevState sv{};
+    sv.xs = D(ost[0]) + o; sv.x0s = D(ost[1]) + o; sv.Txs = D(ost[2]) + o;
+    sv.bb = D(ost[3]) + o; sv.aa = D(ost[4]) + o; sv.vpow = D(ost[5]) + o;
+    sv.ysC = D(ost[6]) + o; sv.ys0C = D(ost[7]) + o; sv.TysC = D(ost[8]) + o;
+    sv.xbuf = D(oxb) + (size_t)b * 3 * c0.vmax; sv.bar = (unsigned long long*)(Bd + obar) + b;
+    sv.info = D(oinfo) + (size_t)b * ffo::INFO_LEN; sv.status = (int32_t*)(Bd + ostat) + b;
+    sv.w_out = w_out + o; sv.y_out = nullptr;
+    hS[b] = sv;
+    ffo::DevControl c = c0;
+    c.nwg = g[b];
+    c.nw = (int)((n_b[b] + g[b] - 1) / g[b]);
+    c.xmode = g[b] == 1 ? ffo::XM_LOCAL : ffo::XM_ATOMIC;
+    hCt[b] = c;
+  }
+  HIPCHK(hipMemcpyAsync(Bd + oP, hP, (size_t)B * sizeof(ffo::DevProblem), hipMemcpyHostToDevice, hs));
+  HIPCHK(hipMemcpyAsync(Bd + oS, hS, (size_t)B * sizeof(ffo::DevState), hipMemcpyHostToDevice, hs));
+  HIPCHK(hipMemcpyAsync(Bd + oCt, hCt, (size_t)B * sizeof(ffo::DevControl), hipMemcpyHostToDevice, hs));
+  HIPCHK(hipEventRecord(ws->ev[1], hs));
+
+  // ---- one cooperative launch per chunk ----
+  for (size_t ci = 0; ci < chunks.size(); ++ci) {
+    int* ht = (int*)(Hb + hteam_o) + ci * W;
+    int* hr = (int*)(Hb + hrank_o) + ci * W;
+    int nb = 0;
+    size_t lds = 0;
+    for (int64_t r = chunks[ci].first; r < chunks[ci].second; ++r) {
+      const int64_t b = order[r];
+      for (int w = 0; w < g[b]; ++w) { ht[nb] = (int)b; hr[nb] = w; ++nb; }
+      lds = std::max(lds, ffo::solve_lds_bytes(hP[b], hCt[b]));
+    }
+    // the device team tables are rewritten in stream order, after the previous launch
+    HIPCHK(hipMemcpyAsync(Bd + oteam, ht, (size_t)nb * 4, hipMemcpyHostToDevice, hs));
+    HIPCHK(hipMemcpyAsync(Bd + orank, hr, (size_t)nb * 4, hipMemcpyHostToDevice, hs));
+    if (int e = ffo::launch_solve_batch((const ffo::DevProblem*)(Bd + oP), (const ffo::DevState*)(Bd + oS),
+                                        (const ffo::DevControl*)(Bd + oCt), (const int*)(Bd + oteam),
+                                        (const int*)(Bd + orank), nb, 0, 0, prec, stream, lds))
+      return fail(FFO_EDEVICE, std::string("cooperative launch of the batched solve kernel failed: ") +
+                                   hipGetErrorString((hipError_t)e));
+  }
+  HIPCHK(hipEventRecord(ws->ev[2], hs));
+  double* hinfo = (double*)(Hb + hinfo_o);
+  int32_t* hstat = (int32_t*)(Hb + hstat_o);
+  HIPCHK(hipMemcpyAsync(hinfo, Bd + oinfo, (size_t)B * ffo::INFO_LEN * 8, hipMemcpyDeviceToHost, hs));
+  HIPCHK(hipMemcpyAsync(hstat, Bd + ostat, (size_t)B * 4, hipMemcpyDeviceToHost, hs));
+  HIPCHK(hipStreamSynchronize(hs));
+  float ms_setup = 0.f, ms_iter = 0.f;
+  hipEventElapsedTime(&ms_setup, ws->ev[0], ws->ev[1]);
+  hipEventElapsedTime(&ms_iter, ws->ev[1], ws->ev[2]);
+  ffo_status worst = FFO_OK;
+  auto rank = [](ffo_status x) {
+    return x == FFO_EDEVICE ? 4 : x == FFO_NUMERIC ? 3 : x == FFO_TIMEOUT ? 2 : x == FFO_NOT_CONVERGED ? 1 : 0;
+  };
+  for (int64_t b = 0; b < B; ++b) {
+    const ffo_status st = status_of(hstat[b]);
+    fill_info(&infos[b], st, hinfo + (size_t)b * ffo::INFO_LEN, ms_setup, ms_iter);
+    if (rank(st) > rank(worst)) worst = st;
+  }
+  if (opt.verbose)
+    std::fprintf(stderr, "[ffo batch] B %lld launches %zu resident %d (occupancy %d) lds %zu | setup %.3f ms solve %.3f ms\n",
+                 (long long)B, chunks.size(), W, occ, lds_cap, ms_setup, ms_iter);
+  if (worst == FFO_NOT_CONVERGED) g_err = "iteration limit reached for at least one instance";
+  else if (worst == FFO_TIMEOUT) g_err = "time limit reached for at least one instance";
+  else if (worst == FFO_NUMERIC) g_err = "NaN or Inf in an FP64 check of at least one instance";
+  else if (worst == FFO_EDEVICE) g_err = "a team ended without a result (bounded wait expired)";
+  return worst;
+}
+
 // Extra diagnostics of the last solve on this thread's (device, stream): not part of the
 // stable interface; used by the benchmark to report exchanges and speculation misses.
 int ffo_debug_last_info(void* stream, double* out16) {
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess) return 1;
   std::lock_guard<std::mutex> lk(g_mu);
-  auto it = g_ws.find({dev, stream});
+  auto it = g_ws.find(std::make_tuple(dev, stream, 0));
   if (it == g_ws.end() || !it->second.host) return 1;
   std::memcpy(out16, it->second.host, ffo::INFO_LEN * sizeof(double));
   return 0;

@@ -6,7 +6,9 @@
 namespace ffo {
 
 // Exchange buffer modes of the persistent kernel.
-enum XMode : int32_t { XM_ATOMIC = 0, XM_GATHER = 1 };
+// Exchange modes: device-scope atomic adds, per-workgroup slots summed in a fixed order,
+// or (a single-workgroup team) LDS only.
+enum XMode : int32_t { XM_ATOMIC = 0, XM_GATHER = 1, XM_LOCAL = 2 };
 
 // Status codes written by the device (mirror ffo_status).
 enum DevStatus : int32_t {
@@ -19,7 +21,8 @@ enum DevStatus : int32_t {
 //   trade rows (per asset) carry drC[t][i] * dc[i] * (+-1)
 struct DevProblem {
   int32_t n, k, m, P, Tp, nr, multi, ldk;
-  const double* K;      // [nr][ldk] scaled constraint rows
+  int32_t kscaled;      // 1: K holds diag(dr) K diag(dc); 0: K holds K diag(dc), rows scaled by dr on use
+  const double* K;      // [nr][ldk] constraint rows (see kscaled)
   const double* dr;     // [nr]
   const double* dc;     // [n]
   const double* drC;    // [Tp][n]
@@ -79,9 +82,24 @@ enum InfoIdx {
 int launch_solve(const DevProblem& p, const DevState& s, const DevControl& c, void* stream,
                  size_t lds_bytes);
 size_t solve_lds_bytes(const DevProblem& p, const DevControl& c);
+// Batched launch: workgroup b of the grid runs rank wg_rank[b] of team wg_team[b]; team t
+// solves problem dp[t] with state ds[t] and control dc[t] (device arrays).  All teams use
+// the same instantiation (kl, sl, prec) and the same dynamic LDS size.
+int launch_solve_batch(const DevProblem* dp, const DevState* ds, const DevControl* dc, const int* wg_team,
+                       const int* wg_rank, int nblocks, int kl, int sl, int prec, void* stream, size_t lds_bytes);
+// Resident workgroups per CU of the batched kernel at the given dynamic LDS size.
+int solve_batch_occupancy(int kl, int sl, int prec, size_t lds_bytes);
 int solve_vmax(const DevProblem& p);
 
 // Setup kernels (setup_kernels.hip).
+// Batched form: shared rows K diag(dc) of the n_max-asset universe (unscaled by rows),
+// per-instance row scales drs [B][nr] over each prefix of nb[b] columns (nb on the
+// device), shared arisk / cvec (zero) / drC (one), packed cost coefficients ca, cb [N].
+int launch_setup_batch(int64_t B, const int64_t* nb_dev, int64_t n_max, int64_t k, int64_t m, int ldk,
+                       const double* F, const double* Cfac, const double* A, const double* delta, int64_t N,
+                       const double* s, const double* q, double g1, double g2, double g3, double* Kbuf,
+                       double* drs, double* dc, double* drC, double* arisk, double* cvec, double* ca, double* cb,
+                       void* stream);
 int launch_setup(int64_t n, int64_t k, int64_t m, int64_t P, int64_t Tp, int ldk,
                  const double* F, const double* Cfac, const double* A, const double* delta,
                  const double* s, const double* q, const double* wT, double g1, double g2,

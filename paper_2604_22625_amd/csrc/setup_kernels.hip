@@ -83,7 +83,7 @@ __global__ __launch_bounds__(TB) void k_scale(int n, int nr, int ldk, double* __
   const int i = blockIdx.x * TB + threadIdx.x;
   const int j = blockIdx.y;
   if (i >= ldk || j >= nr) return;
-  if (i < n) K[(size_t)j * ldk + i] *= dr[j] * dc[i];
+  if (i < n) K[(size_t)j * ldk + i] *= (dr ? dr[j] : 1.0) * dc[i];
   else K[(size_t)j * ldk + i] = 0.0;
 }
 
@@ -99,14 +99,65 @@ __global__ __launch_bounds__(TB) void k_elem(int n, int P, int Tp, int multi, co
   cvec[i] = multi ? wT[i] : 0.0;
   for (int t = 0; t < Tp; ++t) {
     const size_t e = (size_t)t * n + i;
-    ca[e] = g2 * s[e];
-    cb[e] = g3 * q[e];
+    if (s) {
+      ca[e] = g2 * s[e];
+      cb[e] = g3 * q[e];
+    }
     // trade row t touches w_{t-1} and w_t: two unit entries except at the ends
     drC[e] = (!multi || t == 0 || t == P) ? 1.0 : 0.70710678118654752440;
   }
 }
 
+// Batched form, per instance b: row scales over the instance's prefix of nb[b] columns,
+// drs[b][j] = 1/sqrt(sum_{i < nb[b]} |K[j][i]|) (1 for an empty row).  One block per (j, b).
+__global__ __launch_bounds__(TB) void k_rows_prefix(int nr, int ldk, const double* __restrict__ K,
+                                                    const int64_t* __restrict__ nb, double* __restrict__ drs) {
+  __shared__ double s1[TB];
+  const int j = blockIdx.x, b = blockIdx.y;
+  const int64_t n = nb[b];
+  double a = 0.0;
+  for (int64_t i = threadIdx.x; i < n; i += TB) a += fabs(K[(size_t)j * ldk + i]);
+  s1[threadIdx.x] = a;
+  __syncthreads();
+  for (int w = TB / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w) s1[threadIdx.x] += s1[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) drs[(size_t)b * nr + j] = s1[0] > 0.0 ? 1.0 / sqrt(s1[0]) : 1.0;
+}
+
+// Batched form: per-asset cost coefficients of the packed instances.
+__global__ __launch_bounds__(TB) void k_costs(int64_t N, const double* __restrict__ s, const double* __restrict__ q,
+                                              double g2, double g3, double* __restrict__ ca, double* __restrict__ cb) {
+  const int64_t i = blockIdx.x * (int64_t)TB + threadIdx.x;
+  if (i >= N) return;
+  ca[i] = g2 * s[i];
+  cb[i] = g3 * q[i];
+}
+
 }  // namespace
+
+int launch_setup_batch(int64_t B, const int64_t* nb_dev, int64_t n_max, int64_t k, int64_t m, int ldk,
+                       const double* F, const double* Cfac, const double* A, const double* delta, int64_t N,
+                       const double* s, const double* q, double g1, double g2, double g3, double* Kbuf,
+                       double* drs, double* dc, double* drC, double* arisk, double* cvec, double* ca, double* cb,
+                       void* stream) {
+  hipStream_t st = (hipStream_t)stream;
+  const int nb = (int)((n_max + TB - 1) / TB);
+  hipLaunchKernelGGL(k_elem, dim3(nb), dim3(TB), 0, st, (int)n_max, 1, 1, 0, delta, (const double*)nullptr,
+                     (const double*)nullptr, (const double*)nullptr, g1, g2, g3, drC, arisk, cvec, (double*)nullptr,
+                     (double*)nullptr);
+  hipLaunchKernelGGL(k_costs, dim3((unsigned)((N + TB - 1) / TB)), dim3(TB), 0, st, N, s, q, g2, g3, ca, cb);
+  hipLaunchKernelGGL(k_build, dim3(nb), dim3(TB), (size_t)(k * k) * sizeof(double), st, (int)n_max, (int)k, (int)m,
+                     ldk, 1, F, Cfac, A, Kbuf, dc);
+  const int nr = (int)(m + k);
+  if (nr > 0) {
+    hipLaunchKernelGGL(k_rows_prefix, dim3(nr, (unsigned)B), dim3(TB), 0, st, nr, ldk, Kbuf, nb_dev, drs);
+    hipLaunchKernelGGL(k_scale, dim3((ldk + TB - 1) / TB, nr), dim3(TB), 0, st, (int)n_max, nr, ldk, Kbuf,
+                       (const double*)nullptr, dc);
+  }
+  return hipGetLastError() == hipSuccess ? 0 : 1;
+}
 
 int launch_setup(int64_t n, int64_t k, int64_t m, int64_t P, int64_t Tp, int ldk, const double* F,
                  const double* Cfac, const double* A, const double* delta, const double* s,

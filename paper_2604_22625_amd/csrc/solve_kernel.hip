@@ -142,6 +142,7 @@ struct Ctx {
   uint32_t spin_limit;
   ldbl* tot;              // LDS [vmax]
   ldbl* red;              // LDS reduction scratch [RED_LEN]
+  ldbl* lslot;            // LDS [3][vmax] exchange slots of a single-workgroup team (XM_LOCAL)
   lint* flag;             // LDS flag word
   long long t_wait;       // device-clock ticks spent waiting (thread 0)
   long long t_pre;        // ticks from exchange entry to barrier arrival (store completion)
@@ -151,7 +152,11 @@ struct Ctx {
 // Contribution j of this workgroup to the current exchange.  In gather mode every
 // index in [0, V) must be written each exchange; in atomic mode zeros may be skipped.
 __device__ __forceinline__ void put(const Ctx& c, int j, double v) {
-  if (c.xmode == XM_GATHER) {
+  if (c.xmode == XM_LOCAL) {
+    if (v != 0.0)
+      __hip_atomic_fetch_add(&c.lslot[(size_t)(c.epoch % 3) * c.vmax + j], v, __ATOMIC_RELAXED,
+                             __HIP_MEMORY_SCOPE_WORKGROUP);
+  } else if (c.xmode == XM_GATHER) {
     std_(&c.xbuf[((size_t)(c.epoch & 1) * c.nwg + c.wg) * c.vmax + j], v);
   } else if (v != 0.0) {
     addd(&c.xbuf[(size_t)(c.epoch % 3) * c.vmax + j], v);
@@ -162,7 +167,14 @@ __device__ __forceinline__ void put(const Ctx& c, int j, double v) {
 // atomic mode the maximum is taken on the bit patterns, which order non-negative
 // doubles like their values.
 __device__ __forceinline__ void put_max(const Ctx& c, int j, double v) {
-  if (c.xmode == XM_GATHER) {
+  if (c.xmode == XM_LOCAL) {
+    if (v > 0.0) {
+      typedef __attribute__((address_space(3))) unsigned long long lu64;
+      __hip_atomic_fetch_max((lu64*)&c.lslot[(size_t)(c.epoch % 3) * c.vmax + j],
+                             (unsigned long long)__double_as_longlong(v), __ATOMIC_RELAXED,
+                             __HIP_MEMORY_SCOPE_WORKGROUP);
+    }
+  } else if (c.xmode == XM_GATHER) {
     std_(&c.xbuf[((size_t)(c.epoch & 1) * c.nwg + c.wg) * c.vmax + j], v);
   } else if (v > 0.0) {
     unsigned long long* a = (unsigned long long*)&c.xbuf[(size_t)(c.epoch % 3) * c.vmax + j];
@@ -174,6 +186,19 @@ __device__ __forceinline__ void put_max(const Ctx& c, int j, double v) {
 // Barrier + reduction of the V published values into c.tot (LDS).  Returns false when
 // the bounded wait expired.
 __device__ bool xsync(Ctx& c, int V) {
+  if (c.xmode == XM_LOCAL) {   // one workgroup: the slot already holds the totals
+    __syncthreads();
+    const ldbl* cur = c.lslot + (size_t)(c.epoch % 3) * c.vmax;
+    ldbl* nxt = c.lslot + (size_t)((c.epoch + 2) % 3) * c.vmax;
+    for (int j = c.tid; j < c.vmax; j += TB) {
+      if (j < V) c.tot[j] = cur[j];
+      nxt[j] = 0.0;
+    }
+    __syncthreads();
+    c.epoch++;
+    c.mx_lo = c.mx_hi = 0;
+    return true;
+  }
   const long long tp0 = wall_clock64();
   __builtin_amdgcn_s_waitcnt(0);  // this wave's device-scope stores/atomics are complete
   __syncthreads();
@@ -280,9 +305,11 @@ struct Iter {
 template <bool KL, bool SL, class R = double>
 struct S {
   using RC = typename std::conditional<SL, R, double>::type;   // constants: LDS copies or FP64 inputs
+  static constexpr bool KLDS = KL;
   const DevProblem* p;
   const lds_t<R>* Kl;   // LDS slice [nr][ldl] (KL) ...
-  const double* Kg;     // ... or the scaled rows in device memory
+  const double* Kg;     // ... or the rows in device memory, times the LDS row scale ks
+  const ldbl* ks;
   int nw, ldl, i0;
   // state: anchors and per-iteration scratch in FP64, iterates through Iter views
   Arr<SL, double> x0s, bb, aa, xb;          // [P] anchor, prox input b, 1/a, xbar
@@ -295,7 +322,7 @@ struct S {
   Arr<SL, RC> dc, arisk, cvec, w0, wT;      // [1]
   __device__ __forceinline__ double Kat(int j, int li) const {
     if constexpr (KL) return (double)Kl[j * ldl + li];
-    else return Kg[(size_t)j * p->ldk + i0 + li];
+    else return Kg[(size_t)j * p->ldk + i0 + li] * ks[j];
   }
 };
 
@@ -346,12 +373,47 @@ __device__ void kty_all(const Ctx& c, const SV& v, const ldbl* y, int P, int nr,
   __syncthreads();
 }
 
+// Row products for rows read from device memory: lanes run over assets (coalesced
+// loads), each wave takes RB rows at a time and reduces them with DPP; emit as below.
+template <int NX, class SV, class F>
+__device__ void rows_prod_wide(const Ctx& c, const SV& v, const ldbl* x1, const ldbl* x2, int nw, int P, int nr,
+                               F emit) {
+  constexpr int RB = 8;
+  const int lane = c.tid & 63, wave = c.tid >> 6, ntot = P * nr;
+  for (int base = wave * RB; base < ntot; base += NWAVE * RB) {
+    double a[RB][NX];
+#pragma unroll
+    for (int r = 0; r < RB; ++r)
+#pragma unroll
+      for (int u = 0; u < NX; ++u) a[r][u] = 0.0;
+    for (int li = lane; li < c.nwa; li += 64) {
+#pragma unroll
+      for (int r = 0; r < RB; ++r) {
+        const int e = base + r;
+        if (e < ntot) {
+          const int t = e / nr, j = e - t * nr;
+          const double kv = v.Kat(j, li);
+          a[r][0] = fma(kv, x1[t * nw + li], a[r][0]);
+          if (NX > 1) a[r][NX - 1] = fma(kv, x2[t * nw + li], a[r][NX - 1]);
+        }
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < RB; ++r) {
+      double sum[NX];
+#pragma unroll
+      for (int u = 0; u < NX; ++u) sum[u] = wave_sum(a[r][u]);
+      if (lane == 0 && base + r < ntot) emit(base + r, sum);
+    }
+  }
+}
+
 // Row products over the owned assets with four lanes per row: for every e = t*nr + j,
 // emit(e, a) with a[q] = sum_li K~[j][li] xq[t*nw + li] (x1, and x2 when NX = 2; LDS).
 // All threads call (the lane shuffles need full waves).
 template <int NX, class SV, class F>
-__device__ void rows_prod(const Ctx& c, const SV& v, const ldbl* x1, const ldbl* x2, int nw, int P, int nr,
-                          F emit) {
+__device__ void rows_prod_lds(const Ctx& c, const SV& v, const ldbl* x1, const ldbl* x2, int nw, int P, int nr,
+                              F emit) {
   const int q = c.tid & 3, ntot = P * nr;
   for (int base = 0; base < ntot; base += TB / 4) {
     const int e = base + (c.tid >> 2);
@@ -373,6 +435,14 @@ __device__ void rows_prod(const Ctx& c, const SV& v, const ldbl* x1, const ldbl*
     for (int u = 0; u < NX; ++u) a[u] = sum4(a[u]);
     if (q == 0 && e < ntot) emit(e, a);
   }
+}
+
+// Rows in LDS: four lanes per row; rows in device memory: the coalesced wide form.
+template <int NX, class SV, class F>
+__device__ __forceinline__ void rows_prod(const Ctx& c, const SV& v, const ldbl* x1, const ldbl* x2, int nw, int P,
+                                          int nr, F emit) {
+  if constexpr (SV::KLDS) rows_prod_lds<NX>(c, v, x1, x2, nw, P, nr, emit);
+  else rows_prod_wide<NX>(c, v, x1, x2, nw, P, nr, emit);
 }
 
 // Trade-row adjoint for asset li, period t: dc (drC_t yC_t - drC_{t+1} yC_{t+1}).
@@ -599,13 +669,15 @@ extern __shared__ double g_lds[];
 template <class R>
 __host__ __device__ constexpr size_t lds_doubles(size_t count) { return (count * sizeof(R) + 7) / 8; }
 
+// One solve by a team of nwg workgroups; this workgroup is rank wg of the team.
 template <bool KL, bool SL, class R>
-__global__ __launch_bounds__(TB) void k_solve(DevProblem p, DevState s, DevControl ctl) {
+__device__ __forceinline__ void solve_body(const DevProblem& p, const DevState& s, const DevControl& ctl, int wg,
+                                           int nwg) {
   ldbl* lds = (ldbl*)g_lds;
   const int P = p.P, nr = p.nr, n = p.n, Tp = p.Tp, nw = ctl.nw;
   Ctx c;
-  c.wg = blockIdx.x;
-  c.nwg = gridDim.x;
+  c.wg = wg;
+  c.nwg = nwg;
   c.tid = threadIdx.x;
   c.i0 = c.wg * nw;
   c.nwa = max(0, min(nw, n - c.i0));
@@ -637,6 +709,9 @@ __global__ __launch_bounds__(TB) void k_solve(DevProblem p, DevState s, DevContr
   ldbl* xv4 = ptr;  ptr += P * nw;          // 1/a of the current multiplier problem
   ldbl* tot = ptr;  ptr += ctl.vmax;
   ldbl* red = ptr;  ptr += RED_LEN;
+  ldbl* ks = ptr;   ptr += nr;              // row scale applied to rows read from device memory
+  ldbl* lslot = nullptr;
+  if (ctl.xmode == XM_LOCAL) { lslot = ptr; ptr += 3 * (size_t)ctl.vmax; }
   ldbl* cen = ptr;  ptr += P;               // predicted multiplier (centre) ...
   ldbl* hw = ptr;   ptr += P;               // ... and half-width of the central pair
   ldbl* lo = ptr;   ptr += P;               // multisection bracket
@@ -691,7 +766,7 @@ __global__ __launch_bounds__(TB) void k_solve(DevProblem p, DevState s, DevContr
   S<false, false, double> G;
   {
     auto g = [&](const double* b) { return Arr<false, double>{(double*)b, n, c.i0}; };
-    G.p = &p; G.Kl = nullptr; G.Kg = p.K; G.nw = nw; G.ldl = ldl; G.i0 = c.i0;
+    G.p = &p; G.Kl = nullptr; G.Kg = p.K; G.ks = ks; G.nw = nw; G.ldl = ldl; G.i0 = c.i0;
     G.alpha = g(p.alpha); G.ca = g(p.ca); G.cb = g(p.cb); G.drC = g(p.drC);
     G.dc = g(p.dc); G.arisk = g(p.arisk); G.cvec = g(p.cvec); G.w0 = g(p.w0);
     G.wT = g(p.wT ? p.wT : p.w0);
@@ -709,13 +784,19 @@ __global__ __launch_bounds__(TB) void k_solve(DevProblem p, DevState s, DevContr
   c.tot = tot;
   c.red = red;
   c.flag = iflag;
+  c.lslot = lslot;
   V.Kl = Kl;
   V.Kg = p.K;
+  V.ks = ks;
 
+  for (int j = c.tid; j < nr; j += TB) ks[j] = p.kscaled ? 1.0 : p.dr[j];
+  if (lslot)
+    for (int e = c.tid; e < 3 * ctl.vmax; e += TB) lslot[e] = 0.0;
+  __syncthreads();
   if (KL) {
     for (int e = c.tid; e < nr * nw; e += TB) {
       const int j = e / nw, li = e % nw;
-      Kl[j * ldl + li] = li < c.nwa ? p.K[(size_t)j * p.ldk + c.i0 + li] : 0.0;
+      Kl[j * ldl + li] = li < c.nwa ? p.K[(size_t)j * p.ldk + c.i0 + li] * ks[j] : 0.0;
     }
   }
   if (SL) {
@@ -1258,6 +1339,21 @@ barrier_fail:
   return;
 }
 
+template <bool KL, bool SL, class R>
+__global__ __launch_bounds__(TB) void k_solve(DevProblem p, DevState s, DevControl ctl) {
+  solve_body<KL, SL, R>(p, s, ctl, blockIdx.x, gridDim.x);
+}
+
+// Batched: every team solves its own instance; teams never wait for each other.
+template <bool KL, bool SL, class R>
+__global__ __launch_bounds__(TB) void k_solve_batch(const DevProblem* __restrict__ dp, const DevState* __restrict__ ds,
+                                                    const DevControl* __restrict__ dcl, const int* __restrict__ wg_team,
+                                                    const int* __restrict__ wg_rank) {
+  const int team = wg_team[blockIdx.x];
+  const DevControl ctl = dcl[team];
+  solve_body<KL, SL, R>(dp[team], ds[team], ctl, wg_rank[blockIdx.x], ctl.nwg);
+}
+
 }  // namespace
 
 int solve_vmax(const DevProblem& p) {
@@ -1282,7 +1378,8 @@ size_t solve_lds_bytes(const DevProblem& p, const DevControl& c) {
   const bool f32 = c.prec == PREC_FP32;
   size_t d = 0;
   if (c.lds_k) d += f32 ? lds_doubles<float>(nr * (nw | 1)) : lds_doubles<double>(nr * (nw | 1));
-  d += 4 * P * nr + 4 * P * nw + (size_t)c.vmax + RED_LEN + 14 * P;
+  d += 4 * P * nr + 4 * P * nw + (size_t)c.vmax + RED_LEN + 14 * P + nr;
+  if (c.xmode == XM_LOCAL) d += 3 * (size_t)c.vmax;
   if (c.lds_state) d += f32 ? state_lds_doubles<float>(P, Tp, nw) : state_lds_doubles<double>(P, Tp, nw);
   d += (sizeof(Scal) + 7) / 8 + 2 + (P + 1) / 2 + 1;
   return d * sizeof(double);
@@ -1299,6 +1396,28 @@ int launch_solve(const DevProblem& p, const DevState& s, const DevControl& c, vo
                  : (c.lds_state ? (const void*)k_solve<false, true, double> : (const void*)k_solve<false, false, double>);
   hipError_t e = hipLaunchCooperativeKernel(fn, dim3(c.nwg), dim3(TB), args, (unsigned int)lds, (hipStream_t)stream);
   return e == hipSuccess ? 0 : (int)e;
+}
+
+static const void* batch_fn(int kl, int sl, int prec) {
+  if (prec == PREC_FP32)
+    return kl ? (sl ? (const void*)k_solve_batch<true, true, float> : (const void*)k_solve_batch<true, false, float>)
+              : (sl ? (const void*)k_solve_batch<false, true, float> : (const void*)k_solve_batch<false, false, float>);
+  return kl ? (sl ? (const void*)k_solve_batch<true, true, double> : (const void*)k_solve_batch<true, false, double>)
+            : (sl ? (const void*)k_solve_batch<false, true, double> : (const void*)k_solve_batch<false, false, double>);
+}
+
+int launch_solve_batch(const DevProblem* dp, const DevState* ds, const DevControl* dc, const int* wg_team,
+                       const int* wg_rank, int nblocks, int kl, int sl, int prec, void* stream, size_t lds) {
+  void* args[] = {(void*)&dp, (void*)&ds, (void*)&dc, (void*)&wg_team, (void*)&wg_rank};
+  hipError_t e = hipLaunchCooperativeKernel(batch_fn(kl, sl, prec), dim3(nblocks), dim3(TB), args,
+                                            (unsigned int)lds, (hipStream_t)stream);
+  return e == hipSuccess ? 0 : (int)e;
+}
+
+int solve_batch_occupancy(int kl, int sl, int prec, size_t lds) {
+  int blocks = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, batch_fn(kl, sl, prec), TB, lds) != hipSuccess) return 0;
+  return blocks;
 }
 
 }  // namespace ffo

@@ -20,6 +20,7 @@ from .markets import (  # noqa: F401
     make_single,
     make_multi,
     make_batch,
+    batch_instance,
     ushape_profile_inputs,
     make_tiny,
 )

@@ -26,7 +26,7 @@ import math
 
 import numpy as np
 
-__all__ = ["CONFIGS", "make_config", "make_single", "make_multi", "make_batch",
+__all__ = ["CONFIGS", "make_config", "make_single", "make_multi", "make_batch", "batch_instance",
            "ushape_profile_inputs", "make_tiny"]
 
 # Sizes of the five standard workloads (see make_config).
@@ -156,6 +156,20 @@ def make_batch(B: int, k: int, m: int, seed: int, n_lo: int = 500, n_hi: int = 8
     out = dict(B=B, n_b=n_b, offs=offs, n_max=n_max, k=k, m=m, F=F, Omega=Omega, delta=delta,
                A=A, sector=sector, alpha=alpha, s=s, q=q, w0=w0, L=L, U=U, seed=seed, **_SCALARS)
     out.update(overrides)
+    return _contig(out)
+
+
+def batch_instance(batch: dict, b: int) -> dict:
+    """Instance b of a batch as a single-period instance dict (its prefix of the shared
+    universe and its slice of the packed vectors)."""
+    nb = int(batch["n_b"][b])
+    lo, hi = int(batch["offs"][b]), int(batch["offs"][b + 1])
+    out = dict(n=nb, k=batch["k"], m=batch["m"], T=0, F=batch["F"][:nb], Omega=batch["Omega"],
+               delta=batch["delta"][:nb], A=batch["A"][:, :nb], alpha=batch["alpha"][lo:hi][None, :],
+               s=batch["s"][lo:hi][None, :], q=batch["q"][lo:hi][None, :], w0=batch["w0"][lo:hi],
+               L=batch["L"][b], U=batch["U"][b], w_target=None, seed=batch["seed"])
+    for key in ("d", "GMV", "lambda1", "lambda2", "lambda3"):
+        out[key] = batch[key]
     return _contig(out)
 
 

@@ -90,3 +90,45 @@ def test_invalid_options_rejected_on_host():
 
 def test_version_string():
     assert b"gfx950" in ff.lib().ffo_version()
+
+
+def _call_batched(B=3, n_b=(5, 7, 9), n_max=10, k=2, m=1, offs=None, d=1.5, precision=0, null=()):
+    """ffo_solve_batched with fake device pointers and real host arrays; invalid
+    arguments must be rejected before any device pointer is touched."""
+    import numpy as np
+    fake = ctypes.c_void_p(0x1000)
+    nb = np.ascontiguousarray(np.asarray(n_b, dtype=np.int64))
+    of = np.concatenate([[0], np.cumsum(nb)]).astype(np.int64) if offs is None else np.asarray(offs, np.int64)
+    of = np.ascontiguousarray(of)
+    ptr = {name: (None if name in null else fake) for name in
+           ("F", "Omega", "delta", "A", "alpha", "s", "q", "w0", "L", "U", "w_out")}
+    infos = (ff._Info * max(B, 1))()
+    o = ff.default_options()
+    o.precision = precision
+    lib = ff.lib()
+    rc = lib.ffo_solve_batched(B, nb.ctypes.data_as(ctypes.c_void_p), n_max, k, m, ptr["F"], ptr["Omega"],
+                               ptr["delta"], ptr["A"], of.ctypes.data_as(ctypes.c_void_p), ptr["alpha"], ptr["s"],
+                               ptr["q"], ptr["w0"], ptr["L"], ptr["U"], d, 1e9, 1e-9, 1.0, 1.0, ctypes.byref(o),
+                               None, ptr["w_out"], infos)
+    return rc, lib.ffo_last_error().decode()
+
+
+@pytest.mark.parametrize("kw,needle", [
+    (dict(B=0, n_b=()), "B must"),
+    (dict(n_b=(5, 11, 9)), "n_b"),
+    (dict(n_b=(0, 7, 9)), "n_b"),
+    (dict(offs=(0, 5, 13, 21)), "offs"),
+    (dict(offs=(1, 6, 13, 22)), "offs[0]"),
+    (dict(k=129), "k must"),
+    (dict(m=-1), "m must"),
+    (dict(d=1.0), "d must"),
+    (dict(precision=2), "FFO_FP64 or FFO_FP32"),
+    (dict(null=("alpha",)), "null"),
+    (dict(null=("w_out",)), "null"),
+    (dict(null=("F",)), "F and Omega"),
+    (dict(null=("L",)), "A, L and U"),
+])
+def test_batched_rejects_invalid_arguments(kw, needle):
+    rc, msg = _call_batched(**kw)
+    assert rc == 1, (rc, msg)
+    assert needle in msg, msg

@@ -1,0 +1,117 @@
+"""GPU parity of the batched form (ffo_solve_batched): every instance of a batch on one
+shared universe against the FP64 oracle on that instance alone, and against the plain
+single-instance solver.  Teams of one workgroup exchange through LDS; larger instances
+get teams of several workgroups (device-scope exchange), so both paths are covered."""
+import numpy as np
+import pytest
+
+import oracle
+from oracle.problem import normalize, objective
+from synth import make_batch, batch_instance, make_config
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2604_22625_amd as ff
+    return ff
+
+
+def _solve_batched(batch, **kw):
+    ff = _gpu()
+    print(f"[case] batched B={len(batch['n_b'])} n_b={list(batch['n_b'])[:8]} kw={kw}", flush=True)
+    kw.setdefault("time_limit_s", 60.0)
+    kw.setdefault("max_iter", 200000)
+    W, infos = ff.solve_batched(batch, **kw)
+    torch.cuda.synchronize()
+    return W.cpu().numpy(), infos
+
+
+def _check_against_oracle(batch, W, infos, b, tol, w_tol, obj_tol):
+    inst = batch_instance(batch, b)
+    lo, hi = int(batch["offs"][b]), int(batch["offs"][b + 1])
+    wb = W[lo:hi][None, :]
+    info = infos[b]
+    assert info.status == 0 and info.rel_kkt <= tol, info
+    ref = oracle.solve(inst, tol=1e-10)
+    pb = normalize(inst)
+    assert np.max(np.abs(wb - ref.W)) <= w_tol, (b, np.max(np.abs(wb - ref.W)))
+    assert abs(objective(pb, wb) - ref.phi) <= obj_tol * abs(ref.phi)
+    assert abs(objective(pb, wb) - info.primal_obj) <= 1e-12 * abs(info.primal_obj)
+
+
+# The weights follow the objective gap only through strong convexity, whose modulus
+# here is 2*lambda1*GMV*min(delta^2) ~ 2e-4 with only 4 factors: at relative KKT 2e-7 one
+# weight of a 694-asset instance is still 1.6e-5 off, and 1.1e-5 at 1e-9 (the oracle's own
+# certificate bounds its W to ~1e-6).  The bars |W - W*|_inf <= 1e-5 and relative
+# objective <= 1e-6 are therefore asserted on FP64 solves to relative KKT 1e-10; the FP32
+# form, whose float copies of the data put a floor near 1e-7 on the true KKT, is held to
+# 2e-5 at 1e-7.
+BARS = {"fp64": (1e-10, 1e-5), "fp32": (1e-7, 2e-5)}
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_small_batch_matches_oracle(precision):
+    tol, w_tol = BARS[precision]
+    batch = make_batch(8, 4, 6, seed=3, n_lo=40, n_hi=700)
+    W, infos = _solve_batched(batch, tol=tol, precision=precision)
+    for b in range(8):
+        _check_against_oracle(batch, W, infos, b, tol, w_tol=w_tol, obj_tol=1e-6)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_multi_workgroup_teams_match_oracle(precision):
+    # n_b >= 512 is split over several workgroups when spare ones exist
+    tol, w_tol = BARS[precision]
+    batch = make_batch(3, 4, 6, seed=5, n_lo=900, n_hi=2600, n_max=2600)
+    W, infos = _solve_batched(batch, tol=tol, precision=precision)
+    for b in range(3):
+        _check_against_oracle(batch, W, infos, b, tol, w_tol=w_tol, obj_tol=1e-6)
+
+
+def test_batched_agrees_with_plain_solver():
+    ff = _gpu()
+    batch = make_batch(5, 4, 6, seed=9, n_lo=100, n_hi=3000, n_max=3000)
+    W, infos = _solve_batched(batch, tol=1e-9)
+    for b in range(5):
+        inst = batch_instance(batch, b)
+        Wp, ip = ff.solve_instance(inst, tol=1e-9)
+        lo, hi = int(batch["offs"][b]), int(batch["offs"][b + 1])
+        assert infos[b].status == 0 and ip.status == 0
+        assert np.max(np.abs(W[lo:hi] - Wp.cpu().numpy()[0])) <= 1e-5
+
+
+def test_single_asset_and_tiny_instances():
+    batch = make_batch(4, 2, 1, seed=11, n_lo=1, n_hi=6, n_max=6)
+    W, infos = _solve_batched(batch, tol=1e-9)
+    for b in range(4):
+        _check_against_oracle(batch, W, infos, b, 1e-9, w_tol=1e-5, obj_tol=1e-8)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_full_batch_256(precision):
+    """The 256-instance batch (n_b log-uniform in [500, 8000], k = 40, m = 30): every
+    instance converges; the three smallest against the oracle, the three largest against
+    the plain solver."""
+    ff = _gpu()
+    batch = make_config(3)
+    W, infos = _solve_batched(batch, tol=1e-6, precision=precision)
+    assert all(i.status == 0 and i.rel_kkt <= 1e-6 for i in infos)
+    nb = np.asarray(batch["n_b"])
+    for b in range(len(nb)):
+        lo, hi = int(batch["offs"][b]), int(batch["offs"][b + 1])
+        assert np.abs(W[lo:hi]).sum() <= 1.0 + 1e-5
+    order = np.argsort(nb)
+    for b in order[:3]:
+        _check_against_oracle(batch, W, infos, int(b), 1e-6, w_tol=2e-5, obj_tol=2e-6)
+    for b in order[-3:]:
+        inst = batch_instance(batch, int(b))
+        Wp, ip = ff.solve_instance(inst, tol=1e-6)
+        lo, hi = int(batch["offs"][b]), int(batch["offs"][b + 1])
+        pb = normalize(inst)
+        # two solves to relative KKT 1e-6 of the same instance: objectives within 4e-6
+        assert abs(objective(pb, W[lo:hi][None, :]) - objective(pb, Wp.cpu().numpy())) <= 4e-6 * abs(ip.primal_obj)
