@@ -135,6 +135,32 @@ ffo_status ffo_solve(int64_t n, int64_t k, int64_t m, int64_t T,
                      double* w_out, double* y_out, ffo_info* info);
 
 /*
+ * Adjoint form: gradients of a loss l(W*) of the solution with respect to the expected
+ * returns, the spread coefficients and the factor loadings (A, L, U, Omega, delta, q
+ * held fixed).  The problem arguments are those of the ffo_solve call that produced
+ *   w_star [P][n] and y_star [P*m + P*k + T'*n]   (its w_out and y_out, device)
+ * and grad_w [P][n] = dl/dW* (device).  omega: the solve's final primal weight
+ * (ffo_info.omega; 0 selects 1), a conditioning hint only.  Outputs (device,
+ * caller-allocated): grad_alpha [P][n], grad_s [T'][n], grad_F [n][k] (may be NULL iff
+ * k == 0).  Method: the solution is a fixed point z* = T(z*) of the iteration; with
+ * J = dT/dz at z* (every nonsmooth piece frozen as T(z*) finds it: budget supports,
+ * clipped exposure rows, the spread dead zones) the adjoint lambda = J^T lambda + g,
+ * g = (dl/dz*, 0), is solved by the same restarted reflected Halpern iteration, and the
+ * gradients are lambda^T dT/dtheta.  opt->tol_rel_kkt is the relative residual
+ * ||J^T lambda + g - lambda|| / ||g|| to reach (default 1e-9 when opt is NULL);
+ * opt->precision must be FFO_FP64.  Statuses as in ffo_solve (FFO_NOT_CONVERGED: the
+ * gradients hold the last iterate's values).
+ */
+ffo_status ffo_adjoint(int64_t n, int64_t k, int64_t m, int64_t T,
+                       const double* alpha, const double* F, const double* Omega,
+                       const double* delta, const double* s, const double* q, double d,
+                       const double* A, const double* L, const double* U, const double* w0,
+                       double GMV, double lambda1, double lambda2, double lambda3,
+                       const double* w_target, const double* w_star, const double* y_star,
+                       const double* grad_w, double omega, const ffo_options* opt, void* stream,
+                       double* grad_alpha, double* grad_s, double* grad_F, ffo_info* info);
+
+/*
  * Batched form: B independent single-period instances (paper eq. 1-3) that share one
  * asset universe of n_max assets; instance b uses assets [0, n_b[b]).  Shared (device):
  *   F [n_max][k], Omega [k][k], delta [n_max], A [m][n_max]

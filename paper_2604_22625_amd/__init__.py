@@ -13,7 +13,8 @@ from dataclasses import dataclass, asdict
 
 import numpy as np
 
-__all__ = ["solve", "solve_instance", "solve_batched", "Info", "FolioError", "lib", "LIB_PATH", "STATUS"]
+__all__ = ["solve", "solve_instance", "solve_batched", "adjoint", "FolioFn", "Info", "FolioError", "lib",
+           "LIB_PATH", "STATUS"]
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libffolio.so")
 
@@ -86,6 +87,10 @@ def lib() -> ctypes.CDLL:
         L.ffo_solve_batched.argtypes = [_I64, _P, _I64, _I64, _I64, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P,
                                         _D, _D, _D, _D, _D, ctypes.POINTER(_Options), _P, _P, _P]
         L.ffo_solve_batched.restype = ctypes.c_int
+        L.ffo_adjoint.argtypes = [_I64, _I64, _I64, _I64, _P, _P, _P, _P, _P, _P, _D, _P, _P, _P, _P,
+                                  _D, _D, _D, _D, _P, _P, _P, _P, _D, ctypes.POINTER(_Options), _P, _P, _P, _P,
+                                  ctypes.POINTER(_Info)]
+        L.ffo_adjoint.restype = ctypes.c_int
         L.ffo_last_error.argtypes = []
         L.ffo_last_error.restype = ctypes.c_char_p
         L.ffo_release.argtypes = []
@@ -250,3 +255,106 @@ def solve_batched(batch: dict, *, tol: float = 1e-6, max_iter: int = 1_000_000, 
     if rc == 1 or (rc in (2, 3)) or (rc != 0 and raise_on_failure):
         raise FolioError(rc, lib().ffo_last_error().decode())
     return W, out_infos
+
+
+def adjoint(inst: dict, W, Y, grad_w, *, omega: float = 0.0, tol: float = 1e-9, max_iter: int = 1_000_000,
+            time_limit_s: float = 360.0, check_every: int = 64, verbose: int = 0, raise_on_failure: bool = True,
+            device=None, stream=None):
+    """Gradients of l(W*) with respect to alpha, s and F (ffo_adjoint).
+
+    ``inst``: the instance dict the solve ran on; ``W``: its solution [P][n]; ``Y``: its
+    duals as returned by ``solve(..., return_dual=True)`` (tuple yA, yF, yC) or the packed
+    vector; ``grad_w``: dl/dW [P][n].  Returns (grad_alpha [P][n], grad_s [T'][n],
+    grad_F [n][k], Info), float64 CUDA tensors."""
+    torch = _torch()
+    if not torch.cuda.is_available():
+        raise FolioError(3, "no GPU visible to PyTorch: the solver has no CPU path")
+    dev = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
+    T = int(inst.get("T", 0) or 0)
+    a = _dev_f64(inst["alpha"], dev)
+    if a.dim() == 1:
+        a = a[None, :]
+    n = a.shape[1]
+    P = 1 if T == 0 else T - 1
+    Tp = 1 if T == 0 else T
+    Fd = _dev_f64(inst["F"], dev).reshape(n, -1)
+    k = Fd.shape[1]
+    Od = _dev_f64(inst["Omega"], dev).reshape(k, k) if k else None
+    Ad = _dev_f64(inst["A"], dev)
+    Ad = Ad.reshape(-1, n) if Ad is not None and Ad.numel() else None
+    m = 0 if Ad is None else Ad.shape[0]
+    sd = _dev_f64(inst["s"], dev).reshape(-1, n)
+    qd = _dev_f64(inst["q"], dev).reshape(-1, n)
+    Ld = _dev_f64(inst["L"], dev).reshape(m) if m else None
+    Ud = _dev_f64(inst["U"], dev).reshape(m) if m else None
+    dd = _dev_f64(inst["delta"], dev).reshape(n)
+    w0d = _dev_f64(inst["w0"], dev).reshape(n)
+    wTd = _dev_f64(inst["w_target"], dev).reshape(n) if T else None
+    Wd = _dev_f64(W, dev).reshape(P, n)
+    if isinstance(Y, (tuple, list)):
+        Yd = torch.cat([_dev_f64(y, dev).reshape(-1) for y in Y])
+    else:
+        Yd = _dev_f64(Y, dev).reshape(-1)
+    gw = _dev_f64(grad_w, dev).reshape(P, n)
+    g_a = torch.empty((P, n), dtype=torch.float64, device=dev)
+    g_s = torch.empty((Tp, n), dtype=torch.float64, device=dev)
+    g_F = torch.empty((n, k), dtype=torch.float64, device=dev)
+    o = default_options()
+    o.tol_rel_kkt = float(tol)
+    o.max_iter = int(max_iter)
+    o.time_limit_s = float(time_limit_s)
+    o.check_every = int(check_every)
+    o.verbose = int(verbose)
+    info = _Info()
+    st = torch.cuda.current_stream(dev) if stream is None else stream
+    with torch.cuda.device(dev):
+        rc = lib().ffo_adjoint(n, k, m, T, _ptr(a), _ptr(Fd if k else None), _ptr(Od), _ptr(dd), _ptr(sd),
+                               _ptr(qd), float(inst["d"]), _ptr(Ad), _ptr(Ld), _ptr(Ud), _ptr(w0d),
+                               float(inst["GMV"]), float(inst["lambda1"]), float(inst["lambda2"]),
+                               float(inst["lambda3"]), _ptr(wTd), _ptr(Wd), _ptr(Yd), _ptr(gw), float(omega),
+                               ctypes.byref(o), ctypes.c_void_p(st.cuda_stream), _ptr(g_a), _ptr(g_s),
+                               _ptr(g_F if k else None), ctypes.byref(info))
+    inf = Info(**{f[0]: getattr(info, f[0]) for f in _Info._fields_})
+    if rc == 1 or (rc in (2, 3)) or (rc != 0 and raise_on_failure):
+        raise FolioError(rc, lib().ffo_last_error().decode())
+    return g_a, g_s, g_F, inf
+
+
+def _folio_fn():
+    torch = _torch()
+
+    class _FolioFn(torch.autograd.Function):
+        """W* = solve(alpha, s, F; rest) with gradients from the device adjoint.
+
+        forward(alpha [P][n], s [T'][n], F [n][k], rest: dict of the other instance
+        fields, opts: dict of solve keywords) -> W [P][n] (float64 CUDA)."""
+
+        @staticmethod
+        def forward(ctx, alpha, s, F, rest, opts):
+            inst = dict(rest)
+            inst["alpha"], inst["s"], inst["F"] = alpha.detach(), s.detach(), F.detach()
+            W, info, Y = solve_instance(inst, return_dual=True, **(opts or {}))
+            ctx.inst = inst
+            ctx.omega = info.omega
+            ctx.save_for_backward(W, torch.cat([y.reshape(-1) for y in Y]))
+            return W
+
+        @staticmethod
+        def backward(ctx, grad_W):
+            W, Y = ctx.saved_tensors
+            g_a, g_s, g_F, _ = adjoint(ctx.inst, W, Y, grad_W.contiguous(), omega=ctx.omega)
+            return g_a, g_s, g_F, None, None
+
+    return _FolioFn
+
+
+class _LazyFn:
+    _fn = None
+
+    def apply(self, *args):
+        if _LazyFn._fn is None:
+            _LazyFn._fn = _folio_fn()
+        return _LazyFn._fn.apply(*args)
+
+
+FolioFn = _LazyFn()

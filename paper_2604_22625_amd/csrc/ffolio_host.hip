@@ -185,6 +185,40 @@ __global__ void k_validate_packed(int64_t N, int64_t Bm, const double* alpha, co
 
 size_t align_up(size_t x) { return (x + 255) / 256 * 256; }
 
+// Host-only checks of the problem arguments shared by ffo_solve and ffo_adjoint.
+ffo_status check_problem_args(int64_t n, int64_t k, int64_t m, int64_t T, const double* alpha, const double* F,
+                              const double* Omega, const double* delta, const double* s, const double* q, double d,
+                              const double* A, const double* L, const double* U, const double* w0, double GMV,
+                              double lambda1, double lambda2, double lambda3, const double* w_target) {
+  if (n < 1) return fail(FFO_EINVAL, "n must be >= 1");
+  if (k < 0 || k > 128) return fail(FFO_EINVAL, "k must lie in [0, 128]");
+  if (m < 0 || m > 4096) return fail(FFO_EINVAL, "m must lie in [0, 4096]");
+  if (!(T == 0 || T >= 2)) return fail(FFO_EINVAL, "T must be 0 (single-period) or >= 2");
+  if (T > 4096) return fail(FFO_EINVAL, "T must be <= 4096");
+  const int64_t Tp = T == 0 ? 1 : T;
+  if (n * Tp > (int64_t)1 << 30) return fail(FFO_EINVAL, "n * T too large");
+  if (!alpha || !delta || !s || !q || !w0) return fail(FFO_EINVAL, "null array pointer");
+  if (k > 0 && (!F || !Omega)) return fail(FFO_EINVAL, "F and Omega must be non-null when k > 0");
+  if (m > 0 && (!A || !L || !U)) return fail(FFO_EINVAL, "A, L and U must be non-null when m > 0");
+  if ((T == 0) != (w_target == nullptr)) return fail(FFO_EINVAL, "w_target must be NULL iff T == 0");
+  if (!(d > 1.0 && d <= 2.0)) return fail(FFO_EINVAL, "d must lie in (1, 2]");
+  if (!(GMV > 0.0) || !std::isfinite(GMV)) return fail(FFO_EINVAL, "GMV must be positive and finite");
+  if (!(lambda1 > 0.0) || !std::isfinite(lambda1)) return fail(FFO_EINVAL, "lambda1 must be positive and finite");
+  if (!(lambda2 >= 0.0) || !(lambda3 >= 0.0) || !std::isfinite(lambda2) || !std::isfinite(lambda3))
+    return fail(FFO_EINVAL, "lambda2 and lambda3 must be nonnegative and finite");
+  return FFO_OK;
+}
+
+ffo_status check_options(const ffo_options& opt) {
+  if (!(opt.tol_rel_kkt > 0.0)) return fail(FFO_EINVAL, "tol_rel_kkt must be positive");
+  if (opt.max_iter < 1) return fail(FFO_EINVAL, "max_iter must be >= 1");
+  if (opt.check_every < 1) return fail(FFO_EINVAL, "check_every must be >= 1");
+  if (!(opt.time_limit_s > 0.0)) return fail(FFO_EINVAL, "time_limit_s must be positive");
+  if (!(opt.reflection >= 0.0 && opt.reflection <= 1.0)) return fail(FFO_EINVAL, "reflection must lie in [0, 1]");
+  if (opt.workgroups < 0 || opt.workgroups > 4096) return fail(FFO_EINVAL, "workgroups must lie in [0, 4096]");
+  return FFO_OK;
+}
+
 std::string bad_values(int flag) {
   std::string why;
   if (flag & 1) why += " alpha not finite;";
@@ -266,30 +300,14 @@ ffo_status ffo_solve(int64_t n, int64_t k, int64_t m, int64_t T, const double* a
   ffo_default_options(&opt);
   if (opt_in) opt = *opt_in;
   // ---- host-only validation (no device work before this point) ----
-  if (n < 1) return fail(FFO_EINVAL, "n must be >= 1");
-  if (k < 0 || k > 128) return fail(FFO_EINVAL, "k must lie in [0, 128]");
-  if (m < 0 || m > 4096) return fail(FFO_EINVAL, "m must lie in [0, 4096]");
-  if (!(T == 0 || T >= 2)) return fail(FFO_EINVAL, "T must be 0 (single-period) or >= 2");
-  if (T > 4096) return fail(FFO_EINVAL, "T must be <= 4096");
-  const int64_t P = T == 0 ? 1 : T - 1, Tp = T == 0 ? 1 : T;
-  if (n * Tp > (int64_t)1 << 30) return fail(FFO_EINVAL, "n * T too large");
-  if (!alpha || !delta || !s || !q || !w0 || !w_out) return fail(FFO_EINVAL, "null array pointer");
-  if (k > 0 && (!F || !Omega)) return fail(FFO_EINVAL, "F and Omega must be non-null when k > 0");
-  if (m > 0 && (!A || !L || !U)) return fail(FFO_EINVAL, "A, L and U must be non-null when m > 0");
-  if ((T == 0) != (w_target == nullptr)) return fail(FFO_EINVAL, "w_target must be NULL iff T == 0");
-  if (!(d > 1.0 && d <= 2.0)) return fail(FFO_EINVAL, "d must lie in (1, 2]");
-  if (!(GMV > 0.0) || !std::isfinite(GMV)) return fail(FFO_EINVAL, "GMV must be positive and finite");
-  if (!(lambda1 > 0.0) || !std::isfinite(lambda1)) return fail(FFO_EINVAL, "lambda1 must be positive and finite");
-  if (!(lambda2 >= 0.0) || !(lambda3 >= 0.0) || !std::isfinite(lambda2) || !std::isfinite(lambda3))
-    return fail(FFO_EINVAL, "lambda2 and lambda3 must be nonnegative and finite");
-  if (!(opt.tol_rel_kkt > 0.0)) return fail(FFO_EINVAL, "tol_rel_kkt must be positive");
-  if (opt.max_iter < 1) return fail(FFO_EINVAL, "max_iter must be >= 1");
-  if (opt.check_every < 1) return fail(FFO_EINVAL, "check_every must be >= 1");
-  if (!(opt.time_limit_s > 0.0)) return fail(FFO_EINVAL, "time_limit_s must be positive");
-  if (!(opt.reflection >= 0.0 && opt.reflection <= 1.0)) return fail(FFO_EINVAL, "reflection must lie in [0, 1]");
+  if (ffo_status st = check_problem_args(n, k, m, T, alpha, F, Omega, delta, s, q, d, A, L, U, w0, GMV, lambda1,
+                                         lambda2, lambda3, w_target))
+    return st;
+  if (!w_out) return fail(FFO_EINVAL, "null array pointer");
+  if (ffo_status st = check_options(opt)) return st;
   if (opt.precision != FFO_FP64 && opt.precision != FFO_FP32)
     return fail(FFO_EINVAL, "ffo_solve takes FFO_FP64 or FFO_FP32");
-  if (opt.workgroups < 0 || opt.workgroups > 4096) return fail(FFO_EINVAL, "workgroups must lie in [0, 4096]");
+  const int64_t P = T == 0 ? 1 : T - 1, Tp = T == 0 ? 1 : T;
 
   int dev = 0;
   HIPCHK(hipGetDevice(&dev));
@@ -392,7 +410,7 @@ ffo_status ffo_solve(int64_t n, int64_t k, int64_t m, int64_t T, const double* a
     return fail(FFO_EDEVICE, "setup kernel launch failed");
   p.K = D(oK); p.dr = D(odr); p.dc = D(odc); p.drC = D(odrC); p.alpha = alpha; p.arisk = D(oar);
   p.cvec = D(ocv); p.ca = D(oca); p.cb = D(ocb); p.w0 = w0; p.wT = w_target; p.L = L; p.U = U;
-  p.bF = D(obF); p.g1 = g1; p.d = d;
+  p.bF = D(obF); p.g1 = g1; p.d = d; p.g2 = g2;
   p.crisk = D(ocr);
 
   ffo::DevState sv{};
@@ -457,6 +475,146 @@ ffo_status ffo_solve(int64_t n, int64_t k, int64_t m, int64_t T, const double* a
                  hinfo[ffo::IX_T_PRE] * 1e3, hinfo[ffo::IX_T_READ] * 1e3, hinfo[ffo::IX_T_B1] * 1e3,
                  hinfo[ffo::IX_T_B1S] * 1e3, hinfo[ffo::IX_T_B2] * 1e3, hinfo[ffo::IX_T_B3] * 1e3,
                  hinfo[ffo::IX_MISS_IN], hinfo[ffo::IX_MISS_OUT]);
+  return st;
+}
+
+ffo_status ffo_adjoint(int64_t n, int64_t k, int64_t m, int64_t T, const double* alpha, const double* F,
+                       const double* Omega, const double* delta, const double* s, const double* q, double d,
+                       const double* A, const double* L, const double* U, const double* w0, double GMV,
+                       double lambda1, double lambda2, double lambda3, const double* w_target,
+                       const double* w_star, const double* y_star, const double* grad_w, double omega,
+                       const ffo_options* opt_in, void* stream, double* grad_alpha, double* grad_s,
+                       double* grad_F, ffo_info* info) {
+  g_err.clear();
+  ffo_options opt;
+  ffo_default_options(&opt);
+  opt.tol_rel_kkt = 1e-9;
+  if (opt_in) opt = *opt_in;
+  // ---- host-only validation ----
+  if (ffo_status st = check_problem_args(n, k, m, T, alpha, F, Omega, delta, s, q, d, A, L, U, w0, GMV, lambda1,
+                                         lambda2, lambda3, w_target))
+    return st;
+  if (!w_star || !y_star || !grad_w || !grad_alpha || !grad_s) return fail(FFO_EINVAL, "null array pointer");
+  if (k > 0 && !grad_F) return fail(FFO_EINVAL, "grad_F must be non-null when k > 0");
+  if (ffo_status st = check_options(opt)) return st;
+  if (opt.precision != FFO_FP64) return fail(FFO_EINVAL, "ffo_adjoint runs in FFO_FP64");
+  if (!(omega >= 0.0) || !std::isfinite(omega)) return fail(FFO_EINVAL, "omega must be finite and >= 0 (0: default)");
+  const int64_t P = T == 0 ? 1 : T - 1, Tp = T == 0 ? 1 : T;
+
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  hipDeviceProp_t prop;
+  HIPCHK(hipGetDeviceProperties(&prop, dev));
+  int wall_khz = 0;
+  if (hipDeviceGetAttribute(&wall_khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess || wall_khz <= 0)
+    wall_khz = 100000;
+  const int nr = (int)(m + k);
+  const int ldk = (int)((n + 63) / 64 * 64);
+  ffo::DevProblem p{};
+  p.n = (int)n; p.k = (int)k; p.m = (int)m; p.P = (int)P; p.Tp = (int)Tp; p.nr = nr;
+  p.multi = T > 0 ? 1 : 0; p.ldk = ldk; p.kscaled = 1;
+  const int cus = std::max(1, prop.multiProcessorCount);
+  int nwg = opt.workgroups > 0 ? opt.workgroups : (int)std::min<int64_t>(cus, (n + 63) / 64);
+  nwg = std::max(1, std::min<int>(nwg, (int)n));
+  nwg = std::min(nwg, cus);
+  const int nw = (int)((n + nwg - 1) / nwg);
+  nwg = (int)((n + nw - 1) / nw);
+  ffo::DevControl c{};
+  c.tol = opt.tol_rel_kkt; c.time_limit_s = opt.time_limit_s;
+  c.r_suff = opt.restart_suff; c.r_nec = opt.restart_nec; c.r_art = opt.restart_art;
+  c.rho = opt.reflection; c.eta_safety = 0.95; c.max_iter = opt.max_iter;
+  c.check_every = opt.check_every; c.xmode = ffo::XM_ATOMIC; c.nwg = nwg; c.npow = 40;
+  c.verbose = opt.verbose; c.nw = nw; c.spin_limit = 1u << 26; c.wall_hz = (double)wall_khz * 1e3;
+  c.prec = ffo::PREC_FP64; c.spec = 0; c.lds_state = 0;
+  c.vmax = ffo::adjoint_vmax(p);
+  const size_t lds_cap = (size_t)std::min<size_t>(prop.sharedMemPerBlock, 160 * 1024);
+  c.lds_k = 1;
+  size_t lds = ffo::adjoint_lds_bytes(p, c);
+  if (lds > lds_cap) {
+    c.lds_k = 0;
+    lds = ffo::adjoint_lds_bytes(p, c);
+    if (lds > lds_cap) return fail(FFO_EINVAL, "problem too large for the per-workgroup working set (reduce m + k or T)");
+  }
+  // ---- workspace layout ----
+  const size_t Pn = (size_t)P * n, Tpn = (size_t)Tp * n;
+  size_t off = 0;
+  auto carve = [&](size_t cnt, size_t elt) { const size_t o = off; off = align_up(off + cnt * elt); return o; };
+  const size_t oK = carve((size_t)std::max(nr, 1) * ldk, 8), odr = carve(std::max(nr, 1), 8), odc = carve(n, 8);
+  const size_t odrC = carve(Tpn, 8), oar = carve(n, 8), ocv = carve(n, 8), oca = carve(Tpn, 8), ocb = carve(Tpn, 8);
+  const size_t obF = carve(std::max<int64_t>(k, 1), 8), ocr = carve(1, 8), oC = carve(std::max<int64_t>(k * k, 1), 8);
+  size_t ost[7];
+  for (auto& o : ost) o = carve(Pn, 8);
+  size_t osc[6];
+  for (auto& o : osc) o = carve(Tpn, 8);
+  const size_t ogG = carve((size_t)n * std::max<int64_t>(k, 1), 8);
+  const size_t oxb = carve((size_t)3 * c.vmax, 8), obar = carve(1, 8);
+  const size_t oinfo = carve(ffo::INFO_LEN, 8), ostat = carve(1, 4), oflag = carve(1, 4);
+  const size_t total = off;
+  const size_t hk = align_up((size_t)std::max<int64_t>(k * k, 1) * 8);
+  const size_t host_bytes = 2 * hk + align_up(ffo::INFO_LEN * 8) + 4096;
+  Workspace* ws = nullptr;
+  if (ffo_status st = get_workspace(dev, stream, total, host_bytes, &ws, 2)) return st;
+  char* B = (char*)ws->base;
+  auto D = [&](size_t o) { return (double*)(B + o); };
+  hipStream_t hs = (hipStream_t)stream;
+  double* hOm = (double*)ws->host;
+  double* hC = hOm + hk / 8;
+  double* hinfo_buf = hC + hk / 8;
+  int* hflag = (int*)(hinfo_buf + align_up(ffo::INFO_LEN * 8) / 8);
+
+  HIPCHK(hipEventRecord(ws->ev[0], hs));
+  HIPCHK(hipMemsetAsync(B + oflag, 0, 4, hs));
+  hipLaunchKernelGGL(k_validate, dim3(64), dim3(256), 0, hs, n, (int64_t)Pn, (int64_t)Tpn, n * k, m, alpha, F,
+                     delta, s, q, L, U, w0, w_target, (int*)(B + oflag));
+  HIPCHK(hipGetLastError());
+  if (k > 0) HIPCHK(hipMemcpyAsync(hOm, Omega, (size_t)k * k * 8, hipMemcpyDeviceToHost, hs));
+  HIPCHK(hipMemcpyAsync(hflag, B + oflag, 4, hipMemcpyDeviceToHost, hs));
+  HIPCHK(hipStreamSynchronize(hs));
+  if (*hflag) return fail(FFO_EINVAL, bad_values(*hflag));
+  if (k > 0 && !factor_omega((int)k, hOm, hC)) return fail(FFO_EINVAL, "Omega must be symmetric positive semidefinite");
+  if (k > 0) HIPCHK(hipMemcpyAsync(D(oC), hC, (size_t)k * k * 8, hipMemcpyHostToDevice, hs));
+  const double g1 = lambda1 * GMV, g2 = lambda2, g3 = lambda3;
+  if (ffo::launch_setup(n, k, m, P, Tp, ldk, F, D(oC), A, delta, s, q, w_target, g1, g2, g3, D(oK), D(odr),
+                        D(odc), D(odrC), D(oar), D(ocv), D(oca), D(ocb), D(obF), D(ocr), stream))
+    return fail(FFO_EDEVICE, "setup kernel launch failed");
+  p.K = D(oK); p.dr = D(odr); p.dc = D(odc); p.drC = D(odrC); p.alpha = alpha; p.arisk = D(oar);
+  p.cvec = D(ocv); p.ca = D(oca); p.cb = D(ocb); p.w0 = w0; p.wT = w_target; p.L = L; p.U = U;
+  p.bF = D(obF); p.g1 = g1; p.d = d; p.g2 = g2; p.crisk = D(ocr);
+  ffo::AdjState a{};
+  a.w_star = w_star; a.y_star = y_star; a.grad_w = grad_w;
+  a.xs = D(ost[0]); a.xbar = D(ost[1]); a.bb = D(ost[2]); a.sx = D(ost[3]);
+  a.lx = D(ost[4]); a.lx0 = D(ost[5]); a.Tlx = D(ost[6]);
+  a.ysC = D(osc[0]); a.lyC = D(osc[1]); a.lyC0 = D(osc[2]); a.TlyC = D(osc[3]); a.nC = D(osc[4]); a.gsf = D(osc[5]);
+  a.grad_alpha = grad_alpha; a.grad_s = grad_s; a.grad_G = D(ogG);
+  a.xbuf = D(oxb); a.bar = (unsigned long long*)(B + obar); a.info = D(oinfo); a.status = (int32_t*)(B + ostat);
+  HIPCHK(hipMemsetAsync(B + oxb, 0, (size_t)3 * c.vmax * 8, hs));
+  HIPCHK(hipMemsetAsync(B + obar, 0, 8, hs));
+  HIPCHK(hipMemsetAsync(B + oinfo, 0, ffo::INFO_LEN * 8, hs));
+  HIPCHK(hipMemsetAsync(B + ostat, 0xff, 4, hs));
+  HIPCHK(hipEventRecord(ws->ev[1], hs));
+  if (int e = ffo::launch_adjoint(p, a, c, omega > 0.0 ? omega : 1.0, stream, lds))
+    return fail(FFO_EDEVICE, std::string("cooperative launch of the adjoint kernel failed: ") +
+                                 hipGetErrorString((hipError_t)e));
+  if (k > 0 && ffo::launch_grad_F((int)n, (int)k, D(ogG), D(oC), grad_F, stream))
+    return fail(FFO_EDEVICE, "grad_F kernel launch failed");
+  HIPCHK(hipEventRecord(ws->ev[2], hs));
+  HIPCHK(hipMemcpyAsync(hinfo_buf, B + oinfo, ffo::INFO_LEN * 8, hipMemcpyDeviceToHost, hs));
+  HIPCHK(hipMemcpyAsync(hflag, B + ostat, 4, hipMemcpyDeviceToHost, hs));
+  HIPCHK(hipStreamSynchronize(hs));
+  float ms_setup = 0.f, ms_iter = 0.f;
+  hipEventElapsedTime(&ms_setup, ws->ev[0], ws->ev[1]);
+  hipEventElapsedTime(&ms_iter, ws->ev[1], ws->ev[2]);
+  const ffo_status st = status_of(*hflag);
+  if (st == FFO_NOT_CONVERGED) g_err = "adjoint iteration limit reached";
+  else if (st == FFO_NUMERIC) g_err = "NaN or Inf in the adjoint iteration";
+  else if (st == FFO_TIMEOUT) g_err = "time limit reached";
+  else if (st == FFO_EDEVICE) g_err = "adjoint kernel ended without a result (bounded wait expired)";
+  if (info) fill_info(info, st, hinfo_buf, ms_setup, ms_iter);
+  if (opt.verbose)
+    std::fprintf(stderr, "[ffo adjoint] status %d iters %.0f restarts %.0f residual %.3e exchanges %.0f nwg %d lds_k %d "
+                         "| setup %.3f ms adjoint %.3f ms\n",
+                 (int)st, hinfo_buf[ffo::IX_ITERS], hinfo_buf[ffo::IX_RESTARTS], hinfo_buf[ffo::IX_RELKKT],
+                 hinfo_buf[ffo::IX_EXCHANGES], nwg, c.lds_k, ms_setup, ms_iter);
   return st;
 }
 
@@ -650,7 +808,7 @@ ffo_status ffo_solve_batched(int64_t B, const int64_t* n_b, int64_t n_max, int64
     p.K = D(oK); p.dr = D(odrs) + (size_t)b * nr; p.dc = D(odc); p.drC = D(odrC); p.alpha = alpha + o;
     p.arisk = D(oar); p.cvec = D(ocv); p.ca = D(oca) + o; p.cb = D(ocb) + o; p.w0 = w0 + o; p.wT = nullptr;
     p.L = m ? L + (size_t)b * m : nullptr; p.U = m ? U + (size_t)b * m : nullptr;
-    p.bF = D(obF); p.crisk = D(ocr); p.g1 = g1; p.d = d;
+    p.bF = D(obF); p.crisk = D(ocr); p.g1 = g1; p.d = d; p.g2 = g2;
     hP[b] = p;
     ffo::DevState sv{};
     sv.xs = D(ost[0]) + o; sv.x0s = D(ost[1]) + o; sv.Txs = D(ost[2]) + o;

@@ -38,6 +38,7 @@ struct DevProblem {
   const double* bF;     // [k] G^T c (unscaled)
   const double* crisk;  // [1] g1 * sum_i delta_i^2 c_i^2
   double g1, d;
+  double g2;            // spread weight (the adjoint differentiates through ca = g2 s)
 };
 
 // Per-(t,i) state arrays (device memory, each workgroup touches only its own assets).
@@ -70,6 +71,30 @@ struct DevControl {
 };
 
 enum Prec { PREC_FP64 = 0, PREC_FP32 = 1 };
+
+// Adjoint of the solve operator at a solution (device memory; see adjoint_body).
+struct AdjState {
+  const double* w_star;                 // [P][n] solution W*
+  const double* y_star;                 // [P*m + P*k + Tp*n] its duals (unscaled, solve layout)
+  const double* grad_w;                 // [P][n] dl/dW*
+  double *xs, *xbar, *bb, *sx;          // [P][n] x*, xbar, prox input b, support signs / a
+  double *lx, *lx0, *Tlx;               // [P][n] adjoint primal part, anchor, its image
+  double *ysC, *lyC, *lyC0, *TlyC;      // [Tp][n] y_C*, adjoint trade part, anchor, image
+  double *nC, *gsf;                     // [Tp][n] trade prox derivative factors
+  double *grad_alpha;                   // [P][n]
+  double *grad_s;                       // [Tp][n]
+  double *grad_G;                       // [n][k] gradient w.r.t. G = F C
+  double *xbuf;                         // exchange buffer
+  unsigned long long* bar;
+  double* info;                         // [INFO_LEN]
+  int32_t* status;
+};
+int launch_adjoint(const DevProblem& p, const AdjState& a, const DevControl& c, double omega, void* stream,
+                   size_t lds_bytes);
+size_t adjoint_lds_bytes(const DevProblem& p, const DevControl& c);
+int adjoint_vmax(const DevProblem& p);
+// grad_F = grad_G C^T (n x k times k x k).
+int launch_grad_F(int n, int k, const double* grad_G, const double* C, double* grad_F, void* stream);
 
 enum InfoIdx {
   IX_ITERS = 0, IX_RESTARTS, IX_RELKKT, IX_RELPRI, IX_RELDUAL, IX_RELGAP, IX_FPR, IX_POBJ,

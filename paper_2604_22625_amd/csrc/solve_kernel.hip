@@ -1354,6 +1354,498 @@ __global__ __launch_bounds__(TB) void k_solve_batch(const DevProblem* __restrict
   solve_body<KL, SL, R>(dp[team], ds[team], ctl, wg_rank[blockIdx.x], ctl.nwg);
 }
 
+// ---------------------------------------------------------------------------------
+// Adjoint: fixed-point implicit differentiation of the solve operator
+// ---------------------------------------------------------------------------------
+// At a solution z* = T(z*) of the iteration above, a loss l of W* = dc x* has
+// dl/dtheta = lambda^T dT/dtheta with lambda = J^T lambda + g, J = dT/dz at z*, g = (dc dl/dW, 0).
+// J is the linearisation of one step with every nonsmooth piece frozen as T(z*) finds it:
+// the budget support S_t and whether mu_t > 0 (primal prox: per period
+// dw/db = diag(1{S}/a) - s s^T / c_S with s = 1{S} sign(b)/a, c_S = sum_S 1/a, when mu_t > 0),
+// the clipped exposure rows (dual prox derivative 1, else 0), the factor rows
+// (2 g1 / (sigma dr^2 + 2 g1)) and the trade rows (1 - prox'(z), prox' = 0 in the dead
+// zone of the spread term, 1 / (1 + t' b d (d-1) rho^(d-2)) outside it).  Transposing one
+// step in reverse order gives, with mu_y = N lambda_y, q = lambda_x + 2 sigma K~^T mu_y,
+// nu = dw/db (q / dc):
+//   J^T lambda = ( nu / (tau dc) - sigma K~^T mu_y ,  mu_y - K~ (nu / dc) ),
+// and nu is the gradient with respect to alpha.  One exchange per iteration carries the
+// row sums of K~ (1{S}/a q / dc^2) and s^T (q / dc) per period (K~ s / dc is fixed).  The
+// iteration is the same restarted reflected Halpern scheme as the solve.  At the end:
+//   dl/ds   = lambda_yC g2 sign(z) prox'(z) / drC,
+//   dl/dG_il = dr_j (sum_t sigma mu_y,tj w*_ti - y*_tj nu_ti) - [multi-period] sigma dr_j c_i sum_t mu_y,tj
+// for the factor row j = m + l (dK~_ji / dG_il = dr_j dc_i; the scaling is held fixed, which
+// leaves the solution map unchanged), and dl/dF = dl/dG C^T follows in launch_grad_F.
+struct AScal {
+  double omega, eta, tau, sigma, r0, rprev, gnorm;
+  long long it, kk, restarts, checks;
+  int done, status, restart;
+};
+
+template <bool KL>
+__global__ __launch_bounds__(TB) void k_adjoint(DevProblem p, AdjState a, DevControl ctl, double omega_in) {
+  ldbl* lds = (ldbl*)g_lds;
+  const int P = p.P, nr = p.nr, n = p.n, Tp = p.Tp, nw = ctl.nw, m = p.m;
+  Ctx c;
+  c.wg = blockIdx.x;
+  c.nwg = gridDim.x;
+  c.tid = threadIdx.x;
+  c.i0 = c.wg * nw;
+  c.nwa = max(0, min(nw, n - c.i0));
+  c.epoch = 0;
+  c.xbuf = a.xbuf;
+  c.bar = a.bar;
+  c.vmax = ctl.vmax;
+  c.xmode = ctl.xmode;
+  c.P = P;
+  c.spin_limit = ctl.spin_limit;
+  c.mx_lo = c.mx_hi = 0;
+  c.t_wait = c.t_pre = c.t_read = 0;
+
+  // LDS layout (doubles); must match adjoint_lds_bytes
+  ldbl* ptr = lds;
+  ldbl* Kl = nullptr;
+  const int ldl = nw | 1;
+  if (KL) { Kl = ptr; ptr += (size_t)nr * ldl; }
+  ldbl* ks = ptr;   ptr += nr;
+  ldbl* ys = ptr;   ptr += P * nr;     // y* (scaled rows)
+  ldbl* nR = ptr;   ptr += P * nr;     // row prox derivatives
+  ldbl* Kr = ptr;   ptr += P * nr;     // K~ (s / dc), fixed
+  ldbl* ly = ptr;   ptr += P * nr;     // adjoint row part, anchor, image
+  ldbl* ly0 = ptr;  ptr += P * nr;
+  ldbl* Tly = ptr;  ptr += P * nr;
+  ldbl* muy = ptr;  ptr += P * nr;     // N lambda_y (rows)
+  ldbl* KDu = ptr;  ptr += P * nr;     // exchanged row sums
+  ldbl* xv1 = ptr;  ptr += P * nw;
+  ldbl* xv2 = ptr;  ptr += P * nw;
+  ldbl* xv3 = ptr;  ptr += P * nw;
+  ldbl* xv4 = ptr;  ptr += P * nw;
+  ldbl* mC = ptr;   ptr += Tp * nw;    // N lambda_yC of the owned assets
+  ldbl* tot = ptr;  ptr += ctl.vmax;
+  ldbl* red = ptr;  ptr += RED_LEN;
+  ldbl* cen = ptr;  ptr += P;
+  ldbl* hw = ptr;   ptr += P;
+  ldbl* lo = ptr;   ptr += P;
+  ldbl* hi = ptr;   ptr += P;
+  ldbl* mu = ptr;   ptr += P;
+  ldbl* cS = ptr;   ptr += P;
+  ldbl* stu = ptr;  ptr += P;
+  __attribute__((address_space(3))) AScal* sc = (__attribute__((address_space(3))) AScal*)ptr;
+  ptr += (sizeof(AScal) + 7) / 8;
+  lint* iflag = (lint*)ptr; ptr += 2;
+  lint* fbflag = iflag + 1;
+  lint* need = (lint*)ptr;
+  c.tot = tot;
+  c.red = red;
+  c.flag = iflag;
+  c.lslot = nullptr;
+
+  S<KL, false, double> V;
+  {
+    auto g = [&](const double* b) { return Arr<false, double>{(double*)b, n, c.i0}; };
+    V.p = &p; V.Kl = Kl; V.Kg = p.K; V.ks = ks; V.nw = nw; V.ldl = ldl; V.i0 = c.i0;
+    V.alpha = g(p.alpha); V.ca = g(p.ca); V.cb = g(p.cb); V.drC = g(p.drC);
+    V.dc = g(p.dc); V.arisk = g(p.arisk); V.cvec = g(p.cvec); V.w0 = g(p.w0);
+    V.wT = g(p.wT ? p.wT : p.w0);
+  }
+  auto G = [&](double* b) { return Arr<false, double>{b, n, c.i0}; };
+  const auto xs = G(a.xs), xbar = G(a.xbar), bb = G(a.bb), sx = G(a.sx);
+  const auto lx = G(a.lx), lx0 = G(a.lx0), Tlx = G(a.Tlx);
+  const auto ysC = G(a.ysC), lyC = G(a.lyC), lyC0 = G(a.lyC0), TlyC = G(a.TlyC), nC = G(a.nC), gsf = G(a.gsf);
+  const Arr<true, double> mCv{mC, nw, 0}, nbv{xv4, nw, 0};
+
+  for (int j = c.tid; j < nr; j += TB) ks[j] = p.kscaled ? 1.0 : p.dr[j];
+  __syncthreads();
+  if (KL)
+    for (int e = c.tid; e < nr * nw; e += TB) {
+      const int j = e / nw, li = e % nw;
+      Kl[j * ldl + li] = li < c.nwa ? p.K[(size_t)j * p.ldk + c.i0 + li] * ks[j] : 0.0;
+    }
+  // the solution in scaled variables
+  for (int e = c.tid; e < P * c.nwa; e += TB) {
+    const int t = e / c.nwa, li = e % c.nwa;
+    xs(t, li) = a.w_star[(size_t)t * n + c.i0 + li] / V.dc(0, li);
+    xbar(t, li) = 1.0 + 0.25 * (double)(((c.i0 + li) * 7919 + t * 104729) % 1000) / 1000.0;   // power vector
+  }
+  {
+    const double* yC = a.y_star + (size_t)P * nr;
+    for (int e = c.tid; e < Tp * c.nwa; e += TB) {
+      const int t = e / c.nwa, li = e % c.nwa;
+      ysC(t, li) = yC[(size_t)t * n + c.i0 + li] / V.drC(t, li);
+    }
+  }
+  for (int e = c.tid; e < P * nr; e += TB) {
+    const int t = e / nr, j = e % nr;
+    const double yu = j < m ? a.y_star[(size_t)t * m + j] : a.y_star[(size_t)P * m + (size_t)t * p.k + (j - m)];
+    ys[e] = yu / p.dr[j];
+    ly[e] = 0.0; ly0[e] = 0.0; Tly[e] = 0.0;
+  }
+  if (c.tid == 0) {
+    sc->omega = omega_in; sc->it = 0; sc->kk = 0; sc->restarts = 0; sc->checks = 0;
+    sc->r0 = -1.0; sc->rprev = INFINITY; sc->done = 0; sc->status = DS_RUNNING; sc->restart = 0;
+    fbflag[0] = 0;
+    for (int t = 0; t < P; ++t) { cen[t] = 0.0; hw[t] = 0.0; mu[t] = 0.0; need[t] = 0; }
+  }
+  __syncthreads();
+  const long long t_start = wall_clock64();
+
+  // ---- power iteration for ||K~|| (same recipe as the solve)
+  double lam = 0.0;
+  for (int pw = 0; pw < ctl.npow; ++pw) {
+    double loc[2] = {0.0, 0.0};
+    for (int e = c.tid; e < P * c.nwa; e += TB) {
+      const int t = e / c.nwa, li = e % c.nwa;
+      const double x = xbar(t, li);
+      xv1[t * nw + li] = x;
+      loc[0] = fma(x, x, loc[0]);
+    }
+    for (int e = c.tid; e < Tp * c.nwa; e += TB) {
+      const int t = e / c.nwa, li = e % c.nwa;
+      const double u = kx_trade(V, xbar, t, li);
+      loc[1] = fma(u, u, loc[1]);
+    }
+    wg_sum<2>(c, loc);
+    if (c.tid == 0) { put(c, 0, red[RED_OUT]); put(c, 1, red[RED_OUT + 1]); }
+    __syncthreads();
+    rows_prod<1>(c, V, xv1, xv1, nw, P, nr, [&](int e, const double* q) { put(c, 2 + e, q[0]); });
+    if (!xsync(c, 2 + P * nr)) goto adj_fail;
+    {
+      const double vv = tot[0];
+      double kv = tot[1];
+      for (int e = 0; e < P * nr; ++e) kv = fma(tot[2 + e], tot[2 + e], kv);
+      lam = vv > 0.0 ? kv / vv : 0.0;
+      const double scale = (lam > 0.0 && vv > 0.0) ? 1.0 / (lam * sqrt(vv)) : 1.0;
+      kty_all(c, V, tot + 2, P, nr, nw, xv2);
+      for (int e = c.tid; e < P * c.nwa; e += TB) {
+        const int t = e / c.nwa, li = e % c.nwa;
+        double uc = kx_trade(V, xbar, t, li) * V.drC(t, li) * V.dc(0, li);
+        if (p.multi) uc -= kx_trade(V, xbar, t + 1, li) * V.drC(t + 1, li) * V.dc(0, li);
+        xv2[t * nw + li] = (xv2[t * nw + li] + uc) * scale;
+      }
+      __syncthreads();
+      for (int e = c.tid; e < P * c.nwa; e += TB) {
+        const int t = e / c.nwa, li = e % c.nwa;
+        xbar(t, li) = xv2[t * nw + li];
+      }
+      __syncthreads();
+    }
+  }
+  if (c.tid == 0) {
+    sc->eta = ctl.eta_safety / sqrt(fmax(lam, 1e-300));
+    sc->tau = sc->eta / sc->omega;
+    sc->sigma = sc->eta * sc->omega;
+  }
+  __syncthreads();
+
+  {
+    const double tau = sc->tau, sigma = sc->sigma;
+    // ---- one step T(z*): the pieces the linearisation freezes
+    kty_all(c, V, ys, P, nr, nw, xv1);
+    for (int e = c.tid; e < P * c.nwa; e += TB) {
+      const int t = e / c.nwa, li = e % c.nwa;
+      const double Ry = xv1[t * nw + li] + kty_trade(V, ysC, t, li);
+      const double v = xs(t, li) - tau * Ry;
+      const double dci = V.dc(0, li);
+      const double ia = 1.0 / (1.0 / (tau * dci * dci) + V.arisk(0, li));
+      const double b = v / (tau * dci) + V.alpha(t, li) + V.arisk(0, li) * V.cvec(0, li);
+      bb(t, li) = b;
+      xv3[t * nw + li] = fabs(b);
+      xv4[t * nw + li] = ia;
+    }
+    __syncthreads();
+    period_stats(c, xv3, xv4, nw, cen, hw, 0);
+    c.mx_lo = 0;
+    c.mx_hi = STW * P;
+    if (!xsync(c, STW * P)) goto adj_fail;
+    {
+      const int lane = c.tid & 63, wave = c.tid >> 6;
+      for (int t = wave; t < P; t += NWAVE) {
+        double l = 0.0, h = 0.0, m_ = 0.0;
+        const int r = bracket_decide(tot + STW * t, 0.0, 0.0, l, h, m_);
+        if (lane == 0) {
+          if (r == 0 || r == 3) { lo[t] = l; hi[t] = h; need[t] = 1; fbflag[0] = 1; }
+          else { mu[t] = m_; need[t] = 0; }
+        }
+      }
+    }
+    __syncthreads();
+    if (*fbflag && !multisect(c, P, xv3, xv4, nw, need, lo, hi, mu, iflag + 3)) goto adj_fail;
+    // support, x^+, xbar; rows of K~ xbar, sum_S 1/a, K~ (s / dc) in one exchange
+    for (int e = c.tid; e < P * c.nwa; e += TB) {
+      const int t = e / c.nwa, li = e % c.nwa;
+      const double b = bb(t, li), ab = fabs(b), ia = xv4[t * nw + li], dci = V.dc(0, li);
+      const bool in = ab > mu[t];
+      const double xp = in ? sgn(b) * (ab - mu[t]) * ia / dci : 0.0;
+      const double xb = 2.0 * xp - xs(t, li);
+      xbar(t, li) = xb;
+      sx(t, li) = in ? sgn(b) * ia : 0.0;
+      xv1[t * nw + li] = xb;
+      xv2[t * nw + li] = in ? sgn(b) * ia / dci : 0.0;
+      xv3[t * nw + li] = in ? ia : 0.0;
+    }
+    __syncthreads();
+    {
+      const int lane = c.tid & 63, wave = c.tid >> 6;
+      for (int t = wave; t < P; t += NWAVE) {
+        double v = 0.0;
+        for (int li = lane; li < c.nwa; li += 64) v += xv3[t * nw + li];
+        v = wave_sum(v);
+        if (lane == 0) put(c, 2 * P * nr + t, v);
+      }
+    }
+    rows_prod<2>(c, V, xv1, xv2, nw, P, nr, [&](int e, const double* q) {
+      put(c, e, q[0]);
+      put(c, P * nr + e, q[1]);
+    });
+    if (!xsync(c, 2 * P * nr + P)) goto adj_fail;
+    for (int e = c.tid; e < P * nr; e += TB) {
+      const int j = e % nr;
+      const double vs = ys[e] + sigma * tot[e];
+      if (j < m) {
+        const double sd = sigma * p.dr[j], z = vs / sd;
+        nR[e] = (z > p.L[j] && z < p.U[j]) ? 0.0 : 1.0;
+      } else {
+        const double drj = p.dr[j];
+        nR[e] = 2.0 * p.g1 / (sigma * drj * drj + 2.0 * p.g1);
+      }
+      Kr[e] = tot[P * nr + e];
+    }
+    for (int t = c.tid; t < P; t += TB) cS[t] = tot[2 * P * nr + t];
+    for (int e = c.tid; e < Tp * c.nwa; e += TB) {
+      const int t = e / c.nwa, li = e % c.nwa;
+      const double kc = kx_trade(V, xbar, t, li);
+      const double vs = ysC(t, li) + sigma * kc;
+      const double drc = V.drC(t, li);
+      const double z = vs / (sigma * drc) - trade_offset(V, t, li);
+      const double tp = 1.0 / (sigma * drc * drc);
+      const double ca = V.ca(t, li), cb = V.cb(t, li);
+      double dp = 0.0;
+      if (fabs(z) - tp * ca > 0.0) {
+        const double rho = fabs(prox_cost(z, tp, ca, cb, p.d));
+        if (p.d == 2.0) dp = 1.0 / (1.0 + 2.0 * tp * cb);
+        else if (rho > 0.0) dp = 1.0 / (1.0 + tp * cb * p.d * (p.d - 1.0) * pow(rho, p.d - 2.0));
+      }
+      nC(t, li) = 1.0 - dp;
+      gsf(t, li) = p.g2 * sgn(z) * dp / drc;
+      lyC(t, li) = 0.0; lyC0(t, li) = 0.0; TlyC(t, li) = 0.0;
+    }
+    for (int e = c.tid; e < P * c.nwa; e += TB) {
+      const int t = e / c.nwa, li = e % c.nwa;
+      lx(t, li) = 0.0; lx0(t, li) = 0.0; Tlx(t, li) = 0.0;
+    }
+    __syncthreads();
+
+    // ---- adjoint iteration
+    // one application of lambda -> J^T lambda + g; leaves nu in xv3 (per owned (t, i)), mu_y
+    // in muy / mC, K~^T mu_y in xv1.  Returns false when a bounded wait expired.
+    auto apply = [&]() -> bool {
+      for (int e = c.tid; e < P * nr; e += TB) muy[e] = nR[e] * ly[e];
+      for (int e = c.tid; e < Tp * c.nwa; e += TB) {
+        const int t = e / c.nwa, li = e % c.nwa;
+        mC[t * nw + li] = nC(t, li) * lyC(t, li);
+      }
+      __syncthreads();
+      kty_all(c, V, muy, P, nr, nw, xv1);
+      for (int e = c.tid; e < P * c.nwa; e += TB) {
+        const int t = e / c.nwa, li = e % c.nwa;
+        const double Kt = xv1[t * nw + li] + kty_trade(V, mCv, t, li);
+        xv1[t * nw + li] = Kt;
+        const double dci = V.dc(0, li);
+        const double u = (lx(t, li) + 2.0 * sigma * Kt) / dci;
+        const double ia = fabs(sx(t, li));
+        xv2[t * nw + li] = ia * u / dci;     // (1{S}/a) u / dc
+        xv3[t * nw + li] = u;
+      }
+      __syncthreads();
+      {
+        const int lane = c.tid & 63, wave = c.tid >> 6;
+        for (int t = wave; t < P; t += NWAVE) {
+          double v = 0.0;
+          for (int li = lane; li < c.nwa; li += 64) v = fma(sx(t, li), xv3[t * nw + li], v);
+          v = wave_sum(v);
+          if (lane == 0) put(c, P * nr + t, v);
+        }
+      }
+      rows_prod<1>(c, V, xv2, xv2, nw, P, nr, [&](int e, const double* q) { put(c, e, q[0]); });
+      if (!xsync(c, P * nr + P)) return false;
+      for (int t = c.tid; t < P; t += TB) stu[t] = (mu[t] > 0.0 && cS[t] > 0.0) ? tot[P * nr + t] / cS[t] : 0.0;
+      __syncthreads();
+      for (int e = c.tid; e < P * nr; e += TB) {
+        const int t = e / nr;
+        Tly[e] = muy[e] - (tot[e] - stu[t] * Kr[e]);
+      }
+      for (int e = c.tid; e < P * c.nwa; e += TB) {
+        const int t = e / c.nwa, li = e % c.nwa;
+        const double ia = fabs(sx(t, li));
+        const double nu = ia * xv3[t * nw + li] - sx(t, li) * stu[t];
+        const double dci = V.dc(0, li);
+        xv3[t * nw + li] = nu;
+        xv4[t * nw + li] = nu / dci;
+        Tlx(t, li) = nu / (tau * dci) - sigma * xv1[t * nw + li] + dci * a.grad_w[(size_t)t * n + c.i0 + li];
+      }
+      __syncthreads();
+      for (int e = c.tid; e < Tp * c.nwa; e += TB) {
+        const int t = e / c.nwa, li = e % c.nwa;
+        TlyC(t, li) = mC[t * nw + li] - kx_trade(V, nbv, t, li);
+      }
+      __syncthreads();
+      return true;
+    };
+
+    // |g| for the relative residual
+    {
+      double gv[1] = {0.0};
+      for (int e = c.tid; e < P * c.nwa; e += TB) {
+        const int t = e / c.nwa, li = e % c.nwa;
+        const double gx = V.dc(0, li) * a.grad_w[(size_t)t * n + c.i0 + li];
+        gv[0] = fma(gx, gx, gv[0]);
+      }
+      wg_sum<1>(c, gv);
+      if (c.tid == 0) put(c, 0, red[RED_OUT]);
+      if (!xsync(c, 1)) goto adj_fail;
+      if (c.tid == 0) sc->gnorm = sqrt(tot[0]);
+      __syncthreads();
+    }
+    while (true) {
+      if (!apply()) goto adj_fail;
+      const bool check = ((sc->it + 1) % ctl.check_every == 0) || (sc->it + 1 >= ctl.max_iter);
+      if (check) {
+        double v[2] = {0.0, 0.0};
+        for (int e = c.tid; e < P * c.nwa; e += TB) {
+          const int t = e / c.nwa, li = e % c.nwa;
+          const double d = Tlx(t, li) - lx(t, li);
+          v[0] = fma(d, d, v[0]);
+          if (!isfinite(d)) v[1] += 1.0;
+        }
+        for (int e = c.tid; e < Tp * c.nwa; e += TB) {
+          const int t = e / c.nwa, li = e % c.nwa;
+          const double d = TlyC(t, li) - lyC(t, li);
+          v[0] = fma(d, d, v[0]);
+          if (!isfinite(d)) v[1] += 1.0;
+        }
+        if (c.wg == 0)
+          for (int e = c.tid; e < P * nr; e += TB) { const double d = Tly[e] - ly[e]; v[0] = fma(d, d, v[0]); }
+        wg_sum<2>(c, v);
+        if (c.tid < 2) put(c, c.tid, red[RED_OUT + c.tid]);
+        if (c.wg == 0 && c.tid == 0) {
+          const double el = (double)(wall_clock64() - t_start) / ctl.wall_hz;
+          put(c, 2, el > ctl.time_limit_s ? 1.0 : 0.0);
+        }
+        if (!xsync(c, 3)) goto adj_fail;
+        const double res = sqrt(tot[0]) / fmax(sc->gnorm, 1e-300);
+        if (c.tid == 0) {
+          sc->checks++;
+          sc->restart = 0;
+          if (c.wg == 0) { a.info[IX_RELKKT] = res; a.info[IX_FPR] = res; }
+          if (tot[1] > 0.0 || !isfinite(res)) { sc->done = 1; sc->status = DS_NUMERIC; }
+          else if (res <= ctl.tol) { sc->done = 1; sc->status = DS_OK; }
+          else if (tot[2] > 0.0) { sc->done = 1; sc->status = DS_TIMEOUT; }
+          else if (sc->it + 1 >= ctl.max_iter) { sc->done = 1; sc->status = DS_NOT_CONVERGED; }
+          else {
+            if (sc->r0 < 0.0) sc->r0 = res;
+            const bool rs = (res <= ctl.r_suff * sc->r0) || (res <= ctl.r_nec * sc->r0 && res > sc->rprev) ||
+                            ((double)(sc->kk + 1) >= ctl.r_art * (double)(sc->it + 1));
+            sc->rprev = res;
+            if (rs) { sc->r0 = res; sc->rprev = INFINITY; sc->restarts++; sc->restart = 1; }
+          }
+        }
+        __syncthreads();
+        if (sc->done) break;
+        if (sc->restart) {
+          for (int e = c.tid; e < P * c.nwa; e += TB) {
+            const int t = e / c.nwa, li = e % c.nwa;
+            const double x = Tlx(t, li);
+            lx(t, li) = x; lx0(t, li) = x;
+          }
+          for (int e = c.tid; e < Tp * c.nwa; e += TB) {
+            const int t = e / c.nwa, li = e % c.nwa;
+            const double y = TlyC(t, li);
+            lyC(t, li) = y; lyC0(t, li) = y;
+          }
+          for (int e = c.tid; e < P * nr; e += TB) { ly[e] = Tly[e]; ly0[e] = Tly[e]; }
+          __syncthreads();
+          if (c.tid == 0) { sc->kk = 0; sc->it++; }
+          __syncthreads();
+          continue;
+        }
+      }
+      {
+        const double kk = (double)sc->kk;
+        const double a1 = (kk + 1.0) / (kk + 2.0), a0 = 1.0 / (kk + 2.0), rho = ctl.rho;
+        for (int e = c.tid; e < P * c.nwa; e += TB) {
+          const int t = e / c.nwa, li = e % c.nwa;
+          lx(t, li) = a1 * ((1.0 + rho) * Tlx(t, li) - rho * lx(t, li)) + a0 * lx0(t, li);
+        }
+        for (int e = c.tid; e < Tp * c.nwa; e += TB) {
+          const int t = e / c.nwa, li = e % c.nwa;
+          lyC(t, li) = a1 * ((1.0 + rho) * TlyC(t, li) - rho * lyC(t, li)) + a0 * lyC0(t, li);
+        }
+        for (int e = c.tid; e < P * nr; e += TB) ly[e] = a1 * ((1.0 + rho) * Tly[e] - rho * ly[e]) + a0 * ly0[e];
+        __syncthreads();
+        if (c.tid == 0) { sc->kk++; sc->it++; }
+        __syncthreads();
+      }
+    }
+    // ---- gradients at the final lambda (one more application gives nu, mu_y)
+    for (int e = c.tid; e < P * c.nwa; e += TB) {
+      const int t = e / c.nwa, li = e % c.nwa;
+      lx(t, li) = Tlx(t, li);
+    }
+    for (int e = c.tid; e < Tp * c.nwa; e += TB) {
+      const int t = e / c.nwa, li = e % c.nwa;
+      lyC(t, li) = TlyC(t, li);
+    }
+    for (int e = c.tid; e < P * nr; e += TB) ly[e] = Tly[e];
+    __syncthreads();
+    if (!apply()) goto adj_fail;
+    for (int e = c.tid; e < P * c.nwa; e += TB) {
+      const int t = e / c.nwa, li = e % c.nwa;
+      a.grad_alpha[(size_t)t * n + c.i0 + li] = xv3[t * nw + li];
+    }
+    for (int e = c.tid; e < Tp * c.nwa; e += TB) {
+      const int t = e / c.nwa, li = e % c.nwa;
+      a.grad_s[(size_t)t * n + c.i0 + li] = lyC(t, li) * gsf(t, li);
+    }
+    for (int e = c.tid; e < c.nwa * p.k; e += TB) {
+      const int li = e / p.k, l = e % p.k, j = m + l;
+      const double dci = V.dc(0, li), drj = p.dr[j];
+      double gsum = 0.0, msum = 0.0;
+      for (int t = 0; t < P; ++t) {
+        const double wst = dci * xs(t, li);
+        gsum += sigma * muy[t * nr + j] * wst - ys[t * nr + j] * xv3[t * nw + li];
+        msum += muy[t * nr + j];
+      }
+      double g = drj * gsum;
+      if (p.multi) g -= sigma * drj * V.cvec(0, li) * msum;
+      a.grad_G[(size_t)(c.i0 + li) * p.k + l] = g;
+    }
+  }
+  if (c.wg == 0 && c.tid == 0) {
+    a.info[IX_ITERS] = (double)sc->it;
+    a.info[IX_RESTARTS] = (double)sc->restarts;
+    a.info[IX_OMEGA] = sc->omega;
+    a.info[IX_ETA] = sc->eta;
+    a.info[IX_CHECKS] = (double)sc->checks;
+    a.info[IX_EXCHANGES] = (double)c.epoch;
+    a.status[0] = sc->status;
+  }
+  return;
+
+adj_fail:
+  if (c.tid == 0) __hip_atomic_store(a.status, (int32_t)DS_BARRIER, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  return;
+}
+
+// grad_F[i][p] = sum_l grad_G[i][l] C[p][l]
+__global__ __launch_bounds__(TB) void k_grad_F(int n, int k, const double* __restrict__ gG, const double* __restrict__ C,
+                                              double* __restrict__ gF) {
+  const int64_t e = blockIdx.x * (int64_t)TB + threadIdx.x;
+  if (e >= (int64_t)n * k) return;
+  const int i = (int)(e / k), pp = (int)(e % k);
+  double s = 0.0;
+  for (int l = 0; l < k; ++l) s = fma(gG[(size_t)i * k + l], C[(size_t)pp * k + l], s);
+  gF[e] = s;
+}
+
 }  // namespace
 
 int solve_vmax(const DevProblem& p) {
@@ -1418,6 +1910,40 @@ int solve_batch_occupancy(int kl, int sl, int prec, size_t lds) {
   int blocks = 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, batch_fn(kl, sl, prec), TB, lds) != hipSuccess) return 0;
   return blocks;
+}
+
+int adjoint_vmax(const DevProblem& p) {
+  const int P = p.P, nr = p.nr;
+  int v = STW * P;
+  v = std::max(v, 3 * P * MSC);
+  v = std::max(v, 2 * P * nr + P);
+  v = std::max(v, 2 + P * nr);
+  v = std::max(v, 4);
+  return (v + 63) / 64 * 64;
+}
+
+size_t adjoint_lds_bytes(const DevProblem& p, const DevControl& c) {
+  const size_t P = p.P, Tp = p.Tp, nr = p.nr, nw = c.nw;
+  size_t d = 0;
+  if (c.lds_k) d += nr * (nw | 1);
+  d += nr + 8 * P * nr + 4 * P * nw + Tp * nw + (size_t)c.vmax + RED_LEN + 7 * P;
+  d += (sizeof(AScal) + 7) / 8 + 2 + (P + 1) / 2 + 1;
+  return d * sizeof(double);
+}
+
+int launch_adjoint(const DevProblem& p, const AdjState& a, const DevControl& c, double omega, void* stream,
+                   size_t lds) {
+  void* args[] = {(void*)&p, (void*)&a, (void*)&c, (void*)&omega};
+  const void* fn = c.lds_k ? (const void*)k_adjoint<true> : (const void*)k_adjoint<false>;
+  hipError_t e = hipLaunchCooperativeKernel(fn, dim3(c.nwg), dim3(TB), args, (unsigned int)lds, (hipStream_t)stream);
+  return e == hipSuccess ? 0 : (int)e;
+}
+
+int launch_grad_F(int n, int k, const double* gG, const double* C, double* gF, void* stream) {
+  const int64_t tot = (int64_t)n * k;
+  if (tot == 0) return 0;
+  hipLaunchKernelGGL(k_grad_F, dim3((unsigned)((tot + TB - 1) / TB)), dim3(TB), 0, (hipStream_t)stream, n, k, gG, C, gF);
+  return hipGetLastError() == hipSuccess ? 0 : 1;
 }
 
 }  // namespace ffo

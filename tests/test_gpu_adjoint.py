@@ -1,0 +1,113 @@
+"""GPU parity of the adjoint form (ffo_adjoint, and FolioFn for torch.autograd): the
+device gradients of l(W*) = <grad_W, W*> with respect to alpha, s and F against the
+oracle's reference gradient (implicit differentiation on the certified solution's
+piece, itself pinned by finite differences), and at full size (T = 10, n = 2000)
+against central differences of the device solve along random directions."""
+import numpy as np
+import pytest
+
+from oracle.grad import reference_gradient
+from synth import make_single, make_multi, make_config
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2604_22625_amd as ff
+    return ff
+
+
+def _device_grad(inst, gW, tol=1e-10, adj_tol=1e-10):
+    ff = _gpu()
+    print(f"[case] adjoint n={np.asarray(inst['alpha']).shape[-1]} T={inst.get('T', 0)}", flush=True)
+    W, info, Y = ff.solve_instance(inst, tol=tol, return_dual=True, time_limit_s=60.0)
+    assert info.status == 0
+    ga, gs, gF, ainfo = ff.adjoint(inst, W, Y, gW, omega=info.omega, tol=adj_tol, time_limit_s=60.0)
+    torch.cuda.synchronize()
+    assert ainfo.status == 0, ainfo
+    return ga.cpu().numpy(), gs.cpu().numpy(), gF.cpu().numpy(), W.cpu().numpy(), ainfo
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+@pytest.mark.parametrize("seed", [3, 8])
+def test_single_period_matches_oracle_gradient(seed):
+    inst = make_single(30, 3, 2, seed=seed)
+    gW = np.random.default_rng(seed).normal(size=(1, 30))
+    ref = reference_gradient(inst, gW)
+    ga, gs, gF, W, _ = _device_grad(inst, gW)
+    assert np.max(np.abs(W - ref.W)) <= 1e-6
+    assert _rel(ga, ref.alpha) <= 1e-4
+    assert _rel(gs, ref.s) <= 1e-4
+    assert _rel(gF, ref.F) <= 1e-4
+
+
+def test_larger_single_period_matches_oracle_gradient():
+    inst = make_single(300, 8, 6, seed=21)
+    gW = np.random.default_rng(2).normal(size=(1, 300))
+    ref = reference_gradient(inst, gW)
+    ga, gs, gF, W, _ = _device_grad(inst, gW)
+    assert _rel(ga, ref.alpha) <= 1e-4
+    assert _rel(gs, ref.s) <= 1e-4
+    assert _rel(gF, ref.F) <= 1e-4
+
+
+@pytest.mark.parametrize("T,n", [(3, 16), (5, 40)])
+def test_multi_period_matches_oracle_gradient(T, n):
+    inst = make_multi(T, n, 2, 2, seed=12 + T)
+    gW = np.zeros((T - 1, n))
+    gW[-1] = np.random.default_rng(5).normal(size=n)     # loss on the last decision
+    ref = reference_gradient(inst, gW)
+    ga, gs, gF, W, _ = _device_grad(inst, gW)
+    assert _rel(ga, ref.alpha) <= 1e-4
+    assert _rel(gs, ref.s) <= 1e-4
+    assert _rel(gF, ref.F) <= 1e-4
+
+
+def test_autograd_function_matches_adjoint():
+    ff = _gpu()
+    inst = make_single(40, 3, 2, seed=31)
+    dev = torch.device("cuda", 0)
+    alpha = torch.tensor(inst["alpha"], device=dev, requires_grad=True)
+    s = torch.tensor(inst["s"], device=dev, requires_grad=True)
+    F = torch.tensor(inst["F"], device=dev, requires_grad=True)
+    rest = {k: v for k, v in inst.items() if k not in ("alpha", "s", "F")}
+    W = ff.FolioFn.apply(alpha, s, F, rest, {"tol": 1e-10})
+    r = torch.tensor(np.random.default_rng(4).normal(size=(1, 40)), device=dev)
+    (r * W).sum().backward()
+    ref = reference_gradient(inst, r.cpu().numpy())
+    assert _rel(alpha.grad.cpu().numpy(), ref.alpha) <= 1e-4
+    assert _rel(s.grad.cpu().numpy(), ref.s) <= 1e-4
+    assert _rel(F.grad.cpu().numpy(), ref.F) <= 1e-4
+
+
+def test_full_size_multi_period_against_device_differences():
+    """T = 10, n = 2000, k = 40, m = 40 with l = r^T w_{T-1} (the last decision): the
+    adjoint's directional derivatives against central differences of the device solve."""
+    ff = _gpu()
+    inst = make_config(4)
+    P, n = inst["alpha"].shape
+    gW = np.zeros((P, n))
+    gW[-1] = inst["r"]
+    ga, gs, gF, W, ainfo = _device_grad(inst, gW, tol=1e-9, adj_tol=1e-9)
+    rng = np.random.default_rng(7)
+
+    def loss(d):
+        Wd, i = ff.solve_instance(d, tol=1e-11, time_limit_s=120.0)
+        assert i.status == 0
+        return float(np.sum(gW * Wd.cpu().numpy()))
+
+    for key, h, g in (("alpha", 1e-7, ga), ("F", 1e-6, gF)):
+        dvec = rng.normal(size=np.asarray(inst[key]).shape)
+        lp, lm = dict(inst), dict(inst)
+        lp[key] = inst[key] + h * dvec
+        lm[key] = inst[key] - h * dvec
+        fd = (loss(lp) - loss(lm)) / (2 * h)
+        an = float(np.sum(g * dvec))
+        assert abs(an - fd) <= 2e-3 * abs(fd) + 1e-9, (key, an, fd)
