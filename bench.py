@@ -73,6 +73,8 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-max-iter", type=int, default=40000)
     ap.add_argument("--workgroups", type=int, default=0)
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the comparison legs (T=20 solve, FP32 form, batched form, adjoint)")
     return ap.parse_args()
 
 
@@ -98,6 +100,80 @@ def cpu_baseline(inst, tol, max_iter):
             "kind": "oracle",
             "sample": (f"1 instance (seed {inst['seed']}) of the same workload; oracle averaged PDHG to rel KKT "
                        f"{tol:g} ({r.iters} iterations, reached {r.rel_kkt:.2e}, {dt:.1f} s); polish excluded")}
+
+
+def _timed(torch, fn, reps):
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    res = None
+    for _ in range(reps):
+        res = fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / reps, res
+
+
+def comparisons(ff, torch, dev, dev_insts, tol, plain_value):
+    """The other legs of the metric, each timed after one warm-up: the T=20 multi-period
+    solve (n=3000), the FP32 form on the same n=5000 markets, the 256-instance batched
+    form against sequential plain solves of the same instances (a sample of 32, scaled),
+    and the adjoint of the T=10 workload (forward + backward)."""
+    from synth import make_config, batch_instance
+    out = {}
+    # T = 20 multi-period, FP64 and FP32
+    c2 = make_config(2)
+    for prec in ("fp64", "fp32"):
+        ff.solve_instance(c2, tol=tol, precision=prec)
+        dt, (W, info) = _timed(torch, lambda: ff.solve_instance(c2, tol=tol, precision=prec), 2)
+        out[f"multi_period_T20_n3000_{prec}"] = {"solves_per_s": 1.0 / dt, "iters": info.iters,
+                                                 "us_per_iter": info.ms_iter * 1e3 / max(info.iters, 1),
+                                                 "rel_kkt": info.rel_kkt, "status": info.status}
+    # FP32 form on the benchmark markets
+    def fp32_step():
+        return [ff.solve_instance(d, tol=tol, precision="fp32")[1] for d in dev_insts]
+    fp32_step()
+    dt, infos = _timed(torch, fp32_step, 1)
+    out["single_period_n5000_fp32"] = {"solves_per_s": len(dev_insts) / dt, "vs_fp64": (len(dev_insts) / dt) / plain_value,
+                                       "iters_mean": float(np.mean([i.iters for i in infos])),
+                                       "all_ok": all(i.status == 0 for i in infos)}
+    # batched form
+    batch = make_config(3)
+    for prec in ("fp64", "fp32"):
+        ff.solve_batched(batch, tol=tol, precision=prec)
+        dt, (W, binfos) = _timed(torch, lambda: ff.solve_batched(batch, tol=tol, precision=prec), 2)
+        out[f"batched_256_{prec}"] = {"solves_per_s": len(binfos) / dt, "batch_ms": dt * 1e3,
+                                      "iters_max": int(max(i.iters for i in binfos)),
+                                      "all_ok": all(i.status == 0 for i in binfos)}
+    nb = np.asarray(batch["n_b"])
+    idx = np.linspace(0, len(nb) - 1, 32).astype(int)
+    seq = [batch_instance(batch, int(b)) for b in idx]
+    seq_dev = []
+    for inst in seq:
+        d = dict(inst)
+        for key in ("alpha", "F", "Omega", "delta", "s", "q", "A", "L", "U", "w0"):
+            d[key] = torch.as_tensor(d[key], dtype=torch.float64, device=dev).contiguous()
+        seq_dev.append(d)
+    ff.solve_instance(seq_dev[0], tol=tol)
+    dt, _ = _timed(torch, lambda: [ff.solve_instance(d, tol=tol) for d in seq_dev], 1)
+    seq_ms = dt * 1e3 * len(nb) / len(seq_dev)
+    out["sequential_plain_256_fp64_est"] = {"batch_ms": seq_ms, "sample": "32 instances evenly spaced in batch order, scaled to 256",
+                                           "batched_fp64_speedup": seq_ms / out["batched_256_fp64"]["batch_ms"]}
+    # adjoint of the T = 10 workload: forward + backward
+    c4 = make_config(4)
+    P, n = c4["alpha"].shape
+    gW = np.zeros((P, n))
+    gW[-1] = c4["r"]
+    gWd = torch.as_tensor(gW, device=dev)
+
+    def fwd_bwd():
+        W, info, Y = ff.solve_instance(c4, tol=tol, return_dual=True)
+        ga, gs, gF, ainfo = ff.adjoint(c4, W, Y, gWd, omega=info.omega, tol=1e-9)
+        return info, ainfo
+    fwd_bwd()
+    dt, (finfo, ainfo) = _timed(torch, fwd_bwd, 1)
+    out["adjoint_T10_n2000"] = {"forward_plus_backward_ms": dt * 1e3, "forward_kernel_ms": finfo.ms_iter,
+                                "adjoint_kernel_ms": ainfo.ms_iter, "adjoint_iters": ainfo.iters,
+                                "adjoint_rel_residual": ainfo.rel_kkt}
+    return out
 
 
 def main():
@@ -183,6 +259,8 @@ def main():
         "status_all_ok": bool(all(i.status == 0 for i in infos)),
         "bytes_per_iter": bpi,
     }
+    if not a.no_extra and a.config == 1:
+        out["comparisons"] = comparisons(ff, torch, dev, dev_insts, a.tol, value)
     if not a.no_cpu:
         out["cpu_baseline"] = cpu_baseline(insts[0], a.tol, a.cpu_max_iter)
     print(json.dumps(out), flush=True)

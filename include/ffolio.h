@@ -140,7 +140,9 @@ ffo_status ffo_solve(int64_t n, int64_t k, int64_t m, int64_t T,
  * held fixed).  The problem arguments are those of the ffo_solve call that produced
  *   w_star [P][n] and y_star [P*m + P*k + T'*n]   (its w_out and y_out, device)
  * and grad_w [P][n] = dl/dW* (device).  omega: the solve's final primal weight
- * (ffo_info.omega; 0 selects 1), a conditioning hint only.  Outputs (device,
+ * (ffo_info.omega; 0 selects 1), a conditioning hint only: the adjoint iteration first
+ * runs with weight 1/omega for at most 100000 iterations and, if that does not converge,
+ * again from the start with weight omega (ffo_info.iters counts both).  Outputs (device,
  * caller-allocated): grad_alpha [P][n], grad_s [T'][n], grad_F [n][k] (may be NULL iff
  * k == 0).  Method: the solution is a fixed point z* = T(z*) of the iteration; with
  * J = dT/dz at z* (every nonsmooth piece frozen as T(z*) finds it: budget supports,

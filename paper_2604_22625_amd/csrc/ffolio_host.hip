@@ -327,7 +327,7 @@ ffo_status ffo_solve(int64_t n, int64_t k, int64_t m, int64_t T, const double* a
   int nwg = opt.workgroups > 0 ? opt.workgroups : (int)std::min<int64_t>(cus, (n + 63) / 64);
   nwg = std::max(1, std::min<int>(nwg, (int)n));
   nwg = std::min(nwg, cus);  // one workgroup per compute unit keeps the cooperative grid resident
-  const int nw = (int)((n + nwg - 1) / nwg);
+  int nw = (int)((n + nwg - 1) / nwg);
   nwg = (int)((n + nw - 1) / nw);
   ffo::DevControl c{};
   c.tol = opt.tol_rel_kkt; c.time_limit_s = opt.time_limit_s;
@@ -341,9 +341,21 @@ ffo_status ffo_solve(int64_t n, int64_t k, int64_t m, int64_t T, const double* a
   c.spec = P == 1 ? 1 : 0;
   if (const char* e = std::getenv("FFO_SPEC")) c.spec = std::atoi(e) ? 1 : 0;
   // LDS placement: constraint slice and per-asset state in LDS when they fit, in that
-  // order of preference (state first: it is touched in every phase).
+  // order of preference (state first: it is touched in every phase).  With the automatic
+  // workgroup count, more workgroups (smaller slices) are taken while that lets the
+  // constraint slice move into LDS.
   const size_t lds_cap = (size_t)std::min<size_t>(prop.sharedMemPerBlock, 160 * 1024);
   size_t lds = 0;
+  if (opt.workgroups == 0) {
+    for (int g = nwg; g <= std::min<int64_t>(cus, n); g = std::max(g + 1, g * 5 / 4)) {
+      const int w = (int)((n + g - 1) / g);
+      ffo::DevControl t = c;
+      t.nw = w; t.nwg = (int)((n + w - 1) / w); t.lds_k = 1; t.lds_state = 0;
+      if (ffo::solve_lds_bytes(p, t) <= lds_cap) { nw = w; nwg = t.nwg; break; }
+    }
+    c.nw = nw;
+    c.nwg = nwg;
+  }
   {
     const int order[4][2] = {{1, 1}, {0, 1}, {1, 0}, {0, 0}};
     bool placed = false;
@@ -544,7 +556,7 @@ ffo_status ffo_adjoint(int64_t n, int64_t k, int64_t m, int64_t T, const double*
   const size_t obF = carve(std::max<int64_t>(k, 1), 8), ocr = carve(1, 8), oC = carve(std::max<int64_t>(k * k, 1), 8);
   size_t ost[7];
   for (auto& o : ost) o = carve(Pn, 8);
-  size_t osc[6];
+  size_t osc[8];
   for (auto& o : osc) o = carve(Tpn, 8);
   const size_t ogG = carve((size_t)n * std::max<int64_t>(k, 1), 8);
   const size_t oxb = carve((size_t)3 * c.vmax, 8), obar = carve(1, 8);
@@ -585,16 +597,35 @@ ffo_status ffo_adjoint(int64_t n, int64_t k, int64_t m, int64_t T, const double*
   a.xs = D(ost[0]); a.xbar = D(ost[1]); a.bb = D(ost[2]); a.sx = D(ost[3]);
   a.lx = D(ost[4]); a.lx0 = D(ost[5]); a.Tlx = D(ost[6]);
   a.ysC = D(osc[0]); a.lyC = D(osc[1]); a.lyC0 = D(osc[2]); a.TlyC = D(osc[3]); a.nC = D(osc[4]); a.gsf = D(osc[5]);
+  a.tsg = D(osc[6]); a.trho = D(osc[7]);
   a.grad_alpha = grad_alpha; a.grad_s = grad_s; a.grad_G = D(ogG);
   a.xbuf = D(oxb); a.bar = (unsigned long long*)(B + obar); a.info = D(oinfo); a.status = (int32_t*)(B + ostat);
-  HIPCHK(hipMemsetAsync(B + oxb, 0, (size_t)3 * c.vmax * 8, hs));
-  HIPCHK(hipMemsetAsync(B + obar, 0, 8, hs));
-  HIPCHK(hipMemsetAsync(B + oinfo, 0, ffo::INFO_LEN * 8, hs));
-  HIPCHK(hipMemsetAsync(B + ostat, 0xff, 4, hs));
   HIPCHK(hipEventRecord(ws->ev[1], hs));
-  if (int e = ffo::launch_adjoint(p, a, c, omega > 0.0 ? omega : 1.0, stream, lds))
-    return fail(FFO_EDEVICE, std::string("cooperative launch of the adjoint kernel failed: ") +
-                                 hipGetErrorString((hipError_t)e));
+  // The transposed step swaps the roles of the primal and dual steps, and its natural
+  // weight is usually the reciprocal of the solve's (about 20x fewer iterations on the
+  // T = 10, n = 2000 market), but not always: that weight runs first under an iteration
+  // cap, and if it does not converge the solve's own weight runs from scratch.
+  const int64_t first_cap = std::min<int64_t>(opt.max_iter, 100000);
+  const double weights[2] = {omega > 0.0 ? 1.0 / omega : 1.0, omega > 0.0 ? omega : 1.0};
+  int32_t st_dev = -1;
+  int64_t used = 0;
+  for (int attempt = 0; attempt < 2; ++attempt) {
+    ffo::DevControl ca = c;
+    ca.max_iter = attempt == 0 ? first_cap : std::max<int64_t>(1, opt.max_iter - used);
+    HIPCHK(hipMemsetAsync(B + oxb, 0, (size_t)3 * c.vmax * 8, hs));
+    HIPCHK(hipMemsetAsync(B + obar, 0, 8, hs));
+    HIPCHK(hipMemsetAsync(B + oinfo, 0, ffo::INFO_LEN * 8, hs));
+    HIPCHK(hipMemsetAsync(B + ostat, 0xff, 4, hs));
+    if (int e = ffo::launch_adjoint(p, a, ca, weights[attempt], stream, lds))
+      return fail(FFO_EDEVICE, std::string("cooperative launch of the adjoint kernel failed: ") +
+                                   hipGetErrorString((hipError_t)e));
+    HIPCHK(hipMemcpyAsync(hflag, B + ostat, 4, hipMemcpyDeviceToHost, hs));
+    HIPCHK(hipMemcpyAsync(hinfo_buf, B + oinfo, ffo::INFO_LEN * 8, hipMemcpyDeviceToHost, hs));
+    HIPCHK(hipStreamSynchronize(hs));
+    st_dev = *hflag;
+    used += (int64_t)hinfo_buf[ffo::IX_ITERS];
+    if (st_dev != ffo::DS_NOT_CONVERGED || attempt == 1 || weights[0] == weights[1] || used >= opt.max_iter) break;
+  }
   if (k > 0 && ffo::launch_grad_F((int)n, (int)k, D(ogG), D(oC), grad_F, stream))
     return fail(FFO_EDEVICE, "grad_F kernel launch failed");
   HIPCHK(hipEventRecord(ws->ev[2], hs));
@@ -604,6 +635,7 @@ ffo_status ffo_adjoint(int64_t n, int64_t k, int64_t m, int64_t T, const double*
   float ms_setup = 0.f, ms_iter = 0.f;
   hipEventElapsedTime(&ms_setup, ws->ev[0], ws->ev[1]);
   hipEventElapsedTime(&ms_iter, ws->ev[1], ws->ev[2]);
+  hinfo_buf[ffo::IX_ITERS] = (double)used;   // both attempts
   const ffo_status st = status_of(*hflag);
   if (st == FFO_NOT_CONVERGED) g_err = "adjoint iteration limit reached";
   else if (st == FFO_NUMERIC) g_err = "NaN or Inf in the adjoint iteration";
@@ -867,9 +899,23 @@ ffo_status ffo_solve_batched(int64_t B, const int64_t* n_b, int64_t n_max, int64
     fill_info(&infos[b], st, hinfo + (size_t)b * ffo::INFO_LEN, ms_setup, ms_iter);
     if (rank(st) > rank(worst)) worst = st;
   }
-  if (opt.verbose)
+  if (opt.verbose) {
     std::fprintf(stderr, "[ffo batch] B %lld launches %zu resident %d (occupancy %d) lds %zu | setup %.3f ms solve %.3f ms\n",
                  (long long)B, chunks.size(), W, occ, lds_cap, ms_setup, ms_iter);
+    int64_t slow = 0;
+    for (int64_t b = 1; b < B; ++b)
+      if (hinfo[(size_t)b * ffo::INFO_LEN + ffo::IX_T_ITER] > hinfo[(size_t)slow * ffo::INFO_LEN + ffo::IX_T_ITER]) slow = b;
+    const double* h = hinfo + (size_t)slow * ffo::INFO_LEN;
+    std::fprintf(stderr,
+                 "[ffo batch] slowest instance %lld: n %lld team %d xmode %d iters %.0f spec_miss %.0f exchanges %.0f "
+                 "| t_iter %.3f ms t_check %.3f ms t_wait %.3f ms | A %.3f B %.3f C %.3f D %.3f pre %.3f read %.3f "
+                 "| B1 %.3f (stats %.3f) B2 %.3f B3 %.3f ms\n",
+                 (long long)slow, (long long)n_b[slow], hCt[slow].nwg, hCt[slow].xmode, h[ffo::IX_ITERS],
+                 h[ffo::IX_SPEC_MISS], h[ffo::IX_EXCHANGES], h[ffo::IX_T_ITER] * 1e3, h[ffo::IX_T_CHECK] * 1e3,
+                 h[ffo::IX_T_WAIT] * 1e3, h[ffo::IX_T_PHA] * 1e3, h[ffo::IX_T_PHB] * 1e3, h[ffo::IX_T_PHC] * 1e3,
+                 h[ffo::IX_T_PHD] * 1e3, h[ffo::IX_T_PRE] * 1e3, h[ffo::IX_T_READ] * 1e3, h[ffo::IX_T_B1] * 1e3,
+                 h[ffo::IX_T_B1S] * 1e3, h[ffo::IX_T_B2] * 1e3, h[ffo::IX_T_B3] * 1e3);
+  }
   if (worst == FFO_NOT_CONVERGED) g_err = "iteration limit reached for at least one instance";
   else if (worst == FFO_TIMEOUT) g_err = "time limit reached for at least one instance";
   else if (worst == FFO_NUMERIC) g_err = "NaN or Inf in an FP64 check of at least one instance";

@@ -81,6 +81,7 @@ struct AdjState {
   double *lx, *lx0, *Tlx;               // [P][n] adjoint primal part, anchor, its image
   double *ysC, *lyC, *lyC0, *TlyC;      // [Tp][n] y_C*, adjoint trade part, anchor, image
   double *nC, *gsf;                     // [Tp][n] trade prox derivative factors
+  double *tsg, *trho;                   // [Tp][n] sign(z) outside the spread dead zone (else 0), |prox(z)|
   double *grad_alpha;                   // [P][n]
   double *grad_s;                       // [Tp][n]
   double *grad_G;                       // [n][k] gradient w.r.t. G = F C

@@ -373,8 +373,9 @@ __device__ void kty_all(const Ctx& c, const SV& v, const ldbl* y, int P, int nr,
   __syncthreads();
 }
 
-// Row products for rows read from device memory: lanes run over assets (coalesced
-// loads), each wave takes RB rows at a time and reduces them with DPP; emit as below.
+// Row products for long asset slices: lanes run over assets (coalesced loads when the
+// rows live in device memory), each wave takes RB rows at a time and reduces them with
+// DPP; emit as below.  Row bases and scales are resolved once per pass.
 template <int NX, class SV, class F>
 __device__ void rows_prod_wide(const Ctx& c, const SV& v, const ldbl* x1, const ldbl* x2, int nw, int P, int nr,
                                F emit) {
@@ -382,21 +383,41 @@ __device__ void rows_prod_wide(const Ctx& c, const SV& v, const ldbl* x1, const 
   const int lane = c.tid & 63, wave = c.tid >> 6, ntot = P * nr;
   for (int base = wave * RB; base < ntot; base += NWAVE * RB) {
     double a[RB][NX];
+    int jr[RB], tr[RB];
 #pragma unroll
-    for (int r = 0; r < RB; ++r)
+    for (int r = 0; r < RB; ++r) {
+      const int e = min(base + r, ntot - 1);
+      tr[r] = e / nr;
+      jr[r] = e - tr[r] * nr;
 #pragma unroll
       for (int u = 0; u < NX; ++u) a[r][u] = 0.0;
-    for (int li = lane; li < c.nwa; li += 64) {
+    }
+    if constexpr (SV::KLDS) {
+      for (int li = lane; li < c.nwa; li += 64) {
 #pragma unroll
-      for (int r = 0; r < RB; ++r) {
-        const int e = base + r;
-        if (e < ntot) {
-          const int t = e / nr, j = e - t * nr;
-          const double kv = v.Kat(j, li);
-          a[r][0] = fma(kv, x1[t * nw + li], a[r][0]);
-          if (NX > 1) a[r][NX - 1] = fma(kv, x2[t * nw + li], a[r][NX - 1]);
+        for (int r = 0; r < RB; ++r) {
+          const double kv = v.Kat(jr[r], li);
+          a[r][0] = fma(kv, x1[tr[r] * nw + li], a[r][0]);
+          if (NX > 1) a[r][NX - 1] = fma(kv, x2[tr[r] * nw + li], a[r][NX - 1]);
         }
       }
+    } else {
+      // unscaled rows from device memory; the row scale is applied to the sums
+      const double* rp[RB];
+#pragma unroll
+      for (int r = 0; r < RB; ++r) rp[r] = v.Kg + (size_t)jr[r] * v.p->ldk + v.i0;
+      for (int li = lane; li < c.nwa; li += 64) {
+#pragma unroll
+        for (int r = 0; r < RB; ++r) {
+          const double kv = rp[r][li];
+          a[r][0] = fma(kv, x1[tr[r] * nw + li], a[r][0]);
+          if (NX > 1) a[r][NX - 1] = fma(kv, x2[tr[r] * nw + li], a[r][NX - 1]);
+        }
+      }
+#pragma unroll
+      for (int r = 0; r < RB; ++r)
+#pragma unroll
+        for (int u = 0; u < NX; ++u) a[r][u] *= v.ks[jr[r]];
     }
 #pragma unroll
     for (int r = 0; r < RB; ++r) {
@@ -437,12 +458,14 @@ __device__ void rows_prod_lds(const Ctx& c, const SV& v, const ldbl* x1, const l
   }
 }
 
-// Rows in LDS: four lanes per row; rows in device memory: the coalesced wide form.
+// Short slices (the usual case, rows in LDS or not): four lanes per row.  Long slices
+// of rows in device memory (batched teams, very large n): the coalesced wide form,
+// whose per-row wave reductions pay off once each lane has several assets.
 template <int NX, class SV, class F>
 __device__ __forceinline__ void rows_prod(const Ctx& c, const SV& v, const ldbl* x1, const ldbl* x2, int nw, int P,
                                           int nr, F emit) {
-  if constexpr (SV::KLDS) rows_prod_lds<NX>(c, v, x1, x2, nw, P, nr, emit);
-  else rows_prod_wide<NX>(c, v, x1, x2, nw, P, nr, emit);
+  if (!SV::KLDS && c.nwa > 512) rows_prod_wide<NX>(c, v, x1, x2, nw, P, nr, emit);
+  else rows_prod_lds<NX>(c, v, x1, x2, nw, P, nr, emit);
 }
 
 // Trade-row adjoint for asset li, period t: dc (drC_t yC_t - drC_{t+1} yC_{t+1}).
@@ -539,19 +562,54 @@ __device__ __forceinline__ double cand(double cen, double hw, int q) {
 __device__ void period_stats(Ctx& c, const ldbl* absb, const ldbl* inva, int nw, const ldbl* cen,
                              const ldbl* hw, int off0) {
   const int lane = c.tid & 63, wave = c.tid >> 6, g = lane >> 3, sub = lane & 7;
-  for (int t = wave; t < c.P; t += NWAVE) {
-    const double cq = cand(cen[t], hw[t], g);
+  // waves per period: all of them share one period's assets when there are few periods
+  const int WP = c.P >= NWAVE ? 1 : (c.P >= NWAVE / 2 ? 2 : NWAVE);
+  const int pw = wave % WP, tw = wave / WP, groups = NWAVE / WP;
+  static_assert(NWAVE * 32 <= RED_OUT, "reduction scratch");
+  for (int t0 = 0; t0 < c.P; t0 += groups) {
+    const int t = t0 + tw;
+    const bool act = tw < groups && t < c.P;
     double S = 0.0, A0 = 0.0, N = 0.0, S0 = 0.0, mx = 0.0;
-    for (int li = sub; li < c.nwa; li += 8) {
-      const double ab = absb[t * nw + li], ia = inva[t * nw + li];
-      S0 = fma(ab, ia, S0);
-      mx = fmax(mx, ab);
-      if (ab > cq) { S = fma(ab - cq, ia, S); A0 += ia; N += 1.0; }
+    if (act) {
+      const double cq = cand(cen[t], hw[t], g);
+      for (int li = pw * 8 + sub; li < c.nwa; li += 8 * WP) {
+        const double ab = absb[t * nw + li], ia = inva[t * nw + li];
+        S0 = fma(ab, ia, S0);
+        mx = fmax(mx, ab);
+        if (ab > cq) { S = fma(ab - cq, ia, S); A0 += ia; N += 1.0; }
+      }
     }
     S = sum8(S); A0 = sum8(A0); N = sum8(N); S0 = sum8(S0); mx = max8(mx);
-    const int off = off0 + STW * t;
-    if (sub == 0) { put(c, off + 2 + 3 * g, S); put(c, off + 3 + 3 * g, A0); put(c, off + 4 + 3 * g, N); }
-    if (lane == 0) { put(c, off, S0); put_max(c, off + 1, mx); }
+    if (WP == 1) {
+      if (act) {
+        const int off = off0 + STW * t;
+        if (sub == 0) { put(c, off + 2 + 3 * g, S); put(c, off + 3 + 3 * g, A0); put(c, off + 4 + 3 * g, N); }
+        if (lane == 0) { put(c, off, S0); put_max(c, off + 1, mx); }
+      }
+    } else {
+      // combine the WP waves of each period through LDS (fixed order)
+      // per wave: [4g, 4g+3) candidate g's (S, A0, cnt); slot 3 = S(0), slot 7 = max |b|
+      if (sub == 0) {
+        ldbl* r = c.red + wave * 32 + 4 * g;
+        r[0] = S; r[1] = A0; r[2] = N;
+        if (g == 0) r[3] = S0;
+        if (g == 1) r[3] = mx;
+      }
+      __syncthreads();
+      if (pw == 0 && act && sub == 0) {
+        double s3[3] = {0.0, 0.0, 0.0}, s0 = 0.0, m0 = 0.0;
+        for (int w = wave; w < wave + WP; ++w) {
+          const ldbl* r = c.red + w * 32 + 4 * g;
+          s3[0] += r[0]; s3[1] += r[1]; s3[2] += r[2];
+          s0 += c.red[w * 32 + 3];
+          m0 = fmax(m0, (double)c.red[w * 32 + 7]);
+        }
+        const int off = off0 + STW * t;
+        put(c, off + 2 + 3 * g, s3[0]); put(c, off + 3 + 3 * g, s3[1]); put(c, off + 4 + 3 * g, s3[2]);
+        if (g == 0) { put(c, off, s0); put_max(c, off + 1, m0); }
+      }
+      __syncthreads();
+    }
   }
 }
 
@@ -1451,6 +1509,7 @@ __global__ __launch_bounds__(TB) void k_adjoint(DevProblem p, AdjState a, DevCon
   const auto xs = G(a.xs), xbar = G(a.xbar), bb = G(a.bb), sx = G(a.sx);
   const auto lx = G(a.lx), lx0 = G(a.lx0), Tlx = G(a.Tlx);
   const auto ysC = G(a.ysC), lyC = G(a.lyC), lyC0 = G(a.lyC0), TlyC = G(a.TlyC), nC = G(a.nC), gsf = G(a.gsf);
+  const auto tsg = G(a.tsg), trho = G(a.trho);
   const Arr<true, double> mCv{mC, nw, 0}, nbv{xv4, nw, 0};
 
   for (int j = c.tid; j < nr; j += TB) ks[j] = p.kscaled ? 1.0 : p.dr[j];
@@ -1537,7 +1596,7 @@ __global__ __launch_bounds__(TB) void k_adjoint(DevProblem p, AdjState a, DevCon
   __syncthreads();
 
   {
-    const double tau = sc->tau, sigma = sc->sigma;
+    double tau = sc->tau, sigma = sc->sigma;
     // ---- one step T(z*): the pieces the linearisation freezes
     kty_all(c, V, ys, P, nr, nw, xv1);
     for (int e = c.tid; e < P * c.nwa; e += TB) {
@@ -1577,40 +1636,21 @@ __global__ __launch_bounds__(TB) void k_adjoint(DevProblem p, AdjState a, DevCon
       const double xp = in ? sgn(b) * (ab - mu[t]) * ia / dci : 0.0;
       const double xb = 2.0 * xp - xs(t, li);
       xbar(t, li) = xb;
-      sx(t, li) = in ? sgn(b) * ia : 0.0;
+      bb(t, li) = in ? sgn(b) : 0.0;     // frozen support and signs
       xv1[t * nw + li] = xb;
-      xv2[t * nw + li] = in ? sgn(b) * ia / dci : 0.0;
-      xv3[t * nw + li] = in ? ia : 0.0;
     }
     __syncthreads();
-    {
-      const int lane = c.tid & 63, wave = c.tid >> 6;
-      for (int t = wave; t < P; t += NWAVE) {
-        double v = 0.0;
-        for (int li = lane; li < c.nwa; li += 64) v += xv3[t * nw + li];
-        v = wave_sum(v);
-        if (lane == 0) put(c, 2 * P * nr + t, v);
-      }
-    }
-    rows_prod<2>(c, V, xv1, xv2, nw, P, nr, [&](int e, const double* q) {
-      put(c, e, q[0]);
-      put(c, P * nr + e, q[1]);
-    });
-    if (!xsync(c, 2 * P * nr + P)) goto adj_fail;
-    for (int e = c.tid; e < P * nr; e += TB) {
+    rows_prod<1>(c, V, xv1, xv1, nw, P, nr, [&](int e, const double* q) { put(c, e, q[0]); });
+    if (!xsync(c, P * nr)) goto adj_fail;
+    for (int e = c.tid; e < P * nr; e += TB) {   // frozen clipped exposure rows
       const int j = e % nr;
       const double vs = ys[e] + sigma * tot[e];
       if (j < m) {
         const double sd = sigma * p.dr[j], z = vs / sd;
         nR[e] = (z > p.L[j] && z < p.U[j]) ? 0.0 : 1.0;
-      } else {
-        const double drj = p.dr[j];
-        nR[e] = 2.0 * p.g1 / (sigma * drj * drj + 2.0 * p.g1);
       }
-      Kr[e] = tot[P * nr + e];
     }
-    for (int t = c.tid; t < P; t += TB) cS[t] = tot[2 * P * nr + t];
-    for (int e = c.tid; e < Tp * c.nwa; e += TB) {
+    for (int e = c.tid; e < Tp * c.nwa; e += TB) {   // frozen dead zones and trade sizes
       const int t = e / c.nwa, li = e % c.nwa;
       const double kc = kx_trade(V, xbar, t, li);
       const double vs = ysC(t, li) + sigma * kc;
@@ -1618,14 +1658,9 @@ __global__ __launch_bounds__(TB) void k_adjoint(DevProblem p, AdjState a, DevCon
       const double z = vs / (sigma * drc) - trade_offset(V, t, li);
       const double tp = 1.0 / (sigma * drc * drc);
       const double ca = V.ca(t, li), cb = V.cb(t, li);
-      double dp = 0.0;
-      if (fabs(z) - tp * ca > 0.0) {
-        const double rho = fabs(prox_cost(z, tp, ca, cb, p.d));
-        if (p.d == 2.0) dp = 1.0 / (1.0 + 2.0 * tp * cb);
-        else if (rho > 0.0) dp = 1.0 / (1.0 + tp * cb * p.d * (p.d - 1.0) * pow(rho, p.d - 2.0));
-      }
-      nC(t, li) = 1.0 - dp;
-      gsf(t, li) = p.g2 * sgn(z) * dp / drc;
+      const bool live = fabs(z) - tp * ca > 0.0;
+      tsg(t, li) = live ? sgn(z) : 0.0;
+      trho(t, li) = live ? fabs(prox_cost(z, tp, ca, cb, p.d)) : 0.0;
       lyC(t, li) = 0.0; lyC0(t, li) = 0.0; TlyC(t, li) = 0.0;
     }
     for (int e = c.tid; e < P * c.nwa; e += TB) {
@@ -1633,6 +1668,59 @@ __global__ __launch_bounds__(TB) void k_adjoint(DevProblem p, AdjState a, DevCon
       lx(t, li) = 0.0; lx0(t, li) = 0.0; Tlx(t, li) = 0.0;
     }
     __syncthreads();
+
+    // Step-size dependent factors of J for the current (tau, sigma), the pieces held
+    // fixed: sx = 1{S} sign(b) / a, c_S = sum_S 1/a, K~ (sx / dc), the factor-row and
+    // trade-row prox derivatives.  One exchange.
+    auto refactor = [&]() -> bool {
+      tau = sc->tau;
+      sigma = sc->sigma;
+      for (int e = c.tid; e < P * c.nwa; e += TB) {
+        const int t = e / c.nwa, li = e % c.nwa;
+        const double dci = V.dc(0, li);
+        const double ia = 1.0 / (1.0 / (tau * dci * dci) + V.arisk(0, li));
+        const double sv = bb(t, li) * ia;
+        sx(t, li) = sv;
+        xv2[t * nw + li] = sv / dci;
+        xv3[t * nw + li] = fabs(sv);
+      }
+      __syncthreads();
+      {
+        const int lane = c.tid & 63, wave = c.tid >> 6;
+        for (int t = wave; t < P; t += NWAVE) {
+          double v = 0.0;
+          for (int li = lane; li < c.nwa; li += 64) v += xv3[t * nw + li];
+          v = wave_sum(v);
+          if (lane == 0) put(c, P * nr + t, v);
+        }
+      }
+      rows_prod<1>(c, V, xv2, xv2, nw, P, nr, [&](int e, const double* q) { put(c, e, q[0]); });
+      if (!xsync(c, P * nr + P)) return false;
+      for (int e = c.tid; e < P * nr; e += TB) {
+        const int j = e % nr;
+        Kr[e] = tot[e];
+        if (j >= m) {
+          const double drj = p.dr[j];
+          nR[e] = 2.0 * p.g1 / (sigma * drj * drj + 2.0 * p.g1);
+        }
+      }
+      for (int t = c.tid; t < P; t += TB) cS[t] = tot[P * nr + t];
+      for (int e = c.tid; e < Tp * c.nwa; e += TB) {
+        const int t = e / c.nwa, li = e % c.nwa;
+        const double drc = V.drC(t, li), tp = 1.0 / (sigma * drc * drc), cb = V.cb(t, li);
+        const double rho = trho(t, li), sg = tsg(t, li);
+        double dp = 0.0;
+        if (sg != 0.0) {
+          if (p.d == 2.0) dp = 1.0 / (1.0 + 2.0 * tp * cb);
+          else if (rho > 0.0) dp = 1.0 / (1.0 + tp * cb * p.d * (p.d - 1.0) * pow(rho, p.d - 2.0));
+        }
+        nC(t, li) = 1.0 - dp;
+        gsf(t, li) = p.g2 * sg * dp / drc;
+      }
+      __syncthreads();
+      return true;
+    };
+    if (!refactor()) goto adj_fail;
 
     // ---- adjoint iteration
     // one application of lambda -> J^T lambda + g; leaves nu in xv3 (per owned (t, i)), mu_y
@@ -1709,42 +1797,57 @@ __global__ __launch_bounds__(TB) void k_adjoint(DevProblem p, AdjState a, DevCon
       if (!apply()) goto adj_fail;
       const bool check = ((sc->it + 1) % ctl.check_every == 0) || (sc->it + 1 >= ctl.max_iter);
       if (check) {
-        double v[2] = {0.0, 0.0};
+        // [residual^2, non-finite count, |T lambda_x - anchor|^2, |T lambda_y - anchor|^2]
+        double v[4] = {0.0, 0.0, 0.0, 0.0};
         for (int e = c.tid; e < P * c.nwa; e += TB) {
           const int t = e / c.nwa, li = e % c.nwa;
-          const double d = Tlx(t, li) - lx(t, li);
+          const double d = Tlx(t, li) - lx(t, li), dl = Tlx(t, li) - lx0(t, li);
           v[0] = fma(d, d, v[0]);
+          v[2] = fma(dl, dl, v[2]);
           if (!isfinite(d)) v[1] += 1.0;
         }
         for (int e = c.tid; e < Tp * c.nwa; e += TB) {
           const int t = e / c.nwa, li = e % c.nwa;
-          const double d = TlyC(t, li) - lyC(t, li);
+          const double d = TlyC(t, li) - lyC(t, li), dl = TlyC(t, li) - lyC0(t, li);
           v[0] = fma(d, d, v[0]);
+          v[3] = fma(dl, dl, v[3]);
           if (!isfinite(d)) v[1] += 1.0;
         }
         if (c.wg == 0)
-          for (int e = c.tid; e < P * nr; e += TB) { const double d = Tly[e] - ly[e]; v[0] = fma(d, d, v[0]); }
-        wg_sum<2>(c, v);
-        if (c.tid < 2) put(c, c.tid, red[RED_OUT + c.tid]);
+          for (int e = c.tid; e < P * nr; e += TB) {
+            const double d = Tly[e] - ly[e], dl = Tly[e] - ly0[e];
+            v[0] = fma(d, d, v[0]);
+            v[3] = fma(dl, dl, v[3]);
+          }
+        wg_sum<4>(c, v);
+        if (c.tid < 4) put(c, c.tid, red[RED_OUT + c.tid]);
         if (c.wg == 0 && c.tid == 0) {
           const double el = (double)(wall_clock64() - t_start) / ctl.wall_hz;
-          put(c, 2, el > ctl.time_limit_s ? 1.0 : 0.0);
+          put(c, 4, el > ctl.time_limit_s ? 1.0 : 0.0);
         }
-        if (!xsync(c, 3)) goto adj_fail;
+        if (!xsync(c, 5)) goto adj_fail;
         const double res = sqrt(tot[0]) / fmax(sc->gnorm, 1e-300);
         if (c.tid == 0) {
           sc->checks++;
           sc->restart = 0;
-          if (c.wg == 0) { a.info[IX_RELKKT] = res; a.info[IX_FPR] = res; }
+          if (c.wg == 0) {
+            a.info[IX_RELKKT] = res;
+            a.info[IX_FPR] = res;
+            if (ctl.verbose >= 2)
+              printf("[ffo adjoint] it %lld res %.3e omega %.3e |dlx| %.3e |dly| %.3e restarts %lld\n", sc->it + 1, res,
+                     sc->omega, sqrt(tot[2]), sqrt(tot[3]), sc->restarts);
+          }
           if (tot[1] > 0.0 || !isfinite(res)) { sc->done = 1; sc->status = DS_NUMERIC; }
           else if (res <= ctl.tol) { sc->done = 1; sc->status = DS_OK; }
-          else if (tot[2] > 0.0) { sc->done = 1; sc->status = DS_TIMEOUT; }
+          else if (tot[4] > 0.0) { sc->done = 1; sc->status = DS_TIMEOUT; }
           else if (sc->it + 1 >= ctl.max_iter) { sc->done = 1; sc->status = DS_NOT_CONVERGED; }
           else {
             if (sc->r0 < 0.0) sc->r0 = res;
             const bool rs = (res <= ctl.r_suff * sc->r0) || (res <= ctl.r_nec * sc->r0 && res > sc->rprev) ||
                             ((double)(sc->kk + 1) >= ctl.r_art * (double)(sc->it + 1));
             sc->rprev = res;
+            // the weight stays fixed: unlike the solve's, this fixed point moves with
+            // (tau, sigma), so a new weight would discard the progress made
             if (rs) { sc->r0 = res; sc->rprev = INFINITY; sc->restarts++; sc->restart = 1; }
           }
         }
@@ -1916,9 +2019,9 @@ int adjoint_vmax(const DevProblem& p) {
   const int P = p.P, nr = p.nr;
   int v = STW * P;
   v = std::max(v, 3 * P * MSC);
-  v = std::max(v, 2 * P * nr + P);
+  v = std::max(v, P * nr + P);
   v = std::max(v, 2 + P * nr);
-  v = std::max(v, 4);
+  v = std::max(v, 8);
   return (v + 63) / 64 * 64;
 }
 
