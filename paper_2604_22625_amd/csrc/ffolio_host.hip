@@ -340,6 +340,8 @@ ffo_status ffo_solve(int64_t n, int64_t k, int64_t m, int64_t T, const double* a
   c.vmax = ffo::solve_vmax(p);
   c.spec = P == 1 ? 1 : 0;
   if (const char* e = std::getenv("FFO_SPEC")) c.spec = std::atoi(e) ? 1 : 0;
+  c.lists = 1;
+  if (const char* e = std::getenv("FFO_LISTS")) c.lists = std::atoi(e) ? 1 : 0;
   // LDS placement: constraint slice and per-asset state in LDS when they fit, in that
   // order of preference (state first: it is touched in every phase).  With the automatic
   // workgroup count, more workgroups (smaller slices) are taken while that lets the
@@ -380,6 +382,7 @@ ffo_status ffo_solve(int64_t n, int64_t k, int64_t m, int64_t T, const double* a
   for (auto& o : osc) o = carve(Tpn, 8);
   const size_t nxbuf = (size_t)std::max(2 * nwg, 3) * c.vmax;
   const size_t oxb = carve(nxbuf, 8), obar = carve(1, 8);
+  const size_t oblist = carve(c.lists ? (size_t)2 * nwg * P * ffo::LIST_W : 1, 8);
   const size_t oinfo = carve(ffo::INFO_LEN, 8), ostat = carve(1, 4), oflag = carve(1, 4);
   const size_t total = off;
   const size_t host_bytes = align_up((size_t)std::max<int64_t>(k * k, 1) * 8) * 2 + 4096;
@@ -430,6 +433,7 @@ ffo_status ffo_solve(int64_t n, int64_t k, int64_t m, int64_t T, const double* a
   sv.bb = D(ost[3]); sv.aa = D(ost[4]); sv.vpow = D(ost[5]);
   sv.ysC = D(osc[0]); sv.ys0C = D(osc[1]); sv.TysC = D(osc[2]);
   sv.xbuf = D(oxb); sv.bar = (unsigned long long*)(B + obar);
+  sv.blist = c.lists ? D(oblist) : nullptr;
   sv.info = D(oinfo); sv.status = (int32_t*)(B + ostat); sv.w_out = w_out; sv.y_out = y_out;
   HIPCHK(hipMemsetAsync(B + oxb, 0, nxbuf * 8, hs));
   HIPCHK(hipMemsetAsync(B + obar, 0, 8, hs));

@@ -50,6 +50,7 @@ struct DevState {
   double *bb, *aa;                    // [P][n] prox inputs b and a of the current step
   double *vpow;                       // [P][n] power-iteration vector, later scratch
   double *xbuf;                       // exchange buffer (see kernel)
+  double *blist;                      // [2][nwg][P][LIST_W] breakpoint lists (see kernel)
   unsigned long long* bar;            // barrier counter (zeroed by the host)
   double* info;                       // [INFO_LEN] result record written by workgroup 0
   int32_t* status;                    // [1]
@@ -68,7 +69,13 @@ struct DevControl {
   int32_t prec;         // PREC_FP64 or PREC_FP32: stored type of the iterates and LDS copies
   uint32_t spin_limit;
   double wall_hz;       // rate of the device wall clock
+  int32_t lists;        // 1: publish breakpoint lists with the statistics (blist non-null)
 };
+
+// Breakpoint lists: per workgroup and period, a count and LIST_CAP entries
+// (|b|, 1/a, global asset index, sign(b)/(a dc)).
+constexpr int LIST_CAP = 8;
+constexpr int LIST_W = 1 + 4 * LIST_CAP;
 
 enum Prec { PREC_FP64 = 0, PREC_FP32 = 1 };
 

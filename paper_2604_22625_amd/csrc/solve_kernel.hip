@@ -185,8 +185,9 @@ __device__ __forceinline__ void put_max(const Ctx& c, int j, double v) {
 
 // Barrier + reduction of the V published values into c.tot (LDS).  Returns false when
 // the bounded wait expired.
-__device__ bool xsync(Ctx& c, int V) {
+__device__ __forceinline__ bool xsync(Ctx& c, int V) {
   if (c.xmode == XM_LOCAL) {   // one workgroup: the slot already holds the totals
+    __builtin_amdgcn_s_waitcnt(0);   // device-memory stores of this exchange (lists) are complete
     __syncthreads();
     const ldbl* cur = c.lslot + (size_t)(c.epoch % 3) * c.vmax;
     ldbl* nxt = c.lslot + (size_t)((c.epoch + 2) % 3) * c.vmax;
@@ -248,7 +249,7 @@ __device__ bool xsync(Ctx& c, int V) {
 // Fixed-order workgroup sum of NV per-thread values; result in red[RED_OUT + q] (LDS),
 // valid for every thread after the call.  Uses red[0 .. NWAVE*NV), NWAVE*NV <= RED_OUT.
 template <int NV>
-__device__ void wg_sum(const Ctx& c, double (&v)[NV]) {
+__device__ __forceinline__ void wg_sum(const Ctx& c, double (&v)[NV]) {
   static_assert(NWAVE * NV <= RED_OUT && NV <= RED_MAX - RED_OUT, "reduction scratch");
   ldbl* out = c.red + RED_OUT;
   const int lane = c.tid & 63, wave = c.tid >> 6;
@@ -267,7 +268,7 @@ __device__ void wg_sum(const Ctx& c, double (&v)[NV]) {
   __syncthreads();
 }
 
-__device__ double wg_max(const Ctx& c, double x) {
+__device__ __forceinline__ double wg_max(const Ctx& c, double x) {
   x = wave_max(x);
   if ((c.tid & 63) == 0) c.red[RED_MAX + (c.tid >> 6)] = x;
   __syncthreads();
@@ -345,7 +346,7 @@ __device__ __forceinline__ double kcol_dot(const SV& v, const ldbl* y, int li, i
 // (LDS).  Small slices split the rows over 2 or 4 thread groups with partials in
 // red[0, TB).  All threads call; synchronised on return.
 template <class SV>
-__device__ void kty_all(const Ctx& c, const SV& v, const ldbl* y, int P, int nr, int nw, ldbl* out) {
+__device__ __forceinline__ void kty_all(const Ctx& c, const SV& v, const ldbl* y, int P, int nr, int nw, ldbl* out) {
   const int ne = P * c.nwa;
   if (ne == 0) { __syncthreads(); return; }
   const int G = ne <= TB / 4 ? 4 : (ne <= TB / 2 ? 2 : 1);
@@ -377,7 +378,7 @@ __device__ void kty_all(const Ctx& c, const SV& v, const ldbl* y, int P, int nr,
 // rows live in device memory), each wave takes RB rows at a time and reduces them with
 // DPP; emit as below.  Row bases and scales are resolved once per pass.
 template <int NX, class SV, class F>
-__device__ void rows_prod_wide(const Ctx& c, const SV& v, const ldbl* x1, const ldbl* x2, int nw, int P, int nr,
+__device__ __forceinline__ void rows_prod_wide(const Ctx& c, const SV& v, const ldbl* x1, const ldbl* x2, int nw, int P, int nr,
                                F emit) {
   constexpr int RB = 8;
   const int lane = c.tid & 63, wave = c.tid >> 6, ntot = P * nr;
@@ -433,7 +434,7 @@ __device__ void rows_prod_wide(const Ctx& c, const SV& v, const ldbl* x1, const 
 // emit(e, a) with a[q] = sum_li K~[j][li] xq[t*nw + li] (x1, and x2 when NX = 2; LDS).
 // All threads call (the lane shuffles need full waves).
 template <int NX, class SV, class F>
-__device__ void rows_prod_lds(const Ctx& c, const SV& v, const ldbl* x1, const ldbl* x2, int nw, int P, int nr,
+__device__ __forceinline__ void rows_prod_lds(const Ctx& c, const SV& v, const ldbl* x1, const ldbl* x2, int nw, int P, int nr,
                               F emit) {
   const int q = c.tid & 3, ntot = P * nr;
   for (int base = 0; base < ntot; base += TB / 4) {
@@ -559,7 +560,7 @@ __device__ __forceinline__ double cand(double cen, double hw, int q) {
 // A0(c) = sum_{|b| > c} 1/a and cnt(c) = #{|b| > c}.  absb/inva: LDS [P][nw] with |b|
 // and 1/a of the owned assets.  One wave per period, eight lanes per candidate.  The
 // caller sets the max-combined range and synchronises before the exchange.
-__device__ void period_stats(Ctx& c, const ldbl* absb, const ldbl* inva, int nw, const ldbl* cen,
+__device__ __forceinline__ void period_stats(Ctx& c, const ldbl* absb, const ldbl* inva, int nw, const ldbl* cen,
                              const ldbl* hw, int off0) {
   const int lane = c.tid & 63, wave = c.tid >> 6, g = lane >> 3, sub = lane & 7;
   // waves per period: all of them share one period's assets when there are few periods
@@ -620,14 +621,16 @@ __device__ void period_stats(Ctx& c, const ldbl* absb, const ldbl* inva, int nw,
 //   2 = mu = 0 while the central pair was not [0, 0],
 //   0 = multisection needed, root in the central pair (breakpoints inside it),
 //   3 = multisection needed, root outside the central pair.
-// For 0 and 3, lo/hi receive a bracket with S(lo) >= 1 >= S(hi).
+// For 0 and 3, lo/hi receive a bracket with S(lo) >= 1 >= S(hi), and bits 4 and up of the
+// result hold qs + 1, where lo = c_qs is the bracket's lower candidate (qs = -1: lo is 0 or
+// the bracket is [0, max |b|]).
 // Called by a whole wave (uniform arguments; the candidate tests use one lane each).
 __device__ int bracket_decide(const ldbl* st, double cen, double hw, double& lo, double& hi, double& mu) {
   const double S0 = st[0], maxb = st[1];
   if (S0 <= 1.0) { mu = 0.0; return (cen + hw <= 0.0) ? 1 : 2; }
   const int lane = threadIdx.x & 63;
   const unsigned long long ge = __ballot(lane < NC && st[2 + 3 * (lane < NC ? lane : 0)] >= 1.0);
-  const int qs = ge ? 63 - __clzll((long long)ge) : -1;   // S is non-increasing: {q : S(c_q) >= 1} = [0, qs]
+  int qs = ge ? 63 - __clzll((long long)ge) : -1;   // S is non-increasing: {q : S(c_q) >= 1} = [0, qs]
   double a, b;
   if (qs < 0) { a = 0.0; b = cand(cen, hw, 0); }
   else if (qs == NC - 1) { a = cand(cen, hw, NC - 1); b = maxb; }
@@ -636,15 +639,15 @@ __device__ int bracket_decide(const ldbl* st, double cen, double hw, double& lo,
     mu = fmin(fmax(a + (st[2 + 3 * qs] - 1.0) / st[3 + 3 * qs], a), b);
     return qs == 3 ? 1 : 4;
   }
-  if (!(b >= a)) { a = 0.0; b = maxb; }
+  if (!(b >= a)) { a = 0.0; b = maxb; qs = -1; }
   lo = a;
   hi = b;
-  return qs == 3 ? 0 : 3;
+  return (qs == 3 ? 0 : 3) | ((qs + 1) << 4);
 }
 
 // Multisection for the periods with need[t] != 0 (caller synchronised; S(lo) >= 1 >= S(hi)):
 // MSC candidates per round, TB / MSC lanes per candidate.  absb/inva as in period_stats.
-__device__ bool multisect(Ctx& c, int P, const ldbl* absb, const ldbl* inva, int nw, lint* need, ldbl* lo,
+__device__ __forceinline__ bool multisect(Ctx& c, int P, const ldbl* absb, const ldbl* inva, int nw, lint* need, ldbl* lo,
                           ldbl* hi, ldbl* mu, lint* rounds_out) {
   constexpr int MSL = TB / MSC;   // lanes per candidate
   const int q = c.tid / MSL, sub = c.tid % MSL;
@@ -697,6 +700,162 @@ __device__ bool multisect(Ctx& c, int P, const ldbl* absb, const ldbl* inva, int
   return true;
 }
 
+// ---------------------------------------------------------------------------------
+// Breakpoint lists
+// ---------------------------------------------------------------------------------
+// While it forms the prox inputs, every workgroup publishes, for each period, the owned
+// assets whose |b| lies in the window (c_2, c_5] around the prediction (at most LIST_CAP
+// of them, and the true count).  When the root falls inside the window, the lists hold
+// every breakpoint between the bracket ends, so each workgroup finishes the multiplier
+// exactly from them after the statistics barrier (and, in speculative mode, corrects the
+// affine K~ xbar with the few columns whose state differs between c_4 and mu) instead of
+// spending further exchanges.  Every workgroup reads the same lists and sorts them the
+// same way, so all of them reach bit-identical results.
+constexpr int NPOOL = TB;    // listed breakpoints gathered per iteration (all periods)
+
+__device__ __forceinline__ double* list_at(const double* blist, int par, int nwg, int P, int w, int t) {
+  return (double*)blist + (((size_t)par * nwg + w) * P + t) * LIST_W;
+}
+
+// Gathers the lists of every period t with gneed[t] > 0 into pool[NPOOL][4] = (|b|, 1/a,
+// asset, sign(b)/(a dc)), period t in the entries [poff[t], poff[t] + ptot[t]), sorted by
+// (|b|, asset).  A period whose lists overflowed or that does not fit in the pool gets
+// gneed[t] = -1.  Every decision here depends only on the published counts, never on the
+// order of the appends, so all workgroups agree.  Whole workgroup; ptot is zero on entry
+// and returned holding the entry counts.
+__device__ __noinline__ void gather_pool(const double* blist, int par, int nwg, int P, lint* gneed, lint* ptot,
+                                            lint* poff, lint* pfill, ldbl* pool) {
+  constexpr int U = 8;   // pairs per thread with loads in flight together
+  const int npair = P * nwg;
+  // pass 1: per-period entry counts
+  for (int base = threadIdx.x; base < npair; base += TB * U) {
+    double cn[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int idx = base + u * TB, t = idx / nwg, w = idx - t * nwg;
+      cn[u] = (idx < npair && gneed[t] > 0) ? ldd(list_at(blist, par, nwg, P, w, t)) : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      if (!(cn[u] > 0.0)) continue;
+      const int t = (base + u * TB) / nwg, cnt = (int)cn[u];
+      if (cnt > LIST_CAP) gneed[t] = -1;
+      __hip_atomic_fetch_add(&ptot[t], min(cnt, LIST_CAP), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int off = 0;
+    for (int t = 0; t < P; ++t) {
+      pfill[t] = 0;
+      if (gneed[t] > 0 && off + ptot[t] > NPOOL) gneed[t] = -1;
+      if (gneed[t] <= 0) { ptot[t] = 0; continue; }
+      poff[t] = off;
+      off += ptot[t];
+    }
+  }
+  __syncthreads();
+  // pass 2: the entries
+  for (int base = threadIdx.x; base < npair; base += TB * U) {
+    double cn[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int idx = base + u * TB, t = idx / nwg, w = idx - t * nwg;
+      cn[u] = (idx < npair && gneed[t] > 0) ? ldd(list_at(blist, par, nwg, P, w, t)) : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      if (!(cn[u] > 0.0)) continue;
+      const int idx = base + u * TB, t = idx / nwg, w = idx - t * nwg;
+      const int kmax = min((int)cn[u], LIST_CAP);
+      const int pos = poff[t] + __hip_atomic_fetch_add(&pfill[t], kmax, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+      const double* L = list_at(blist, par, nwg, P, w, t) + 1;
+      for (int k0 = 0; k0 < kmax; k0 += 4) {   // four entries' loads in flight together
+        double e[16];
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+#pragma unroll
+          for (int f = 0; f < 4; ++f) e[4 * k + f] = k0 + k < kmax ? ldd(L + 4 * (k0 + k) + f) : 0.0;
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+          if (k0 + k < kmax)
+#pragma unroll
+            for (int f = 0; f < 4; ++f) pool[4 * (pos + k0 + k) + f] = e[4 * k + f];
+      }
+    }
+  }
+  __syncthreads();
+  // sort each period's entries in place by (|b|, asset): entry i takes its rank
+  double e0 = 0.0, e1 = 0.0, e2 = 0.0, e3 = 0.0;
+  int dst = -1;
+  {
+    const int i = threadIdx.x;   // NPOOL == TB: one entry per thread
+    int t = -1;
+    for (int u = 0; u < P; ++u)
+      if (ptot[u] > 0 && i >= poff[u] && i < poff[u] + ptot[u]) t = u;
+    if (t >= 0) {
+      e0 = pool[4 * i]; e1 = pool[4 * i + 1]; e2 = pool[4 * i + 2]; e3 = pool[4 * i + 3];
+      int r = 0;
+      for (int j = poff[t]; j < poff[t] + ptot[t]; ++j) {
+        const double vj = pool[4 * j], gj = pool[4 * j + 2];
+        r += (vj < e0 || (vj == e0 && gj < e2)) ? 1 : 0;
+      }
+      dst = poff[t] + r;
+    }
+  }
+  __syncthreads();
+  if (dst >= 0) {
+    ldbl* q = pool + 4 * dst;
+    q[0] = e0; q[1] = e1; q[2] = e2; q[3] = e3;
+  }
+}
+
+// Index range [k0, k1) of the sorted entries pool[a, a + cnt) with |b| in (lo, hi] (one
+// whole wave; uniform result).
+__device__ __forceinline__ void pool_range(const ldbl* pool, int a, int cnt, double lo, double hi, int& k0, int& k1) {
+  const int lane = threadIdx.x & 63;
+  int nb = 0, nu = 0;
+  for (int j0 = 0; j0 < cnt; j0 += 64) {
+    const int j = j0 + lane;
+    const double v = j < cnt ? (double)pool[4 * (a + j)] : INFINITY;
+    nb += __popcll(__ballot(v <= lo));
+    nu += __popcll(__ballot(v <= hi));
+  }
+  k0 = a + nb;
+  k1 = a + nu;
+}
+
+// Exact root of S(mu) = 1 on [lo, hi] from S(lo), A0(lo) and the sorted breakpoints in
+// (lo, hi] (one whole wave; uniform result).  Between breakpoints S is affine:
+// S(v_k) = S(lo) - (v_k - lo) A0(lo) + sum_{j<k} (v_k - v_j)/a_j, slope -(A0(lo) - sum_{j<=k} 1/a_j).
+__device__ double solve_from_list(const ldbl* buf, int n, double lo, double hi, double Slo, double Alo) {
+  const int lane = threadIdx.x & 63;
+  double Sk = 0.0, slope_after = 0.0;
+  if (lane < n) {
+    const double v = buf[lane * 4];
+    double acc = Slo - (v - lo) * Alo, iasum = 0.0;
+    for (int j = 0; j < lane; ++j) acc = fma(v - buf[j * 4], buf[j * 4 + 1], acc);
+    for (int j = 0; j <= lane; ++j) iasum += buf[j * 4 + 1];
+    Sk = acc;
+    slope_after = Alo - iasum;
+  }
+  const unsigned long long ge = __ballot(lane < n && Sk >= 1.0);
+  double mu;
+  if (!ge) {
+    const double nxt = n > 0 ? (double)buf[0] : hi;
+    mu = Alo > 0.0 ? lo + (Slo - 1.0) / Alo : lo;
+    mu = fmin(fmax(mu, lo), nxt);
+  } else {
+    const int k = 63 - __clzll((long long)ge);
+    const double vk = buf[k * 4];
+    const double Skk = lane_of(Sk, k), sl = lane_of(slope_after, k);
+    const double nxt = k + 1 < n ? (double)buf[(k + 1) * 4] : hi;
+    mu = sl > 0.0 ? vk + (Skk - 1.0) / sl : vk;
+    mu = fmin(fmax(mu, vk), nxt);
+  }
+  return mu;
+}
+
 // Relative half-width policy after a decision r (see bracket_decide): kept on a hit,
 // shrunk when breakpoints fell inside the central pair, grown when the root was outside.
 __device__ __forceinline__ double adapt_width(int r, double w) {
@@ -728,7 +887,7 @@ template <class R>
 __host__ __device__ constexpr size_t lds_doubles(size_t count) { return (count * sizeof(R) + 7) / 8; }
 
 // One solve by a team of nwg workgroups; this workgroup is rank wg of the team.
-template <bool KL, bool SL, class R>
+template <bool KL, bool SL, class R, bool LS>
 __device__ __forceinline__ void solve_body(const DevProblem& p, const DevState& s, const DevControl& ctl, int wg,
                                            int nwg) {
   ldbl* lds = (ldbl*)g_lds;
@@ -784,6 +943,9 @@ __device__ __forceinline__ void solve_body(const DevProblem& p, const DevState& 
   ldbl* dmu = ptr;  ptr += P;
   ldbl* dmp = ptr;  ptr += P;
   ldbl* dwd = ptr;  ptr += P;
+  const bool lists = LS && ctl.lists;       // breakpoint lists (single-team launches only)
+  ldbl* pool = nullptr;                     // gathered breakpoint lists (sorted)
+  if (lists) { pool = ptr; ptr += NPOOL * 4; }
   using SV = S<KL, SL, R>;
   SV V;
   V.p = &p;
@@ -839,6 +1001,14 @@ __device__ __forceinline__ void solve_body(const DevProblem& p, const DevState& 
   lint* fbflag = iflag + 1;
   lint* msflag = iflag + 2;
   lint* need = (lint*)ptr;
+  lint* ncor = need + P;                    // per period: list corrections of K~ xbar (-1: none) ...
+  lint* ncs = ncor + P;                     // ... starting at this pool entry
+  lint* gneed = ncs + P;                    // per period: lists wanted (1 solve, 2 correction), -1 overflow
+  lint* ldec = gneed + P;                   // per period: bracket decision
+  lint* lcnt = ldec + P;                    // per period: entries published by this workgroup
+  lint* ptot = lcnt + P;                    // per period: gathered entries, their first pool
+  lint* poff = ptot + P;                    // entry, and the fill counter
+  lint* pfill = poff + P;
   c.tot = tot;
   c.red = red;
   c.flag = iflag;
@@ -885,6 +1055,8 @@ __device__ __forceinline__ void solve_body(const DevProblem& p, const DevState& 
       cen[t] = 0.0; hw[t] = 0.0; lo[t] = 0.0; hi[t] = 0.0; mu[t] = 0.0; mpv[t] = 0.0; wid[t] = 1e-3;
       dcen[t] = 0.0; dhw[t] = 0.0; dlo[t] = 0.0; dhi[t] = 0.0; dmu[t] = 0.0; dmp[t] = 0.0; dwd[t] = 1e-3;
       need[t] = 0;
+      ncor[t] = -1; ncs[t] = 0; gneed[t] = 0; ldec[t] = 0; lcnt[t] = 0;
+      ptot[t] = 0; poff[t] = 0; pfill[t] = 0;
     }
   }
   __syncthreads();
@@ -903,6 +1075,7 @@ __device__ __forceinline__ void solve_body(const DevProblem& p, const DevState& 
   const long long t_start = wall_clock64();
   long long t_check = 0;
   long long t_loop = t_start;
+  int lpar = 0;   // list buffer of this iteration (alternates)
 
   // ------------------------------------------------------------- power iteration
   // lambda ~ ||K~ v||^2 / ||v||^2 ; v <- K~^T K~ v / (lambda ||v||)  (v kept in xb)
@@ -971,8 +1144,26 @@ __device__ __forceinline__ void solve_body(const DevProblem& p, const DevState& 
       V.aa(t, li) = 1.0 / a;
       xv3[t * nw + li] = fabs(b);
       xv4[t * nw + li] = 1.0 / a;
+      if (lists) {
+        const double ab = fabs(b);
+        if (ab > cand(cen[t], hw[t], 2) && ab <= cand(cen[t], hw[t], 5)) {
+          const int pos = __hip_atomic_fetch_add(&lcnt[t], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+          if (pos < LIST_CAP) {
+            double* L = list_at(s.blist, lpar, nwg, P, c.wg, t) + 1 + 4 * pos;
+            std_(L, ab);
+            std_(L + 1, 1.0 / a);
+            std_(L + 2, (double)(c.i0 + li));
+            std_(L + 3, sgn(b) / (a * dci));
+          }
+        }
+      }
     }
     __syncthreads();
+    if (lists)
+      for (int t = c.tid; t < P; t += TB) {
+        std_(list_at(s.blist, lpar, nwg, P, c.wg, t), (double)lcnt[t]);
+        lcnt[t] = 0;
+      }
     const long long tb0 = wall_clock64();
     t_phA += tb0 - ta0;
 
@@ -1008,19 +1199,67 @@ __device__ __forceinline__ void solve_body(const DevProblem& p, const DevState& 
         const int lane = c.tid & 63, wave = c.tid >> 6;
         for (int t = wave; t < P; t += NWAVE) {   // one wave per period
           double l = 0.0, h = 0.0, m_ = 0.0;
-          const int r = bracket_decide(tot + STW * t, cen[t], hw[t], l, h, m_);
+          const int rq = bracket_decide(tot + STW * t, cen[t], hw[t], l, h, m_);
           if (lane == 0) {
-            wid[t] = adapt_width(r, wid[t]);
+            const int r0 = rq & 15, qs = (rq >> 4) - 1;
+            int g = 0;
+            if (lists && r0 != 1) {
+              const double c2 = cand(cen[t], hw[t], 2), c5 = cand(cen[t], hw[t], 5);
+              if ((r0 == 0 || r0 == 3) && qs >= 2 && qs <= 4 && l >= c2 && h <= c5) g = 1;   // solve from lists
+              else if (ctl.spec && (r0 == 2 || r0 == 4) && m_ >= c2 && m_ <= c5) g = 2;       // correct K~ xbar
+            }
+            gneed[t] = g;
+            ldec[t] = rq;
+            lo[t] = l; hi[t] = h;
+            wid[t] = adapt_width(r0, wid[t]);
             mpv[t] = mu[t];
+            if (r0 != 0 && r0 != 3) mu[t] = m_;
+          }
+        }
+      }
+      __syncthreads();
+      if (lists) {
+        int anyg = 0;
+        for (int t = 0; t < P; ++t) anyg |= gneed[t];
+        if (anyg) {
+          gather_pool(s.blist, lpar, nwg, P, gneed, ptot, poff, pfill, pool);
+          __syncthreads();
+        }
+      }
+      {
+        const int lane = c.tid & 63, wave = c.tid >> 6;
+        for (int t = wave; t < P; t += NWAVE) {   // one wave per period
+          const int rq = ldec[t], r0 = rq & 15, qs = (rq >> 4) - 1, g = gneed[t];
+          const double l = lo[t], h = hi[t];
+          double m_ = mu[t];
+          int r = r0, nc = -1, k0 = 0;
+          if (g > 0) {
+            if (g == 1) {
+              int k1;
+              pool_range(pool, poff[t], ptot[t], l, h, k0, k1);
+              if (k1 - k0 <= 64) {
+                const ldbl* st = tot + STW * t;
+                m_ = solve_from_list(pool + 4 * k0, k1 - k0, l, h, st[2 + 3 * qs], st[3 + 3 * qs]);
+                r = 4;
+              }
+            }
+            const double c4 = cand(cen[t], hw[t], 4);
+            if (ctl.spec && r != 0 && r != 3 && m_ >= cand(cen[t], hw[t], 2) && m_ <= cand(cen[t], hw[t], 5)) {
+              int k1;
+              pool_range(pool, poff[t], ptot[t], fmin(m_, c4), fmax(m_, c4), k0, k1);
+              nc = k1 - k0;
+            }
+          }
+          if (lane == 0) {
+            ncor[t] = nc;
+            ncs[t] = k0;
             if (r == 1) {
-              mu[t] = m_;
               need[t] = 0;
             } else if (r == 2 || r == 4) {
               mu[t] = m_;
               need[t] = 0;
-              __hip_atomic_fetch_or(fbflag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+              if (nc < 0) __hip_atomic_fetch_or(fbflag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
             } else {
-              lo[t] = l; hi[t] = h;
               need[t] = 1;
               __hip_atomic_fetch_or(fbflag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
               __hip_atomic_fetch_or(msflag, r == 0 ? 1 : 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
@@ -1038,6 +1277,7 @@ __device__ __forceinline__ void solve_body(const DevProblem& p, const DevState& 
         if (anymiss & 2) sc->miss_out++;
         *fbflag = 0;
         *msflag = 0;
+        for (int t = 0; t < P; ++t) ptot[t] = 0;
       }
       __syncthreads();
       const long long tb3 = wall_clock64();
@@ -1045,8 +1285,24 @@ __device__ __forceinline__ void solve_body(const DevProblem& p, const DevState& 
       const int redo = *iflag;
       if (!redo) {
         for (int e = c.tid; e < P * nr; e += TB) {
-          const int t = e / nr;
-          Kx[e] = tot[oP1 + e] + 2.0 * (mu[t] - cand(cen[t], hw[t], 4)) * tot[oP2 + e];
+          const int t = e / nr, j = e - t * nr;
+          const double c4 = cand(cen[t], hw[t], 4), m_ = mu[t];
+          double v = tot[oP1 + e] + 2.0 * (m_ - c4) * tot[oP2 + e];
+          const int nc = ncor[t];
+          if (nc > 0) {
+            // x_hat(mu) - (affine piece at c_4) = sgn(b)/(a dc) (|b| - mu) ([|b| > mu] - [|b| > c_4])
+            const ldbl* lb = pool + 4 * ncs[t];
+            const double* Kr = p.K + (size_t)j * p.ldk;
+            double corr = 0.0;
+            for (int k = 0; k < nc; ++k) {
+              const double vk = lb[4 * k], cf = lb[4 * k + 3];
+              const int g = (int)lb[4 * k + 2];
+              const double dx = cf * (vk - m_) * ((vk > m_ ? 1.0 : 0.0) - (vk > c4 ? 1.0 : 0.0));
+              corr = fma(Kr[g], dx, corr);
+            }
+            v = fma(2.0 * ks[j], corr, v);
+          }
+          Kx[e] = v;
         }
         __syncthreads();
       } else {
@@ -1067,6 +1323,7 @@ __device__ __forceinline__ void solve_body(const DevProblem& p, const DevState& 
         __syncthreads();
       }
       for (int t = c.tid; t < P; t += TB) next_bracket(mu[t], mpv[t], wid[t], cen[t], hw[t]);
+      lpar ^= 1;
       __syncthreads();
       t_b3 += wall_clock64() - tb3;
     }
@@ -1223,7 +1480,7 @@ __device__ __forceinline__ void solve_body(const DevProblem& p, const DevState& 
         const int lane = c.tid & 63, wave = c.tid >> 6;
         for (int t = wave; t < P; t += NWAVE) {   // one wave per period
           double l = 0.0, h = 0.0, m_ = 0.0;
-          const int r = bracket_decide(tot + oD + STW * t, dcen[t], dhw[t], l, h, m_);
+          const int r = bracket_decide(tot + oD + STW * t, dcen[t], dhw[t], l, h, m_) & 15;
           if (lane == 0) {
             dwd[t] = adapt_width(r, dwd[t]);
             dmp[t] = dmu[t];
@@ -1399,17 +1656,17 @@ barrier_fail:
 
 template <bool KL, bool SL, class R>
 __global__ __launch_bounds__(TB) void k_solve(DevProblem p, DevState s, DevControl ctl) {
-  solve_body<KL, SL, R>(p, s, ctl, blockIdx.x, gridDim.x);
+  solve_body<KL, SL, R, true>(p, s, ctl, blockIdx.x, gridDim.x);
 }
 
 // Batched: every team solves its own instance; teams never wait for each other.
 template <bool KL, bool SL, class R>
-__global__ __launch_bounds__(TB) void k_solve_batch(const DevProblem* __restrict__ dp, const DevState* __restrict__ ds,
+__global__ __launch_bounds__(TB) __attribute__((amdgpu_waves_per_eu(2))) void k_solve_batch(const DevProblem* __restrict__ dp, const DevState* __restrict__ ds,
                                                     const DevControl* __restrict__ dcl, const int* __restrict__ wg_team,
                                                     const int* __restrict__ wg_rank) {
   const int team = wg_team[blockIdx.x];
   const DevControl ctl = dcl[team];
-  solve_body<KL, SL, R>(dp[team], ds[team], ctl, wg_rank[blockIdx.x], ctl.nwg);
+  solve_body<KL, SL, R, false>(dp[team], ds[team], ctl, wg_rank[blockIdx.x], ctl.nwg);
 }
 
 // ---------------------------------------------------------------------------------
@@ -1619,7 +1876,7 @@ __global__ __launch_bounds__(TB) void k_adjoint(DevProblem p, AdjState a, DevCon
       const int lane = c.tid & 63, wave = c.tid >> 6;
       for (int t = wave; t < P; t += NWAVE) {
         double l = 0.0, h = 0.0, m_ = 0.0;
-        const int r = bracket_decide(tot + STW * t, 0.0, 0.0, l, h, m_);
+        const int r = bracket_decide(tot + STW * t, 0.0, 0.0, l, h, m_) & 15;
         if (lane == 0) {
           if (r == 0 || r == 3) { lo[t] = l; hi[t] = h; need[t] = 1; fbflag[0] = 1; }
           else { mu[t] = m_; need[t] = 0; }
@@ -1976,7 +2233,8 @@ size_t solve_lds_bytes(const DevProblem& p, const DevControl& c) {
   d += 4 * P * nr + 4 * P * nw + (size_t)c.vmax + RED_LEN + 14 * P + nr;
   if (c.xmode == XM_LOCAL) d += 3 * (size_t)c.vmax;
   if (c.lds_state) d += f32 ? state_lds_doubles<float>(P, Tp, nw) : state_lds_doubles<double>(P, Tp, nw);
-  d += (sizeof(Scal) + 7) / 8 + 2 + (P + 1) / 2 + 1;
+  if (c.lists) d += NPOOL * 4;
+  d += (sizeof(Scal) + 7) / 8 + 2 + 5 * P + 1;   // flags and nine per-period integer arrays
   return d * sizeof(double);
 }
 
