@@ -374,6 +374,8 @@ ffo_status ffo_solve(int64_t n, int64_t k, int64_t m, int64_t T, const double* a
   size_t off = 0;
   auto carve = [&](size_t cnt, size_t elt) { const size_t o = off; off = align_up(off + cnt * elt); return o; };
   const size_t oK = carve((size_t)std::max(nr, 1) * ldk, 8), odr = carve(std::max(nr, 1), 8), odc = carve(n, 8);
+  const bool f32rows = c.prec == ffo::PREC_FP32 && !c.lds_k;   // FP32 form reading rows from device memory
+  const size_t oKf = carve(f32rows ? (size_t)std::max(nr, 1) * ldk : 1, 4);
   const size_t odrC = carve(Tpn, 8), oar = carve(n, 8), ocv = carve(n, 8), oca = carve(Tpn, 8), ocb = carve(Tpn, 8);
   const size_t obF = carve(std::max<int64_t>(k, 1), 8), ocr = carve(1, 8), oC = carve(std::max<int64_t>(k * k, 1), 8);
   size_t ost[6];
@@ -427,6 +429,11 @@ ffo_status ffo_solve(int64_t n, int64_t k, int64_t m, int64_t T, const double* a
   p.cvec = D(ocv); p.ca = D(oca); p.cb = D(ocb); p.w0 = w0; p.wT = w_target; p.L = L; p.U = U;
   p.bF = D(obF); p.g1 = g1; p.d = d; p.g2 = g2;
   p.crisk = D(ocr);
+  if (f32rows) {
+    if (ffo::launch_to_float(D(oK), (float*)(B + oKf), (int64_t)nr * ldk, stream))
+      return fail(FFO_EDEVICE, "setup kernel launch failed");
+    p.Kf = (const float*)(B + oKf);
+  }
 
   ffo::DevState sv{};
   sv.xs = D(ost[0]); sv.x0s = D(ost[1]); sv.Txs = D(ost[2]);
@@ -773,6 +780,8 @@ ffo_status ffo_solve_batched(int64_t B, const int64_t* n_b, int64_t n_max, int64
   size_t off = 0;
   auto carve = [&](size_t cnt, size_t elt) { const size_t o = off; off = align_up(off + cnt * elt); return o; };
   const size_t oK = carve((size_t)std::max(nr, 1) * ldk, 8), odc = carve(n_max, 8), odrC = carve(n_max, 8);
+  const bool f32rows = prec == ffo::PREC_FP32;   // the batched kernel reads rows from device memory
+  const size_t oKf = carve(f32rows ? (size_t)std::max(nr, 1) * ldk : 1, 4);
   const size_t oar = carve(n_max, 8), ocv = carve(n_max, 8), obF = carve(std::max<int64_t>(k, 1), 8);
   const size_t ocr = carve(1, 8), oC = carve(std::max<int64_t>(k * k, 1), 8), onb = carve(B, 8);
   const size_t odrs = carve((size_t)B * std::max(nr, 1), 8), oca = carve(N, 8), ocb = carve(N, 8);
@@ -826,6 +835,8 @@ ffo_status ffo_solve_batched(int64_t B, const int64_t* n_b, int64_t n_max, int64
   if (ffo::launch_setup_batch(B, (const int64_t*)(Bd + onb), n_max, k, m, ldk, F, D(oC), A, delta, N, s, q, g1, g2, g3,
                               D(oK), D(odrs), D(odc), D(odrC), D(oar), D(ocv), D(oca), D(ocb), stream))
     return fail(FFO_EDEVICE, "setup kernel launch failed");
+  if (f32rows && ffo::launch_to_float(D(oK), (float*)(Bd + oKf), (int64_t)nr * ldk, stream))
+    return fail(FFO_EDEVICE, "setup kernel launch failed");
   HIPCHK(hipMemsetAsync(Bd + obF, 0, (size_t)std::max<int64_t>(k, 1) * 8, hs));
   HIPCHK(hipMemsetAsync(Bd + ocr, 0, 8, hs));
   HIPCHK(hipMemsetAsync(Bd + oxb, 0, (size_t)B * 3 * c0.vmax * 8, hs));
@@ -841,7 +852,7 @@ ffo_status ffo_solve_batched(int64_t B, const int64_t* n_b, int64_t n_max, int64
     const int64_t o = offs[b];
     ffo::DevProblem p = p0;
     p.n = (int)n_b[b];
-    p.K = D(oK); p.dr = D(odrs) + (size_t)b * nr; p.dc = D(odc); p.drC = D(odrC); p.alpha = alpha + o;
+    p.K = D(oK); p.Kf = f32rows ? (const float*)(Bd + oKf) : nullptr; p.dr = D(odrs) + (size_t)b * nr; p.dc = D(odc); p.drC = D(odrC); p.alpha = alpha + o;
     p.arisk = D(oar); p.cvec = D(ocv); p.ca = D(oca) + o; p.cb = D(ocb) + o; p.w0 = w0 + o; p.wT = nullptr;
     p.L = m ? L + (size_t)b * m : nullptr; p.U = m ? U + (size_t)b * m : nullptr;
     p.bF = D(obF); p.crisk = D(ocr); p.g1 = g1; p.d = d; p.g2 = g2;
@@ -909,16 +920,21 @@ ffo_status ffo_solve_batched(int64_t B, const int64_t* n_b, int64_t n_max, int64
     int64_t slow = 0;
     for (int64_t b = 1; b < B; ++b)
       if (hinfo[(size_t)b * ffo::INFO_LEN + ffo::IX_T_ITER] > hinfo[(size_t)slow * ffo::INFO_LEN + ffo::IX_T_ITER]) slow = b;
-    const double* h = hinfo + (size_t)slow * ffo::INFO_LEN;
-    std::fprintf(stderr,
-                 "[ffo batch] slowest instance %lld: n %lld team %d xmode %d iters %.0f spec_miss %.0f exchanges %.0f "
-                 "| t_iter %.3f ms t_check %.3f ms t_wait %.3f ms | A %.3f B %.3f C %.3f D %.3f pre %.3f read %.3f "
-                 "| B1 %.3f (stats %.3f) B2 %.3f B3 %.3f ms\n",
-                 (long long)slow, (long long)n_b[slow], hCt[slow].nwg, hCt[slow].xmode, h[ffo::IX_ITERS],
-                 h[ffo::IX_SPEC_MISS], h[ffo::IX_EXCHANGES], h[ffo::IX_T_ITER] * 1e3, h[ffo::IX_T_CHECK] * 1e3,
-                 h[ffo::IX_T_WAIT] * 1e3, h[ffo::IX_T_PHA] * 1e3, h[ffo::IX_T_PHB] * 1e3, h[ffo::IX_T_PHC] * 1e3,
-                 h[ffo::IX_T_PHD] * 1e3, h[ffo::IX_T_PRE] * 1e3, h[ffo::IX_T_READ] * 1e3, h[ffo::IX_T_B1] * 1e3,
-                 h[ffo::IX_T_B1S] * 1e3, h[ffo::IX_T_B2] * 1e3, h[ffo::IX_T_B3] * 1e3);
+    auto show = [&](const char* what, int64_t b) {
+      const double* h = hinfo + (size_t)b * ffo::INFO_LEN;
+      std::fprintf(stderr,
+                   "[ffo batch] %s instance %lld: n %lld team %d xmode %d iters %.0f spec_miss %.0f exchanges %.0f "
+                   "| t_iter %.3f ms t_check %.3f ms t_wait %.3f ms | A %.3f B %.3f C %.3f D %.3f pre %.3f read %.3f "
+                   "| B1 %.3f (stats %.3f) B2 %.3f B3 %.3f ms\n",
+                   what, (long long)b, (long long)n_b[b], hCt[b].nwg, hCt[b].xmode, h[ffo::IX_ITERS],
+                   h[ffo::IX_SPEC_MISS], h[ffo::IX_EXCHANGES], h[ffo::IX_T_ITER] * 1e3, h[ffo::IX_T_CHECK] * 1e3,
+                   h[ffo::IX_T_WAIT] * 1e3, h[ffo::IX_T_PHA] * 1e3, h[ffo::IX_T_PHB] * 1e3, h[ffo::IX_T_PHC] * 1e3,
+                   h[ffo::IX_T_PHD] * 1e3, h[ffo::IX_T_PRE] * 1e3, h[ffo::IX_T_READ] * 1e3, h[ffo::IX_T_B1] * 1e3,
+                   h[ffo::IX_T_B1S] * 1e3, h[ffo::IX_T_B2] * 1e3, h[ffo::IX_T_B3] * 1e3);
+    };
+    show("slowest", slow);
+    if (std::getenv("FFO_BATCH_ALL"))
+      for (int64_t b = 0; b < B; ++b) show("every", b);
   }
   if (worst == FFO_NOT_CONVERGED) g_err = "iteration limit reached for at least one instance";
   else if (worst == FFO_TIMEOUT) g_err = "time limit reached for at least one instance";

@@ -23,6 +23,7 @@ struct DevProblem {
   int32_t n, k, m, P, Tp, nr, multi, ldk;
   int32_t kscaled;      // 1: K holds diag(dr) K diag(dc); 0: K holds K diag(dc), rows scaled by dr on use
   const double* K;      // [nr][ldk] constraint rows (see kscaled)
+  const float* Kf;      // the same rows rounded to float (FP32 form reading rows from device memory), or null
   const double* dr;     // [nr]
   const double* dc;     // [n]
   const double* drC;    // [Tp][n]
@@ -133,6 +134,8 @@ int launch_setup_batch(int64_t B, const int64_t* nb_dev, int64_t n_max, int64_t 
                        const double* s, const double* q, double g1, double g2, double g3, double* Kbuf,
                        double* drs, double* dc, double* drC, double* arisk, double* cvec, double* ca, double* cb,
                        void* stream);
+// Kf[i] = (float)K[i] for i < count (FP32 form).
+int launch_to_float(const double* K, float* Kf, int64_t count, void* stream);
 int launch_setup(int64_t n, int64_t k, int64_t m, int64_t P, int64_t Tp, int ldk,
                  const double* F, const double* Cfac, const double* A, const double* delta,
                  const double* s, const double* q, const double* wT, double g1, double g2,

@@ -6,6 +6,7 @@
 // dr = 1/sqrt(r), dc = 1/sqrt(c) and K~ = diag(dr) K diag(dc).  Trade rows have unit
 // entries, so their row sums are 1 (single-period, first and last multi-period trade)
 // or 2, and every column gains 1 (single-period) or 2 (multi-period).
+#include <algorithm>
 #include <hip/hip_runtime.h>
 #include "internal.h"
 
@@ -156,6 +157,18 @@ int launch_setup_batch(int64_t B, const int64_t* nb_dev, int64_t n_max, int64_t 
     hipLaunchKernelGGL(k_scale, dim3((ldk + TB - 1) / TB, nr), dim3(TB), 0, st, (int)n_max, nr, ldk, Kbuf,
                        (const double*)nullptr, dc);
   }
+  return hipGetLastError() == hipSuccess ? 0 : 1;
+}
+
+__global__ __launch_bounds__(TB) void k_to_float(const double* __restrict__ K, float* __restrict__ Kf, int64_t count) {
+  for (int64_t i = blockIdx.x * (int64_t)TB + threadIdx.x; i < count; i += (int64_t)gridDim.x * TB)
+    Kf[i] = (float)K[i];
+}
+
+int launch_to_float(const double* K, float* Kf, int64_t count, void* stream) {
+  if (count <= 0) return 0;
+  const int64_t nb = std::min<int64_t>((count + TB - 1) / TB, 4096);
+  hipLaunchKernelGGL(k_to_float, dim3((unsigned)nb), dim3(TB), 0, (hipStream_t)stream, K, Kf, count);
   return hipGetLastError() == hipSuccess ? 0 : 1;
 }
 

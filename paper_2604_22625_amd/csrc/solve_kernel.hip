@@ -115,6 +115,10 @@ __device__ __forceinline__ double wave_max(double x) {
 // instead of generic (flat) memory instructions.
 typedef __attribute__((address_space(3))) double ldbl;
 typedef __attribute__((address_space(3))) int lint;
+// Device-memory pointers in the global address space: their loads count only against
+// vmcnt (generic FLAT loads also count against lgkmcnt, so every LDS wait would drain them).
+template <class T>
+using gmem_t = __attribute__((address_space(1))) T;
 template <class R>
 using lds_t = __attribute__((address_space(3))) R;
 
@@ -180,6 +184,33 @@ __device__ __forceinline__ void put_max(const Ctx& c, int j, double v) {
     unsigned long long* a = (unsigned long long*)&c.xbuf[(size_t)(c.epoch % 3) * c.vmax + j];
     __hip_atomic_fetch_max(a, (unsigned long long)__double_as_longlong(v), __ATOMIC_RELAXED,
                            __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
+
+// Destination of this workgroup's contributions to the current exchange, for code that
+// runs out of line (no Ctx): put_at(put_to(c), j, v) does what put(c, j, v) does.
+struct PutTo {
+  double* g;   // device slot (gather: this workgroup's; atomic: the shared one)
+  ldbl* l;     // LDS slot of a single-workgroup team
+  int mode;
+};
+
+__device__ __forceinline__ PutTo put_to(const Ctx& c) {
+  PutTo q;
+  q.mode = c.xmode;
+  q.l = c.lslot ? c.lslot + (size_t)(c.epoch % 3) * c.vmax : nullptr;
+  q.g = c.xmode == XM_GATHER ? c.xbuf + ((size_t)(c.epoch & 1) * c.nwg + c.wg) * c.vmax
+                             : c.xbuf + (size_t)(c.epoch % 3) * c.vmax;
+  return q;
+}
+
+__device__ __forceinline__ void put_at(const PutTo& q, int j, double v) {
+  if (q.mode == XM_LOCAL) {
+    if (v != 0.0) __hip_atomic_fetch_add(&q.l[j], v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+  } else if (q.mode == XM_GATHER) {
+    std_(&q.g[j], v);
+  } else if (v != 0.0) {
+    addd(&q.g[j], v);
   }
 }
 
@@ -307,9 +338,11 @@ template <bool KL, bool SL, class R = double>
 struct S {
   using RC = typename std::conditional<SL, R, double>::type;   // constants: LDS copies or FP64 inputs
   static constexpr bool KLDS = KL;
+  // element type of the rows read from device memory: float in the FP32 form
+  using KG = typename std::conditional<std::is_same<R, float>::value, float, double>::type;
   const DevProblem* p;
   const lds_t<R>* Kl;   // LDS slice [nr][ldl] (KL) ...
-  const double* Kg;     // ... or the rows in device memory, times the LDS row scale ks
+  const KG* Kg;         // ... or the rows in device memory, times the LDS row scale ks
   const ldbl* ks;
   int nw, ldl, i0;
   // state: anchors and per-iteration scratch in FP64, iterates through Iter views
@@ -323,7 +356,7 @@ struct S {
   Arr<SL, RC> dc, arisk, cvec, w0, wT;      // [1]
   __device__ __forceinline__ double Kat(int j, int li) const {
     if constexpr (KL) return (double)Kl[j * ldl + li];
-    else return Kg[(size_t)j * p->ldk + i0 + li] * ks[j];
+    else return (double)Kg[(size_t)j * p->ldk + i0 + li] * ks[j];
   }
 };
 
@@ -345,8 +378,56 @@ __device__ __forceinline__ double kcol_dot(const SV& v, const ldbl* y, int li, i
 // (K~^T y) over the exposure and factor rows for every owned (t, li), into out[t*nw + li]
 // (LDS).  Small slices split the rows over 2 or 4 thread groups with partials in
 // red[0, TB).  All threads call; synchronised on return.
+// The same with the rows in device memory (K~[j][li] = K[j*ldk + i0 + li] ks[j]).
+template <class KG>
+__device__ __forceinline__ void kty_dev(const KG* K, int ldk, int i0, const ldbl* ks, const ldbl* y, int P, int nr,
+                                     int nw, int nwa, ldbl* red, ldbl* out) {
+  const int tid = threadIdx.x, ne = P * nwa;
+  auto dot = [&](const ldbl* yt, int li, int j0, int j1) {
+    const gmem_t<KG>* col = (const gmem_t<KG>*)(K + i0 + li);
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+    int j = j0;
+    for (; j + 4 <= j1; j += 4) {
+      s0 = fma((double)col[(size_t)j * ldk] * ks[j], yt[j], s0);
+      s1 = fma((double)col[(size_t)(j + 1) * ldk] * ks[j + 1], yt[j + 1], s1);
+      s2 = fma((double)col[(size_t)(j + 2) * ldk] * ks[j + 2], yt[j + 2], s2);
+      s3 = fma((double)col[(size_t)(j + 3) * ldk] * ks[j + 3], yt[j + 3], s3);
+    }
+    for (; j < j1; ++j) s0 = fma((double)col[(size_t)j * ldk] * ks[j], yt[j], s0);
+    return (s0 + s1) + (s2 + s3);
+  };
+  if (ne == 0) { __syncthreads(); return; }
+  const int G = ne <= TB / 4 ? 4 : (ne <= TB / 2 ? 2 : 1);
+  if (G > 1) {
+    const int per = TB / G, g = tid / per, e = tid - g * per;
+    double r = 0.0;
+    if (e < ne) {
+      const int t = e / nwa, li = e - t * nwa;
+      r = dot(y + t * nr, li, g * nr / G, (g + 1) * nr / G);
+    }
+    red[tid] = r;
+    __syncthreads();
+    if (tid < ne) {
+      const int t = tid / nwa, li = tid - t * nwa;
+      double a = 0.0;
+      for (int gg = 0; gg < G; ++gg) a += red[gg * per + tid];
+      out[t * nw + li] = a;
+    }
+  } else {
+    for (int e = tid; e < ne; e += TB) {
+      const int t = e / nwa, li = e - t * nwa;
+      out[t * nw + li] = dot(y + t * nr, li, 0, nr);
+    }
+  }
+  __syncthreads();
+}
+
 template <class SV>
 __device__ __forceinline__ void kty_all(const Ctx& c, const SV& v, const ldbl* y, int P, int nr, int nw, ldbl* out) {
+  if constexpr (!SV::KLDS) {
+    kty_dev(v.Kg, v.p->ldk, v.i0, v.ks, y, P, nr, nw, c.nwa, c.red, out);
+    return;
+  }
   const int ne = P * c.nwa;
   if (ne == 0) { __syncthreads(); return; }
   const int G = ne <= TB / 4 ? 4 : (ne <= TB / 2 ? 2 : 1);
@@ -374,58 +455,61 @@ __device__ __forceinline__ void kty_all(const Ctx& c, const SV& v, const ldbl* y
   __syncthreads();
 }
 
-// Row products for long asset slices: lanes run over assets (coalesced loads when the
-// rows live in device memory), each wave takes RB rows at a time and reduces them with
-// DPP; emit as below.  Row bases and scales are resolved once per pass.
-template <int NX, class SV, class F>
-__device__ __forceinline__ void rows_prod_wide(const Ctx& c, const SV& v, const ldbl* x1, const ldbl* x2, int nw, int P, int nr,
-                               F emit) {
+// Row products for long asset slices with the rows in device memory: lanes run over
+// assets (coalesced loads), each wave takes RB rows at a time and reduces them with wave
+// sums; the sums go to the exchange: put_at(q, off1 + e, K~x1) and, when NX = 2,
+// put_at(q, off2 + e, K~x2) for every e = t*nr + j.  All threads call; no synchronisation.
+template <int NX, class KG>
+__device__ __forceinline__ void rows_dev(const KG* K, int ldk, int i0, const ldbl* ks, const ldbl* x1, const ldbl* x2,
+                                      int nw, int nwa, int P, int nr, PutTo q, int off1, int off2) {
   constexpr int RB = 8;
-  const int lane = c.tid & 63, wave = c.tid >> 6, ntot = P * nr;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, ntot = P * nr;
   for (int base = wave * RB; base < ntot; base += NWAVE * RB) {
     double a[RB][NX];
     int jr[RB], tr[RB];
+    const gmem_t<KG>* rp[RB];
 #pragma unroll
     for (int r = 0; r < RB; ++r) {
       const int e = min(base + r, ntot - 1);
       tr[r] = e / nr;
       jr[r] = e - tr[r] * nr;
+      rp[r] = (const gmem_t<KG>*)(K + (size_t)jr[r] * ldk + i0);
 #pragma unroll
       for (int u = 0; u < NX; ++u) a[r][u] = 0.0;
     }
-    if constexpr (SV::KLDS) {
-      for (int li = lane; li < c.nwa; li += 64) {
+    if (tr[0] == tr[RB - 1]) {   // all RB rows in one period: one x value per asset
+      const ldbl* y1 = x1 + tr[0] * nw;
+      const ldbl* y2 = x2 + tr[0] * nw;
+      for (int li = lane; li < nwa; li += 64) {
+        double kv[RB];   // all RB loads issued before the first use
+#pragma unroll
+        for (int r = 0; r < RB; ++r) kv[r] = (double)rp[r][li];
+        const double u1 = y1[li], u2 = NX > 1 ? (double)y2[li] : 0.0;
 #pragma unroll
         for (int r = 0; r < RB; ++r) {
-          const double kv = v.Kat(jr[r], li);
-          a[r][0] = fma(kv, x1[tr[r] * nw + li], a[r][0]);
-          if (NX > 1) a[r][NX - 1] = fma(kv, x2[tr[r] * nw + li], a[r][NX - 1]);
+          a[r][0] = fma(kv[r], u1, a[r][0]);
+          if (NX > 1) a[r][NX - 1] = fma(kv[r], u2, a[r][NX - 1]);
         }
       }
     } else {
-      // unscaled rows from device memory; the row scale is applied to the sums
-      const double* rp[RB];
+      for (int li = lane; li < nwa; li += 64) {
+        double kv[RB];
 #pragma unroll
-      for (int r = 0; r < RB; ++r) rp[r] = v.Kg + (size_t)jr[r] * v.p->ldk + v.i0;
-      for (int li = lane; li < c.nwa; li += 64) {
+        for (int r = 0; r < RB; ++r) kv[r] = (double)rp[r][li];
 #pragma unroll
         for (int r = 0; r < RB; ++r) {
-          const double kv = rp[r][li];
-          a[r][0] = fma(kv, x1[tr[r] * nw + li], a[r][0]);
-          if (NX > 1) a[r][NX - 1] = fma(kv, x2[tr[r] * nw + li], a[r][NX - 1]);
+          a[r][0] = fma(kv[r], x1[tr[r] * nw + li], a[r][0]);
+          if (NX > 1) a[r][NX - 1] = fma(kv[r], x2[tr[r] * nw + li], a[r][NX - 1]);
         }
       }
-#pragma unroll
-      for (int r = 0; r < RB; ++r)
-#pragma unroll
-        for (int u = 0; u < NX; ++u) a[r][u] *= v.ks[jr[r]];
     }
 #pragma unroll
     for (int r = 0; r < RB; ++r) {
-      double sum[NX];
 #pragma unroll
-      for (int u = 0; u < NX; ++u) sum[u] = wave_sum(a[r][u]);
-      if (lane == 0 && base + r < ntot) emit(base + r, sum);
+      for (int u = 0; u < NX; ++u) {
+        const double sum = wave_sum(a[r][u] * ks[jr[r]]);
+        if (lane == 0 && base + r < ntot) put_at(q, (u == 0 ? off1 : off2) + base + r, sum);
+      }
     }
   }
 }
@@ -462,11 +546,19 @@ __device__ __forceinline__ void rows_prod_lds(const Ctx& c, const SV& v, const l
 // Short slices (the usual case, rows in LDS or not): four lanes per row.  Long slices
 // of rows in device memory (batched teams, very large n): the coalesced wide form,
 // whose per-row wave reductions pay off once each lane has several assets.
-template <int NX, class SV, class F>
+template <int NX, class SV>
 __device__ __forceinline__ void rows_prod(const Ctx& c, const SV& v, const ldbl* x1, const ldbl* x2, int nw, int P,
-                                          int nr, F emit) {
-  if (!SV::KLDS && c.nwa > 512) rows_prod_wide<NX>(c, v, x1, x2, nw, P, nr, emit);
-  else rows_prod_lds<NX>(c, v, x1, x2, nw, P, nr, emit);
+                                          int nr, int off1, int off2 = 0) {
+  if constexpr (!SV::KLDS) {
+    if (c.nwa > 512) {
+      rows_dev<NX>(v.Kg, v.p->ldk, v.i0, v.ks, x1, x2, nw, c.nwa, P, nr, put_to(c), off1, off2);
+      return;
+    }
+  }
+  rows_prod_lds<NX>(c, v, x1, x2, nw, P, nr, [&](int e, const double* a) {
+    put(c, off1 + e, a[0]);
+    if (NX > 1) put(c, off2 + e, a[NX - 1]);
+  });
 }
 
 // Trade-row adjoint for asset li, period t: dc (drC_t yC_t - drC_{t+1} yC_{t+1}).
@@ -698,6 +790,37 @@ __device__ __forceinline__ bool multisect(Ctx& c, int P, const ldbl* absb, const
     __syncthreads();
   }
   return true;
+}
+
+// Out-of-line forms of the exchange, the statistics and the multisection.  The solve body
+// inlines them when it runs alone on the device (its hot loops then keep the workgroup
+// context in registers); the batched kernel calls them, which leaves its long
+// device-memory loops enough registers to keep their loads in flight.
+__device__ __noinline__ bool xsync_call(Ctx& c, int V) { return xsync(c, V); }
+__device__ __noinline__ void period_stats_call(Ctx& c, const ldbl* absb, const ldbl* inva, int nw, const ldbl* cen,
+                                               const ldbl* hw, int off0) {
+  period_stats(c, absb, inva, nw, cen, hw, off0);
+}
+__device__ __noinline__ bool multisect_call(Ctx& c, int P, const ldbl* absb, const ldbl* inva, int nw, lint* need,
+                                            ldbl* lo, ldbl* hi, ldbl* mu, lint* rounds_out) {
+  return multisect(c, P, absb, inva, nw, need, lo, hi, mu, rounds_out);
+}
+template <bool INL>
+__device__ __forceinline__ bool xsync_x(Ctx& c, int V) {
+  if constexpr (INL) return xsync(c, V);
+  else return xsync_call(c, V);
+}
+template <bool INL>
+__device__ __forceinline__ void period_stats_x(Ctx& c, const ldbl* absb, const ldbl* inva, int nw, const ldbl* cen,
+                                               const ldbl* hw, int off0) {
+  if constexpr (INL) period_stats(c, absb, inva, nw, cen, hw, off0);
+  else period_stats_call(c, absb, inva, nw, cen, hw, off0);
+}
+template <bool INL>
+__device__ __forceinline__ bool multisect_x(Ctx& c, int P, const ldbl* absb, const ldbl* inva, int nw, lint* need,
+                                            ldbl* lo, ldbl* hi, ldbl* mu, lint* rounds_out) {
+  if constexpr (INL) return multisect(c, P, absb, inva, nw, need, lo, hi, mu, rounds_out);
+  else return multisect_call(c, P, absb, inva, nw, need, lo, hi, mu, rounds_out);
 }
 
 // ---------------------------------------------------------------------------------
@@ -1014,7 +1137,8 @@ __device__ __forceinline__ void solve_body(const DevProblem& p, const DevState& 
   c.flag = iflag;
   c.lslot = lslot;
   V.Kl = Kl;
-  V.Kg = p.K;
+  if constexpr (std::is_same<typename SV::KG, float>::value) V.Kg = p.Kf;
+  else V.Kg = p.K;
   V.ks = ks;
 
   for (int j = c.tid; j < nr; j += TB) ks[j] = p.kscaled ? 1.0 : p.dr[j];
@@ -1096,8 +1220,8 @@ __device__ __forceinline__ void solve_body(const DevProblem& p, const DevState& 
     wg_sum<2>(c, loc);
     if (c.tid == 0) { put(c, 0, red[RED_OUT]); put(c, 1, red[RED_OUT + 1]); }
     __syncthreads();
-    rows_prod<1>(c, V, xv1, xv1, nw, P, nr, [&](int e, const double* a) { put(c, 2 + e, a[0]); });
-    if (!xsync(c, 2 + P * nr)) goto barrier_fail;
+    rows_prod<1>(c, V, xv1, xv1, nw, P, nr, 2);
+    if (!xsync_x<LS>(c, 2 + P * nr)) goto barrier_fail;
     {
       const double vv = tot[0];
       double kv = tot[1];
@@ -1171,7 +1295,7 @@ __device__ __forceinline__ void solve_body(const DevProblem& p, const DevState& 
     {
       const int oP1 = STW * P, oP2 = oP1 + P * nr;
       const int VE1 = ctl.spec ? oP2 + P * nr : STW * P;
-      period_stats(c, xv3, xv4, nw, cen, hw, 0);
+      period_stats_x<LS>(c, xv3, xv4, nw, cen, hw, 0);
       t_b1s += wall_clock64() - tb0;
       if (ctl.spec) {
         // affine pieces at hi: P1 = K~ (2 xhat_s(hi) - xs), P2 = K~ d xhat_s / d mu
@@ -1184,85 +1308,107 @@ __device__ __forceinline__ void solve_body(const DevProblem& p, const DevState& 
           xv2[t * nw + li] = ab > h ? -sgn(b) * ia / dci : 0.0;
         }
         __syncthreads();
-        rows_prod<2>(c, V, xv1, xv2, nw, P, nr, [&](int e, const double* a) {
-          put(c, oP1 + e, a[0]);
-          put(c, oP2 + e, a[1]);
-        });
+        rows_prod<2>(c, V, xv1, xv2, nw, P, nr, oP1, oP2);
       }
       const long long tb1 = wall_clock64();
       t_b1 += tb1 - tb0;
       c.mx_lo = 0;
       c.mx_hi = STW * P;
-      if (!xsync(c, VE1)) goto barrier_fail;
+      if (!xsync_x<LS>(c, VE1)) goto barrier_fail;
       const long long tb2 = wall_clock64();
-      {
+      if constexpr (!LS) {
         const int lane = c.tid & 63, wave = c.tid >> 6;
         for (int t = wave; t < P; t += NWAVE) {   // one wave per period
           double l = 0.0, h = 0.0, m_ = 0.0;
-          const int rq = bracket_decide(tot + STW * t, cen[t], hw[t], l, h, m_);
+          const int r = bracket_decide(tot + STW * t, cen[t], hw[t], l, h, m_) & 15;
           if (lane == 0) {
-            const int r0 = rq & 15, qs = (rq >> 4) - 1;
-            int g = 0;
-            if (lists && r0 != 1) {
-              const double c2 = cand(cen[t], hw[t], 2), c5 = cand(cen[t], hw[t], 5);
-              if ((r0 == 0 || r0 == 3) && qs >= 2 && qs <= 4 && l >= c2 && h <= c5) g = 1;   // solve from lists
-              else if (ctl.spec && (r0 == 2 || r0 == 4) && m_ >= c2 && m_ <= c5) g = 2;       // correct K~ xbar
-            }
-            gneed[t] = g;
-            ldec[t] = rq;
-            lo[t] = l; hi[t] = h;
-            wid[t] = adapt_width(r0, wid[t]);
+            wid[t] = adapt_width(r, wid[t]);
             mpv[t] = mu[t];
-            if (r0 != 0 && r0 != 3) mu[t] = m_;
-          }
-        }
-      }
-      __syncthreads();
-      if (lists) {
-        int anyg = 0;
-        for (int t = 0; t < P; ++t) anyg |= gneed[t];
-        if (anyg) {
-          gather_pool(s.blist, lpar, nwg, P, gneed, ptot, poff, pfill, pool);
-          __syncthreads();
-        }
-      }
-      {
-        const int lane = c.tid & 63, wave = c.tid >> 6;
-        for (int t = wave; t < P; t += NWAVE) {   // one wave per period
-          const int rq = ldec[t], r0 = rq & 15, qs = (rq >> 4) - 1, g = gneed[t];
-          const double l = lo[t], h = hi[t];
-          double m_ = mu[t];
-          int r = r0, nc = -1, k0 = 0;
-          if (g > 0) {
-            if (g == 1) {
-              int k1;
-              pool_range(pool, poff[t], ptot[t], l, h, k0, k1);
-              if (k1 - k0 <= 64) {
-                const ldbl* st = tot + STW * t;
-                m_ = solve_from_list(pool + 4 * k0, k1 - k0, l, h, st[2 + 3 * qs], st[3 + 3 * qs]);
-                r = 4;
-              }
-            }
-            const double c4 = cand(cen[t], hw[t], 4);
-            if (ctl.spec && r != 0 && r != 3 && m_ >= cand(cen[t], hw[t], 2) && m_ <= cand(cen[t], hw[t], 5)) {
-              int k1;
-              pool_range(pool, poff[t], ptot[t], fmin(m_, c4), fmax(m_, c4), k0, k1);
-              nc = k1 - k0;
-            }
-          }
-          if (lane == 0) {
-            ncor[t] = nc;
-            ncs[t] = k0;
             if (r == 1) {
+              mu[t] = m_;
               need[t] = 0;
             } else if (r == 2 || r == 4) {
               mu[t] = m_;
               need[t] = 0;
-              if (nc < 0) __hip_atomic_fetch_or(fbflag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+              __hip_atomic_fetch_or(fbflag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
             } else {
+              lo[t] = l; hi[t] = h;
               need[t] = 1;
               __hip_atomic_fetch_or(fbflag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
               __hip_atomic_fetch_or(msflag, r == 0 ? 1 : 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            }
+          }
+        }
+      } else {
+        {
+          const int lane = c.tid & 63, wave = c.tid >> 6;
+          for (int t = wave; t < P; t += NWAVE) {   // one wave per period
+            double l = 0.0, h = 0.0, m_ = 0.0;
+            const int rq = bracket_decide(tot + STW * t, cen[t], hw[t], l, h, m_);
+            if (lane == 0) {
+              const int r0 = rq & 15, qs = (rq >> 4) - 1;
+              int g = 0;
+              if (lists && r0 != 1) {
+                const double c2 = cand(cen[t], hw[t], 2), c5 = cand(cen[t], hw[t], 5);
+                if ((r0 == 0 || r0 == 3) && qs >= 2 && qs <= 4 && l >= c2 && h <= c5) g = 1;   // solve from lists
+                else if (ctl.spec && (r0 == 2 || r0 == 4) && m_ >= c2 && m_ <= c5) g = 2;       // correct K~ xbar
+              }
+              gneed[t] = g;
+              ldec[t] = rq;
+              lo[t] = l; hi[t] = h;
+              wid[t] = adapt_width(r0, wid[t]);
+              mpv[t] = mu[t];
+              if (r0 != 0 && r0 != 3) mu[t] = m_;
+            }
+          }
+        }
+        __syncthreads();
+        if (lists) {
+          int anyg = 0;
+          for (int t = 0; t < P; ++t) anyg |= gneed[t];
+          if (anyg) {
+            gather_pool(s.blist, lpar, nwg, P, gneed, ptot, poff, pfill, pool);
+            __syncthreads();
+          }
+        }
+        {
+          const int lane = c.tid & 63, wave = c.tid >> 6;
+          for (int t = wave; t < P; t += NWAVE) {   // one wave per period
+            const int rq = ldec[t], r0 = rq & 15, qs = (rq >> 4) - 1, g = gneed[t];
+            const double l = lo[t], h = hi[t];
+            double m_ = mu[t];
+            int r = r0, nc = -1, k0 = 0;
+            if (g > 0) {
+              if (g == 1) {
+                int k1;
+                pool_range(pool, poff[t], ptot[t], l, h, k0, k1);
+                if (k1 - k0 <= 64) {
+                  const ldbl* st = tot + STW * t;
+                  m_ = solve_from_list(pool + 4 * k0, k1 - k0, l, h, st[2 + 3 * qs], st[3 + 3 * qs]);
+                  r = 4;
+                }
+              }
+              const double c4 = cand(cen[t], hw[t], 4);
+              if (ctl.spec && r != 0 && r != 3 && m_ >= cand(cen[t], hw[t], 2) && m_ <= cand(cen[t], hw[t], 5)) {
+                int k1;
+                pool_range(pool, poff[t], ptot[t], fmin(m_, c4), fmax(m_, c4), k0, k1);
+                nc = k1 - k0;
+              }
+            }
+            if (lane == 0) {
+              ncor[t] = nc;
+              ncs[t] = k0;
+              if (r == 1) {
+                need[t] = 0;
+              } else if (r == 2 || r == 4) {
+                mu[t] = m_;
+                need[t] = 0;
+                if (nc < 0) __hip_atomic_fetch_or(fbflag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+              } else {
+                need[t] = 1;
+                __hip_atomic_fetch_or(fbflag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                __hip_atomic_fetch_or(msflag, r == 0 ? 1 : 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+              }
             }
           }
         }
@@ -1277,7 +1423,8 @@ __device__ __forceinline__ void solve_body(const DevProblem& p, const DevState& 
         if (anymiss & 2) sc->miss_out++;
         *fbflag = 0;
         *msflag = 0;
-        for (int t = 0; t < P; ++t) ptot[t] = 0;
+        if constexpr (LS)
+          for (int t = 0; t < P; ++t) ptot[t] = 0;
       }
       __syncthreads();
       const long long tb3 = wall_clock64();
@@ -1288,7 +1435,7 @@ __device__ __forceinline__ void solve_body(const DevProblem& p, const DevState& 
           const int t = e / nr, j = e - t * nr;
           const double c4 = cand(cen[t], hw[t], 4), m_ = mu[t];
           double v = tot[oP1 + e] + 2.0 * (m_ - c4) * tot[oP2 + e];
-          const int nc = ncor[t];
+          const int nc = LS ? (int)ncor[t] : -1;
           if (nc > 0) {
             // x_hat(mu) - (affine piece at c_4) = sgn(b)/(a dc) (|b| - mu) ([|b| > mu] - [|b| > c_4])
             const ldbl* lb = pool + 4 * ncs[t];
@@ -1308,7 +1455,7 @@ __device__ __forceinline__ void solve_body(const DevProblem& p, const DevState& 
       } else {
         int any = 0;
         for (int t = 0; t < P; ++t) any |= need[t];
-        if (any && !multisect(c, P, xv3, xv4, nw, need, lo, hi, mu, &sc->ms_rounds)) goto barrier_fail;
+        if (any && !multisect_x<LS>(c, P, xv3, xv4, nw, need, lo, hi, mu, &sc->ms_rounds)) goto barrier_fail;
         // exact K~ xbar for every period
         for (int e = c.tid; e < P * c.nwa; e += TB) {
           const int t = e / c.nwa, li = e % c.nwa;
@@ -1317,8 +1464,8 @@ __device__ __forceinline__ void solve_body(const DevProblem& p, const DevState& 
           xv1[t * nw + li] = 2.0 * xh - V.xs(t, li);
         }
         __syncthreads();
-        rows_prod<1>(c, V, xv1, xv1, nw, P, nr, [&](int e, const double* a) { put(c, e, a[0]); });
-        if (!xsync(c, P * nr)) goto barrier_fail;
+        rows_prod<1>(c, V, xv1, xv1, nw, P, nr, 0);
+        if (!xsync_x<LS>(c, P * nr)) goto barrier_fail;
         for (int e = c.tid; e < P * nr; e += TB) Kx[e] = tot[e];
         __syncthreads();
       }
@@ -1426,7 +1573,7 @@ __device__ __forceinline__ void solve_body(const DevProblem& p, const DevState& 
           if (lane == 0) put(c, oB + t, b);
         }
       }
-      rows_prod<1>(c, Vc, xv1, xv1, nw, P, nr, [&](int e, const double* a) { put(c, oR + e, a[0]); });
+      rows_prod<1>(c, Vc, xv1, xv1, nw, P, nr, oR);
       // dual inner problem: b' = alpha + arisk c - R' (signed, in bb), 1/a' in aa,
       // R' = unscaled K^T Y at T(y).
       kty_all(c, Vc, Tys, P, nr, nw, xv2);
@@ -1439,10 +1586,10 @@ __device__ __forceinline__ void solve_body(const DevProblem& p, const DevState& 
         xv4[t * nw + li] = 1.0 / Vc.arisk(0, li);
       }
       __syncthreads();
-      period_stats(c, xv3, xv4, nw, dcen, dhw, oD);
+      period_stats_x<LS>(c, xv3, xv4, nw, dcen, dhw, oD);
       c.mx_lo = oD;
       c.mx_hi = oD + STW * P;
-      if (!xsync(c, VC1)) goto barrier_fail;
+      if (!xsync_x<LS>(c, VC1)) goto barrier_fail;
       double c1s[16];
       for (int q = 0; q < 16; ++q) c1s[q] = tot[q];
       // row terms, spread over the threads: primal residual, clip norm, factor risk, and
@@ -1495,7 +1642,7 @@ __device__ __forceinline__ void solve_body(const DevProblem& p, const DevState& 
       __syncthreads();
       if (c.tid == 0) { *iflag = *fbflag; *fbflag = 0; }
       __syncthreads();
-      if (*iflag && !multisect(c, P, xv3, xv4, nw, need, dlo, dhi, dmu, &sc->ms_rounds)) goto barrier_fail;
+      if (*iflag && !multisect_x<LS>(c, P, xv3, xv4, nw, need, dlo, dhi, dmu, &sc->ms_rounds)) goto barrier_fail;
       for (int t = c.tid; t < P; t += TB) next_bracket(dmu[t], dmp[t], dwd[t], dcen[t], dhw[t]);
       __syncthreads();
       // C2: inner value sum (a'/2 w^2 - b' w), w = sign(b') max(|b'| - mu', 0) / a'
@@ -1509,7 +1656,7 @@ __device__ __forceinline__ void solve_body(const DevProblem& p, const DevState& 
         }
         wg_sum<1>(c, iv);
         if (c.tid == 0) put(c, 0, red[RED_OUT]);
-        if (!xsync(c, 1)) goto barrier_fail;
+        if (!xsync_x<LS>(c, 1)) goto barrier_fail;
       }
       const double psi = tot[0] + (double)P * p.crisk[0] - c1s[6] - c1s[5] + psi_rows;
       const double rel_pri = sqrt(pres2) / (1.0 + sqrt(clip2));
@@ -1822,7 +1969,7 @@ __global__ __launch_bounds__(TB) void k_adjoint(DevProblem p, AdjState a, DevCon
     wg_sum<2>(c, loc);
     if (c.tid == 0) { put(c, 0, red[RED_OUT]); put(c, 1, red[RED_OUT + 1]); }
     __syncthreads();
-    rows_prod<1>(c, V, xv1, xv1, nw, P, nr, [&](int e, const double* q) { put(c, 2 + e, q[0]); });
+    rows_prod<1>(c, V, xv1, xv1, nw, P, nr, 2);
     if (!xsync(c, 2 + P * nr)) goto adj_fail;
     {
       const double vv = tot[0];
@@ -1897,7 +2044,7 @@ __global__ __launch_bounds__(TB) void k_adjoint(DevProblem p, AdjState a, DevCon
       xv1[t * nw + li] = xb;
     }
     __syncthreads();
-    rows_prod<1>(c, V, xv1, xv1, nw, P, nr, [&](int e, const double* q) { put(c, e, q[0]); });
+    rows_prod<1>(c, V, xv1, xv1, nw, P, nr, 0);
     if (!xsync(c, P * nr)) goto adj_fail;
     for (int e = c.tid; e < P * nr; e += TB) {   // frozen clipped exposure rows
       const int j = e % nr;
@@ -1951,7 +2098,7 @@ __global__ __launch_bounds__(TB) void k_adjoint(DevProblem p, AdjState a, DevCon
           if (lane == 0) put(c, P * nr + t, v);
         }
       }
-      rows_prod<1>(c, V, xv2, xv2, nw, P, nr, [&](int e, const double* q) { put(c, e, q[0]); });
+      rows_prod<1>(c, V, xv2, xv2, nw, P, nr, 0);
       if (!xsync(c, P * nr + P)) return false;
       for (int e = c.tid; e < P * nr; e += TB) {
         const int j = e % nr;
@@ -2010,7 +2157,7 @@ __global__ __launch_bounds__(TB) void k_adjoint(DevProblem p, AdjState a, DevCon
           if (lane == 0) put(c, P * nr + t, v);
         }
       }
-      rows_prod<1>(c, V, xv2, xv2, nw, P, nr, [&](int e, const double* q) { put(c, e, q[0]); });
+      rows_prod<1>(c, V, xv2, xv2, nw, P, nr, 0);
       if (!xsync(c, P * nr + P)) return false;
       for (int t = c.tid; t < P; t += TB) stu[t] = (mu[t] > 0.0 && cS[t] > 0.0) ? tot[P * nr + t] / cS[t] : 0.0;
       __syncthreads();
