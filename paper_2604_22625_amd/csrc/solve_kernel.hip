@@ -842,17 +842,19 @@ __device__ __forceinline__ double* list_at(const double* blist, int par, int nwg
 
 // Gathers the lists of every period t with gneed[t] > 0 into pool[NPOOL][4] = (|b|, 1/a,
 // asset, sign(b)/(a dc)), period t in the entries [poff[t], poff[t] + ptot[t]), sorted by
-// (|b|, asset).  A period whose lists overflowed or that does not fit in the pool gets
-// gneed[t] = -1.  Every decision here depends only on the published counts, never on the
-// order of the appends, so all workgroups agree.  Whole workgroup; ptot is zero on entry
-// and returned holding the entry counts.
+// (|b|, asset).  Periods take pool space in order; a period whose lists overflowed, or
+// that (with all the needing periods before it) does not fit, gets gneed[t] = -1.  Every
+// decision here depends only on the published counts, never on the order of the
+// appends, so all workgroups agree.  Whole workgroup; ptot is zero on entry and returned
+// holding the entry counts.
 __device__ __noinline__ void gather_pool(const double* blist, int par, int nwg, int P, lint* gneed, lint* ptot,
                                             lint* poff, lint* pfill, ldbl* pool) {
   constexpr int U = 8;   // pairs per thread with loads in flight together
-  const int npair = P * nwg;
+  const int npair = P * nwg, tid = threadIdx.x;
+  const bool held = npair <= TB * U;   // one pass covers every pair: the counts stay in registers
+  double cn[U];
   // pass 1: per-period entry counts
-  for (int base = threadIdx.x; base < npair; base += TB * U) {
-    double cn[U];
+  for (int base = tid; base < npair; base += TB * U) {
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const int idx = base + u * TB, t = idx / nwg, w = idx - t * nwg;
@@ -867,29 +869,44 @@ __device__ __noinline__ void gather_pool(const double* blist, int par, int nwg, 
     }
   }
   __syncthreads();
-  if (threadIdx.x == 0) {
-    int off = 0;
-    for (int t = 0; t < P; ++t) {
-      pfill[t] = 0;
-      if (gneed[t] > 0 && off + ptot[t] > NPOOL) gneed[t] = -1;
-      if (gneed[t] <= 0) { ptot[t] = 0; continue; }
-      poff[t] = off;
-      off += ptot[t];
+  // pool offsets: exclusive prefix over the needing periods (wave 0, one lane per period)
+  if (tid < 64) {
+    int carry = 0;
+    for (int t0 = 0; t0 < P; t0 += 64) {
+      const int t = t0 + tid;
+      const int g = t < P ? (int)gneed[t] : 0;
+      const int v = g > 0 ? (int)ptot[t] : 0;
+      int incl = v;
+#pragma unroll
+      for (int d = 1; d < 64; d <<= 1) {
+        const int o = __shfl_up(incl, d);
+        if (tid >= d) incl += o;
+      }
+      const int excl = carry + incl - v;
+      if (t < P) {
+        const bool fits = g > 0 && excl + v <= NPOOL;
+        if (g > 0 && !fits) gneed[t] = -1;
+        ptot[t] = fits ? v : 0;
+        poff[t] = excl;
+        pfill[t] = 0;
+      }
+      carry += __shfl(incl, 63);
     }
   }
   __syncthreads();
   // pass 2: the entries
-  for (int base = threadIdx.x; base < npair; base += TB * U) {
-    double cn[U];
+  for (int base = tid; base < npair; base += TB * U) {
+    if (!held) {
 #pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const int idx = base + u * TB, t = idx / nwg, w = idx - t * nwg;
-      cn[u] = (idx < npair && gneed[t] > 0) ? ldd(list_at(blist, par, nwg, P, w, t)) : 0.0;
+      for (int u = 0; u < U; ++u) {
+        const int idx = base + u * TB, t = idx / nwg, w = idx - t * nwg;
+        cn[u] = (idx < npair && gneed[t] > 0) ? ldd(list_at(blist, par, nwg, P, w, t)) : 0.0;
+      }
     }
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      if (!(cn[u] > 0.0)) continue;
       const int idx = base + u * TB, t = idx / nwg, w = idx - t * nwg;
+      if (!(cn[u] > 0.0) || gneed[t] <= 0) continue;
       const int kmax = min((int)cn[u], LIST_CAP);
       const int pos = poff[t] + __hip_atomic_fetch_add(&pfill[t], kmax, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
       const double* L = list_at(blist, par, nwg, P, w, t) + 1;
@@ -908,15 +925,17 @@ __device__ __noinline__ void gather_pool(const double* blist, int par, int nwg, 
     }
   }
   __syncthreads();
-  // sort each period's entries in place by (|b|, asset): entry i takes its rank
+  // sort each period's entries in place by (|b|, asset): entry i takes its rank.  The
+  // offsets grow with the period, so entry i belongs to the last period starting at or
+  // before it.
   double e0 = 0.0, e1 = 0.0, e2 = 0.0, e3 = 0.0;
   int dst = -1;
   {
-    const int i = threadIdx.x;   // NPOOL == TB: one entry per thread
+    const int i = tid;   // NPOOL == TB: one entry per thread
     int t = -1;
     for (int u = 0; u < P; ++u)
-      if (ptot[u] > 0 && i >= poff[u] && i < poff[u] + ptot[u]) t = u;
-    if (t >= 0) {
+      if (poff[u] <= i) t = u;
+    if (t >= 0 && i < poff[t] + ptot[t]) {
       e0 = pool[4 * i]; e1 = pool[4 * i + 1]; e2 = pool[4 * i + 2]; e3 = pool[4 * i + 3];
       int r = 0;
       for (int j = poff[t]; j < poff[t] + ptot[t]; ++j) {
