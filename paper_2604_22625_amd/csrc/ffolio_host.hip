@@ -353,6 +353,7 @@ ffo_status ffo_solve(int64_t n, int64_t k, int64_t m, int64_t T, const double* a
       const int w = (int)((n + g - 1) / g);
       ffo::DevControl t = c;
       t.nw = w; t.nwg = (int)((n + w - 1) / w); t.lds_k = 1; t.lds_state = 0;
+      t.prec = ffo::PREC_FP64;   // the same grid for both forms: the FP32 slice is smaller, not the work
       if (ffo::solve_lds_bytes(p, t) <= lds_cap) { nw = w; nwg = t.nwg; break; }
     }
     c.nw = nw;

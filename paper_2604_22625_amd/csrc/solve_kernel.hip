@@ -388,10 +388,13 @@ __device__ __forceinline__ void kty_dev(const KG* K, int ldk, int i0, const ldbl
     double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
     int j = j0;
     for (; j + 4 <= j1; j += 4) {
-      s0 = fma((double)col[(size_t)j * ldk] * ks[j], yt[j], s0);
-      s1 = fma((double)col[(size_t)(j + 1) * ldk] * ks[j + 1], yt[j + 1], s1);
-      s2 = fma((double)col[(size_t)(j + 2) * ldk] * ks[j + 2], yt[j + 2], s2);
-      s3 = fma((double)col[(size_t)(j + 3) * ldk] * ks[j + 3], yt[j + 3], s3);
+      const KG k0 = col[(size_t)j * ldk], k1 = col[(size_t)(j + 1) * ldk];
+      const KG k2 = col[(size_t)(j + 2) * ldk], k3 = col[(size_t)(j + 3) * ldk];
+      __builtin_amdgcn_sched_barrier(0);   // the four loads in flight together
+      s0 = fma((double)k0 * ks[j], yt[j], s0);
+      s1 = fma((double)k1 * ks[j + 1], yt[j + 1], s1);
+      s2 = fma((double)k2 * ks[j + 2], yt[j + 2], s2);
+      s3 = fma((double)k3 * ks[j + 3], yt[j + 3], s3);
     }
     for (; j < j1; ++j) s0 = fma((double)col[(size_t)j * ldk] * ks[j], yt[j], s0);
     return (s0 + s1) + (s2 + s3);
@@ -481,10 +484,14 @@ __device__ __forceinline__ void rows_dev(const KG* K, int ldk, int i0, const ldb
       const ldbl* y1 = x1 + tr[0] * nw;
       const ldbl* y2 = x2 + tr[0] * nw;
       for (int li = lane; li < nwa; li += 64) {
-        double kv[RB];   // all RB loads issued before the first use
+        KG kr[RB];   // all RB loads issued before the first use
 #pragma unroll
-        for (int r = 0; r < RB; ++r) kv[r] = (double)rp[r][li];
+        for (int r = 0; r < RB; ++r) kr[r] = rp[r][li];
+        __builtin_amdgcn_sched_barrier(0);   // keep the conversions behind the loads
         const double u1 = y1[li], u2 = NX > 1 ? (double)y2[li] : 0.0;
+        double kv[RB];
+#pragma unroll
+        for (int r = 0; r < RB; ++r) kv[r] = (double)kr[r];
 #pragma unroll
         for (int r = 0; r < RB; ++r) {
           a[r][0] = fma(kv[r], u1, a[r][0]);
@@ -493,9 +500,13 @@ __device__ __forceinline__ void rows_dev(const KG* K, int ldk, int i0, const ldb
       }
     } else {
       for (int li = lane; li < nwa; li += 64) {
+        KG kr[RB];
+#pragma unroll
+        for (int r = 0; r < RB; ++r) kr[r] = rp[r][li];
+        __builtin_amdgcn_sched_barrier(0);
         double kv[RB];
 #pragma unroll
-        for (int r = 0; r < RB; ++r) kv[r] = (double)rp[r][li];
+        for (int r = 0; r < RB; ++r) kv[r] = (double)kr[r];
 #pragma unroll
         for (int r = 0; r < RB; ++r) {
           a[r][0] = fma(kv[r], x1[tr[r] * nw + li], a[r][0]);
