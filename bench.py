@@ -115,7 +115,9 @@ def _timed(torch, fn, reps):
 def comparisons(ff, torch, dev, dev_insts, tol, plain_value):
     """The other legs of the metric, each timed after one warm-up: the T=20 multi-period
     solve (n=3000), the FP32 form on the same n=5000 markets, the 256-instance batched
-    form against sequential plain solves of the same instances (a sample of 32, scaled),
+    form (FP64, FP32, FP32 with bfloat16 rows; the reduced forms with their weight error
+    against the FP64 batch) against sequential plain solves of the same instances (a sample
+    of 32, scaled),
     and the adjoint of the T=10 workload (forward + backward)."""
     from synth import make_config, batch_instance
     out = {}
@@ -137,12 +139,23 @@ def comparisons(ff, torch, dev, dev_insts, tol, plain_value):
                                        "all_ok": all(i.status == 0 for i in infos)}
     # batched form
     batch = make_config(3)
-    for prec in ("fp64", "fp32"):
+    offs = np.asarray(batch["offs"])
+    W64 = None
+    for prec in ("fp64", "fp32", "fp32_bf16k"):
         ff.solve_batched(batch, tol=tol, precision=prec)
         dt, (W, binfos) = _timed(torch, lambda: ff.solve_batched(batch, tol=tol, precision=prec), 2)
-        out[f"batched_256_{prec}"] = {"solves_per_s": len(binfos) / dt, "batch_ms": dt * 1e3,
-                                      "iters_max": int(max(i.iters for i in binfos)),
-                                      "all_ok": all(i.status == 0 for i in binfos)}
+        leg = {"solves_per_s": len(binfos) / dt, "batch_ms": dt * 1e3,
+               "iters_max": int(max(i.iters for i in binfos)), "all_ok": all(i.status == 0 for i in binfos)}
+        Wn = W.cpu().numpy()
+        if W64 is None:
+            W64 = Wn
+        else:
+            # error against the FP64 batch, per instance relative to max |w|
+            rel = [float(np.max(np.abs(Wn[a:b] - W64[a:b])) / max(1e-300, np.max(np.abs(W64[a:b]))))
+                   for a, b in zip(offs[:-1], offs[1:])]
+            leg["w_rel_err_vs_fp64_max"] = max(rel)
+            leg["w_rel_err_vs_fp64_median"] = float(np.median(rel))
+        out[f"batched_256_{prec}"] = leg
     nb = np.asarray(batch["n_b"])
     idx = np.linspace(0, len(nb) - 1, 32).astype(int)
     seq = [batch_instance(batch, int(b)) for b in idx]

@@ -60,8 +60,13 @@ typedef enum {
                               per-asset data copies in float32; every reduction, the
                               budget multipliers, checks, restarts and the KKT residual
                               in float64 against the float64 inputs                  */
-  FFO_FP32_BF16K = 2       /* batched solver only: as FP32, constraint matrix in bfloat16
-                              (ffo_solve returns FFO_EINVAL)                          */
+  FFO_FP32_BF16K = 2       /* batched solver only: as FP32, with the scaled constraint
+                              rows rounded to bfloat16 (to nearest even, through float)
+                              for the iteration and the checks alike, so the solve
+                              converges on the rounded problem; its weights differ from
+                              the FP64 solution by a few 1e-3 of max |w| (the caller
+                              states that error).  ffo_solve and ffo_adjoint return
+                              FFO_EINVAL                                              */
 } ffo_precision;
 
 typedef struct {
@@ -174,8 +179,8 @@ ffo_status ffo_adjoint(int64_t n, int64_t k, int64_t m, int64_t T,
  * Every instance runs the same restarted Halpern PDHG as ffo_solve, to its own relative
  * KKT tolerance, on a team of workgroups sized to its asset count; all teams of a launch
  * are resident at once and never wait for each other (batches larger than the resident
- * grid run in several launches, largest instances first).  opt->precision: FFO_FP64 or
- * FFO_FP32; opt->workgroups is ignored; statuses as in ffo_solve.
+ * grid run in several launches, largest instances first).  opt->precision: FFO_FP64,
+ * FFO_FP32 or FFO_FP32_BF16K; opt->workgroups is ignored; statuses as in ffo_solve.
  * Returns FFO_OK if every instance converged, else the most severe instance status
  * (FFO_EDEVICE > FFO_NUMERIC > FFO_TIMEOUT > FFO_NOT_CONVERGED); infos[b].status holds
  * each instance's own status.  FFO_EINVAL is returned before any device work.

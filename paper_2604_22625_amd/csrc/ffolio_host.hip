@@ -698,8 +698,8 @@ ffo_status ffo_solve_batched(int64_t B, const int64_t* n_b, int64_t n_max, int64
   if (opt.check_every < 1) return fail(FFO_EINVAL, "check_every must be >= 1");
   if (!(opt.time_limit_s > 0.0)) return fail(FFO_EINVAL, "time_limit_s must be positive");
   if (!(opt.reflection >= 0.0 && opt.reflection <= 1.0)) return fail(FFO_EINVAL, "reflection must lie in [0, 1]");
-  if (opt.precision != FFO_FP64 && opt.precision != FFO_FP32)
-    return fail(FFO_EINVAL, "ffo_solve_batched takes FFO_FP64 or FFO_FP32");
+  if (opt.precision != FFO_FP64 && opt.precision != FFO_FP32 && opt.precision != FFO_FP32_BF16K)
+    return fail(FFO_EINVAL, "ffo_solve_batched takes FFO_FP64, FFO_FP32 or FFO_FP32_BF16K");
 
   int dev = 0;
   HIPCHK(hipGetDevice(&dev));
@@ -711,7 +711,8 @@ ffo_status ffo_solve_batched(int64_t B, const int64_t* n_b, int64_t n_max, int64
   const int cus = std::max(1, prop.multiProcessorCount);
   const int nr = (int)(m + k);
   const int ldk = (int)((n_max + 63) / 64 * 64);
-  const int prec = opt.precision == FFO_FP32 ? ffo::PREC_FP32 : ffo::PREC_FP64;
+  const int prec = opt.precision == FFO_FP32 ? ffo::PREC_FP32
+                   : (opt.precision == FFO_FP32_BF16K ? ffo::PREC_BF16K : ffo::PREC_FP64);
 
   // ---- control and team sizing ----
   ffo::DevProblem p0{};
@@ -782,7 +783,9 @@ ffo_status ffo_solve_batched(int64_t B, const int64_t* n_b, int64_t n_max, int64
   auto carve = [&](size_t cnt, size_t elt) { const size_t o = off; off = align_up(off + cnt * elt); return o; };
   const size_t oK = carve((size_t)std::max(nr, 1) * ldk, 8), odc = carve(n_max, 8), odrC = carve(n_max, 8);
   const bool f32rows = prec == ffo::PREC_FP32;   // the batched kernel reads rows from device memory
+  const bool bf16rows = prec == ffo::PREC_BF16K;
   const size_t oKf = carve(f32rows ? (size_t)std::max(nr, 1) * ldk : 1, 4);
+  const size_t oKb = carve(bf16rows ? (size_t)std::max(nr, 1) * ldk : 1, 2);
   const size_t oar = carve(n_max, 8), ocv = carve(n_max, 8), obF = carve(std::max<int64_t>(k, 1), 8);
   const size_t ocr = carve(1, 8), oC = carve(std::max<int64_t>(k * k, 1), 8), onb = carve(B, 8);
   const size_t odrs = carve((size_t)B * std::max(nr, 1), 8), oca = carve(N, 8), ocb = carve(N, 8);
@@ -838,6 +841,8 @@ ffo_status ffo_solve_batched(int64_t B, const int64_t* n_b, int64_t n_max, int64
     return fail(FFO_EDEVICE, "setup kernel launch failed");
   if (f32rows && ffo::launch_to_float(D(oK), (float*)(Bd + oKf), (int64_t)nr * ldk, stream))
     return fail(FFO_EDEVICE, "setup kernel launch failed");
+  if (bf16rows && ffo::launch_to_bf16(D(oK), (uint16_t*)(Bd + oKb), (int64_t)nr * ldk, stream))
+    return fail(FFO_EDEVICE, "setup kernel launch failed");
   HIPCHK(hipMemsetAsync(Bd + obF, 0, (size_t)std::max<int64_t>(k, 1) * 8, hs));
   HIPCHK(hipMemsetAsync(Bd + ocr, 0, 8, hs));
   HIPCHK(hipMemsetAsync(Bd + oxb, 0, (size_t)B * 3 * c0.vmax * 8, hs));
@@ -853,7 +858,8 @@ ffo_status ffo_solve_batched(int64_t B, const int64_t* n_b, int64_t n_max, int64
     const int64_t o = offs[b];
     ffo::DevProblem p = p0;
     p.n = (int)n_b[b];
-    p.K = D(oK); p.Kf = f32rows ? (const float*)(Bd + oKf) : nullptr; p.dr = D(odrs) + (size_t)b * nr; p.dc = D(odc); p.drC = D(odrC); p.alpha = alpha + o;
+    p.K = D(oK); p.Kf = f32rows ? (const float*)(Bd + oKf) : nullptr;
+    p.Kb = bf16rows ? (const uint16_t*)(Bd + oKb) : nullptr; p.dr = D(odrs) + (size_t)b * nr; p.dc = D(odc); p.drC = D(odrC); p.alpha = alpha + o;
     p.arisk = D(oar); p.cvec = D(ocv); p.ca = D(oca) + o; p.cb = D(ocb) + o; p.w0 = w0 + o; p.wT = nullptr;
     p.L = m ? L + (size_t)b * m : nullptr; p.U = m ? U + (size_t)b * m : nullptr;
     p.bF = D(obF); p.crisk = D(ocr); p.g1 = g1; p.d = d; p.g2 = g2;

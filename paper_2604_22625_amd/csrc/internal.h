@@ -24,6 +24,7 @@ struct DevProblem {
   int32_t kscaled;      // 1: K holds diag(dr) K diag(dc); 0: K holds K diag(dc), rows scaled by dr on use
   const double* K;      // [nr][ldk] constraint rows (see kscaled)
   const float* Kf;      // the same rows rounded to float (FP32 form reading rows from device memory), or null
+  const uint16_t* Kb;   // the same rows as bfloat16 bit patterns (PREC_BF16K), or null
   const double* dr;     // [nr]
   const double* dc;     // [n]
   const double* drC;    // [Tp][n]
@@ -78,7 +79,8 @@ struct DevControl {
 constexpr int LIST_CAP = 8;
 constexpr int LIST_W = 1 + 4 * LIST_CAP;
 
-enum Prec { PREC_FP64 = 0, PREC_FP32 = 1 };
+// PREC_BF16K: the FP32 form reading rows rounded to bfloat16 (batched kernel only).
+enum Prec { PREC_FP64 = 0, PREC_FP32 = 1, PREC_BF16K = 2 };
 
 // Adjoint of the solve operator at a solution (device memory; see adjoint_body).
 struct AdjState {
@@ -136,6 +138,9 @@ int launch_setup_batch(int64_t B, const int64_t* nb_dev, int64_t n_max, int64_t 
                        void* stream);
 // Kf[i] = (float)K[i] for i < count (FP32 form).
 int launch_to_float(const double* K, float* Kf, int64_t count, void* stream);
+// Kb[i] = bfloat16(K[i]) (round to nearest even, through float), then K[i] = Kb[i] exactly,
+// so that every reader of K sees the rounded rows.
+int launch_to_bf16(double* K, uint16_t* Kb, int64_t count, void* stream);
 int launch_setup(int64_t n, int64_t k, int64_t m, int64_t P, int64_t Tp, int ldk,
                  const double* F, const double* Cfac, const double* A, const double* delta,
                  const double* s, const double* q, const double* wT, double g1, double g2,

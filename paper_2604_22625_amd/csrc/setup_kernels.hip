@@ -165,6 +165,23 @@ __global__ __launch_bounds__(TB) void k_to_float(const double* __restrict__ K, f
     Kf[i] = (float)K[i];
 }
 
+__global__ __launch_bounds__(TB) void k_to_bf16(double* __restrict__ K, uint16_t* __restrict__ Kb, int64_t count) {
+  for (int64_t i = blockIdx.x * (int64_t)TB + threadIdx.x; i < count; i += (int64_t)gridDim.x * TB) {
+    uint32_t u = __float_as_uint((float)K[i]);   // inputs are finite (validated)
+    u += 0x7FFFu + ((u >> 16) & 1u);              // round to nearest, ties to even
+    const uint16_t b = (uint16_t)(u >> 16);
+    Kb[i] = b;
+    K[i] = (double)__uint_as_float((uint32_t)b << 16);
+  }
+}
+
+int launch_to_bf16(double* K, uint16_t* Kb, int64_t count, void* stream) {
+  if (count <= 0) return 0;
+  const int64_t nb = std::min<int64_t>((count + TB - 1) / TB, 4096);
+  hipLaunchKernelGGL(k_to_bf16, dim3((unsigned)nb), dim3(TB), 0, (hipStream_t)stream, K, Kb, count);
+  return hipGetLastError() == hipSuccess ? 0 : 1;
+}
+
 int launch_to_float(const double* K, float* Kf, int64_t count, void* stream) {
   if (count <= 0) return 0;
   const int64_t nb = std::min<int64_t>((count + TB - 1) / TB, 4096);

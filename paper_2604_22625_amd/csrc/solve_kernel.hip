@@ -332,14 +332,37 @@ struct Iter {
   }
 };
 
+// A bfloat16 bit pattern in device memory (rows of the FP32_BF16K form); widening to
+// double is exact.
+struct bf16 {
+  uint16_t b;
+  __device__ __forceinline__ explicit operator double() const { return (double)__uint_as_float((uint32_t)b << 16); }
+};
+
+// Row element loaded through a global-address pointer.
+template <class T>
+__device__ __forceinline__ T gload(const gmem_t<T>* p) { return *p; }
+template <>
+__device__ __forceinline__ bf16 gload<bf16>(const gmem_t<bf16>* p) {
+  bf16 r;
+  r.b = *(const gmem_t<uint16_t>*)p;
+  return r;
+}
+
+// Element type of the rows read from device memory: double in the FP64 form, float in
+// the FP32 form (bf16 is chosen explicitly).
+template <class R>
+struct default_kg {
+  using type = typename std::conditional<std::is_same<R, float>::value, float, double>::type;
+};
+
 // R: stored type of the per-asset iterates and of the LDS copies (double in the FP64
 // form, float in the FP32 form); every expression evaluates in double.
-template <bool KL, bool SL, class R = double>
+template <bool KL, bool SL, class R = double, class KGT = typename default_kg<R>::type>
 struct S {
   using RC = typename std::conditional<SL, R, double>::type;   // constants: LDS copies or FP64 inputs
   static constexpr bool KLDS = KL;
-  // element type of the rows read from device memory: float in the FP32 form
-  using KG = typename std::conditional<std::is_same<R, float>::value, float, double>::type;
+  using KG = KGT;
   const DevProblem* p;
   const lds_t<R>* Kl;   // LDS slice [nr][ldl] (KL) ...
   const KG* Kg;         // ... or the rows in device memory, times the LDS row scale ks
@@ -388,15 +411,15 @@ __device__ __forceinline__ void kty_dev(const KG* K, int ldk, int i0, const ldbl
     double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
     int j = j0;
     for (; j + 4 <= j1; j += 4) {
-      const KG k0 = col[(size_t)j * ldk], k1 = col[(size_t)(j + 1) * ldk];
-      const KG k2 = col[(size_t)(j + 2) * ldk], k3 = col[(size_t)(j + 3) * ldk];
+      const KG k0 = gload(col + (size_t)j * ldk), k1 = gload(col + (size_t)(j + 1) * ldk);
+      const KG k2 = gload(col + (size_t)(j + 2) * ldk), k3 = gload(col + (size_t)(j + 3) * ldk);
       __builtin_amdgcn_sched_barrier(0);   // the four loads in flight together
       s0 = fma((double)k0 * ks[j], yt[j], s0);
       s1 = fma((double)k1 * ks[j + 1], yt[j + 1], s1);
       s2 = fma((double)k2 * ks[j + 2], yt[j + 2], s2);
       s3 = fma((double)k3 * ks[j + 3], yt[j + 3], s3);
     }
-    for (; j < j1; ++j) s0 = fma((double)col[(size_t)j * ldk] * ks[j], yt[j], s0);
+    for (; j < j1; ++j) s0 = fma((double)gload(col + (size_t)j * ldk) * ks[j], yt[j], s0);
     return (s0 + s1) + (s2 + s3);
   };
   if (ne == 0) { __syncthreads(); return; }
@@ -486,7 +509,7 @@ __device__ __forceinline__ void rows_dev(const KG* K, int ldk, int i0, const ldb
       for (int li = lane; li < nwa; li += 64) {
         KG kr[RB];   // all RB loads issued before the first use
 #pragma unroll
-        for (int r = 0; r < RB; ++r) kr[r] = rp[r][li];
+        for (int r = 0; r < RB; ++r) kr[r] = gload(rp[r] + li);
         __builtin_amdgcn_sched_barrier(0);   // keep the conversions behind the loads
         const double u1 = y1[li], u2 = NX > 1 ? (double)y2[li] : 0.0;
         double kv[RB];
@@ -502,7 +525,7 @@ __device__ __forceinline__ void rows_dev(const KG* K, int ldk, int i0, const ldb
       for (int li = lane; li < nwa; li += 64) {
         KG kr[RB];
 #pragma unroll
-        for (int r = 0; r < RB; ++r) kr[r] = rp[r][li];
+        for (int r = 0; r < RB; ++r) kr[r] = gload(rp[r] + li);
         __builtin_amdgcn_sched_barrier(0);
         double kv[RB];
 #pragma unroll
@@ -1040,7 +1063,7 @@ template <class R>
 __host__ __device__ constexpr size_t lds_doubles(size_t count) { return (count * sizeof(R) + 7) / 8; }
 
 // One solve by a team of nwg workgroups; this workgroup is rank wg of the team.
-template <bool KL, bool SL, class R, bool LS>
+template <bool KL, bool SL, class R, bool LS, class KGT = typename default_kg<R>::type>
 __device__ __forceinline__ void solve_body(const DevProblem& p, const DevState& s, const DevControl& ctl, int wg,
                                            int nwg) {
   ldbl* lds = (ldbl*)g_lds;
@@ -1099,7 +1122,7 @@ __device__ __forceinline__ void solve_body(const DevProblem& p, const DevState& 
   const bool lists = LS && ctl.lists;       // breakpoint lists (single-team launches only)
   ldbl* pool = nullptr;                     // gathered breakpoint lists (sorted)
   if (lists) { pool = ptr; ptr += NPOOL * 4; }
-  using SV = S<KL, SL, R>;
+  using SV = S<KL, SL, R, KGT>;
   SV V;
   V.p = &p;
   V.nw = nw;
@@ -1167,7 +1190,8 @@ __device__ __forceinline__ void solve_body(const DevProblem& p, const DevState& 
   c.flag = iflag;
   c.lslot = lslot;
   V.Kl = Kl;
-  if constexpr (std::is_same<typename SV::KG, float>::value) V.Kg = p.Kf;
+  if constexpr (std::is_same<typename SV::KG, bf16>::value) V.Kg = (const bf16*)p.Kb;
+  else if constexpr (std::is_same<typename SV::KG, float>::value) V.Kg = p.Kf;
   else V.Kg = p.K;
   V.ks = ks;
 
@@ -1837,13 +1861,13 @@ __global__ __launch_bounds__(TB) void k_solve(DevProblem p, DevState s, DevContr
 }
 
 // Batched: every team solves its own instance; teams never wait for each other.
-template <bool KL, bool SL, class R>
+template <bool KL, bool SL, class R, class KGT = typename default_kg<R>::type>
 __global__ __launch_bounds__(TB) __attribute__((amdgpu_waves_per_eu(2))) void k_solve_batch(const DevProblem* __restrict__ dp, const DevState* __restrict__ ds,
                                                     const DevControl* __restrict__ dcl, const int* __restrict__ wg_team,
                                                     const int* __restrict__ wg_rank) {
   const int team = wg_team[blockIdx.x];
   const DevControl ctl = dcl[team];
-  solve_body<KL, SL, R, false>(dp[team], ds[team], ctl, wg_rank[blockIdx.x], ctl.nwg);
+  solve_body<KL, SL, R, false, KGT>(dp[team], ds[team], ctl, wg_rank[blockIdx.x], ctl.nwg);
 }
 
 // ---------------------------------------------------------------------------------
@@ -2404,7 +2428,7 @@ static size_t state_lds_doubles(size_t P, size_t Tp, size_t nw) {
 
 size_t solve_lds_bytes(const DevProblem& p, const DevControl& c) {
   const size_t P = p.P, Tp = p.Tp, nr = p.nr, nw = c.nw;
-  const bool f32 = c.prec == PREC_FP32;
+  const bool f32 = c.prec != PREC_FP64;
   size_t d = 0;
   if (c.lds_k) d += f32 ? lds_doubles<float>(nr * (nw | 1)) : lds_doubles<double>(nr * (nw | 1));
   d += 4 * P * nr + 4 * P * nw + (size_t)c.vmax + RED_LEN + 14 * P + nr;
@@ -2429,6 +2453,9 @@ int launch_solve(const DevProblem& p, const DevState& s, const DevControl& c, vo
 }
 
 static const void* batch_fn(int kl, int sl, int prec) {
+  // the batched kernel reads its rows from device memory: no LDS slice in the bf16 form
+  if (prec == PREC_BF16K) return kl ? nullptr : (sl ? (const void*)k_solve_batch<false, true, float, bf16>
+                                                      : (const void*)k_solve_batch<false, false, float, bf16>);
   if (prec == PREC_FP32)
     return kl ? (sl ? (const void*)k_solve_batch<true, true, float> : (const void*)k_solve_batch<true, false, float>)
               : (sl ? (const void*)k_solve_batch<false, true, float> : (const void*)k_solve_batch<false, false, float>);
@@ -2439,14 +2466,17 @@ static const void* batch_fn(int kl, int sl, int prec) {
 int launch_solve_batch(const DevProblem* dp, const DevState* ds, const DevControl* dc, const int* wg_team,
                        const int* wg_rank, int nblocks, int kl, int sl, int prec, void* stream, size_t lds) {
   void* args[] = {(void*)&dp, (void*)&ds, (void*)&dc, (void*)&wg_team, (void*)&wg_rank};
-  hipError_t e = hipLaunchCooperativeKernel(batch_fn(kl, sl, prec), dim3(nblocks), dim3(TB), args,
+  const void* fn = batch_fn(kl, sl, prec);
+  if (!fn) return (int)hipErrorInvalidValue;
+  hipError_t e = hipLaunchCooperativeKernel(fn, dim3(nblocks), dim3(TB), args,
                                             (unsigned int)lds, (hipStream_t)stream);
   return e == hipSuccess ? 0 : (int)e;
 }
 
 int solve_batch_occupancy(int kl, int sl, int prec, size_t lds) {
   int blocks = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, batch_fn(kl, sl, prec), TB, lds) != hipSuccess) return 0;
+  const void* fn = batch_fn(kl, sl, prec);
+  if (!fn || hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, fn, TB, lds) != hipSuccess) return 0;
   return blocks;
 }
 

@@ -79,7 +79,7 @@ def test_invalid_options_rejected_on_host():
     lib = ff.lib()
     fake = ctypes.c_void_p(0x1000)
     for field, val in (("tol_rel_kkt", 0.0), ("max_iter", 0), ("check_every", 0), ("reflection", 1.5),
-                       ("precision", 7), ("time_limit_s", -1.0)):
+                       ("precision", 7), ("precision", 2), ("time_limit_s", -1.0)):   # bf16 rows: batched only
         o = ff.default_options()
         setattr(o, field, val)
         info = ff._Info()
@@ -122,7 +122,7 @@ def _call_batched(B=3, n_b=(5, 7, 9), n_max=10, k=2, m=1, offs=None, d=1.5, prec
     (dict(k=129), "k must"),
     (dict(m=-1), "m must"),
     (dict(d=1.0), "d must"),
-    (dict(precision=2), "FFO_FP64 or FFO_FP32"),
+    (dict(precision=7), "FFO_FP64, FFO_FP32 or FFO_FP32_BF16K"),
     (dict(null=("alpha",)), "null"),
     (dict(null=("w_out",)), "null"),
     (dict(null=("F",)), "F and Omega"),
