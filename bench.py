@@ -193,7 +193,7 @@ def main():
     a = parse()
     if a.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}), flush=True)
-        print("bench.py: only --gpus 1 is supported (single-GPU solver; see DESIGN.md for sharding)",
+        print("bench.py: only --gpus 1 is supported (the solver runs on one GPU; sharding across GPUs is not built)",
               file=sys.stderr)
         sys.exit(2)
     import torch
