@@ -192,7 +192,7 @@ def comparisons(ff, torch, dev, dev_insts, tol, plain_value):
 def main():
     a = parse()
     if a.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}), flush=True)
+        print(json.dumps({"error": "the solver runs on one GPU; --gpus must be 1"}), flush=True)
         print("bench.py: only --gpus 1 is supported (the solver runs on one GPU; sharding across GPUs is not built)",
               file=sys.stderr)
         sys.exit(2)
