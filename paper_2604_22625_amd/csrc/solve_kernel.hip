@@ -771,6 +771,32 @@ __device__ int bracket_decide(const ldbl* st, double cen, double hw, double& lo,
   return (qs == 3 ? 0 : 3) | ((qs + 1) << 4);
 }
 
+// The same decision with eight lanes per period (lane & 7 = candidate, lane >> 3 = group),
+// so one wave decides eight periods at once.  Called by the eight lanes of each group that
+// has a period; the lanes of a group receive the same results.
+__device__ __forceinline__ int bracket_decide8(const ldbl* st, double cen, double hw, double& lo, double& hi,
+                                               double& mu) {
+  static_assert(NC == 8, "one lane per candidate");
+  const double S0 = st[0], maxb = st[1];
+  if (S0 <= 1.0) { mu = 0.0; return (cen + hw <= 0.0) ? 1 : 2; }
+  const int lane = threadIdx.x & 63, sub = lane & 7, grp = lane >> 3;
+  const unsigned long long all = __ballot(st[2 + 3 * sub] >= 1.0);
+  const unsigned ge = (unsigned)((all >> (8 * grp)) & 0xFFull);
+  int qs = ge ? 31 - __clz(ge) : -1;   // S is non-increasing: {q : S(c_q) >= 1} = [0, qs]
+  double a, b;
+  if (qs < 0) { a = 0.0; b = cand(cen, hw, 0); }
+  else if (qs == NC - 1) { a = cand(cen, hw, NC - 1); b = maxb; }
+  else { a = cand(cen, hw, qs); b = cand(cen, hw, qs + 1); }
+  if (qs >= 0 && qs < NC - 1 && st[4 + 3 * qs] == st[4 + 3 * (qs + 1)] && st[3 + 3 * qs] > 0.0) {
+    mu = fmin(fmax(a + (st[2 + 3 * qs] - 1.0) / st[3 + 3 * qs], a), b);
+    return qs == 3 ? 1 : 4;
+  }
+  if (!(b >= a)) { a = 0.0; b = maxb; qs = -1; }
+  lo = a;
+  hi = b;
+  return (qs == 3 ? 0 : 3) | ((qs + 1) << 4);
+}
+
 // Multisection for the periods with need[t] != 0 (caller synchronised; S(lo) >= 1 >= S(hi)):
 // MSC candidates per round, TB / MSC lanes per candidate.  absb/inva as in period_stats.
 __device__ __forceinline__ bool multisect(Ctx& c, int P, const ldbl* absb, const ldbl* inva, int nw, lint* need, ldbl* lo,
@@ -1395,11 +1421,13 @@ __device__ __forceinline__ void solve_body(const DevProblem& p, const DevState& 
         }
       } else {
         {
-          const int lane = c.tid & 63, wave = c.tid >> 6;
-          for (int t = wave; t < P; t += NWAVE) {   // one wave per period
+          const int lane = c.tid & 63, wave = c.tid >> 6, grp = lane >> 3, sub = lane & 7;
+          for (int t0 = wave * 8; t0 < P; t0 += NWAVE * 8) {   // eight periods per wave
+            const int t = t0 + grp;
+            if (t >= P) continue;
             double l = 0.0, h = 0.0, m_ = 0.0;
-            const int rq = bracket_decide(tot + STW * t, cen[t], hw[t], l, h, m_);
-            if (lane == 0) {
+            const int rq = bracket_decide8(tot + STW * t, cen[t], hw[t], l, h, m_);
+            if (sub == 0) {
               const int r0 = rq & 15, qs = (rq >> 4) - 1;
               int g = 0;
               if (lists && r0 != 1) {
