@@ -118,7 +118,7 @@ def comparisons(ff, torch, dev, dev_insts, tol, plain_value):
     form (FP64, FP32, FP32 with bfloat16 rows; the reduced forms with their weight error
     against the FP64 batch) against sequential plain solves of the same instances (a sample
     of 32, scaled),
-    and the adjoint of the T=10 workload (forward + backward)."""
+    and the adjoint of the T=10 workload (FP32 forward + FP64 backward)."""
     from synth import make_config, batch_instance
     out = {}
     # T = 20 multi-period, FP64 and FP32
@@ -177,15 +177,21 @@ def comparisons(ff, torch, dev, dev_insts, tol, plain_value):
     gW[-1] = c4["r"]
     gWd = torch.as_tensor(gW, device=dev)
 
-    def fwd_bwd():
-        W, info, Y = ff.solve_instance(c4, tol=tol, return_dual=True)
+    # FP32 forward (FP64 restarts and checks), FP64 adjoint; the gradient is compared with
+    # the one at the FP64 forward solution
+    def fwd_bwd(prec):
+        W, info, Y = ff.solve_instance(c4, tol=tol, return_dual=True, precision=prec)
         ga, gs, gF, ainfo = ff.adjoint(c4, W, Y, gWd, omega=info.omega, tol=1e-9)
-        return info, ainfo
-    fwd_bwd()
-    dt, (finfo, ainfo) = _timed(torch, fwd_bwd, 1)
-    out["adjoint_T10_n2000"] = {"forward_plus_backward_ms": dt * 1e3, "forward_kernel_ms": finfo.ms_iter,
+        return info, ainfo, ga
+    _, _, ga64 = fwd_bwd("fp64")
+    fwd_bwd("fp32")
+    dt, (finfo, ainfo, ga32) = _timed(torch, lambda: fwd_bwd("fp32"), 1)
+    rel = float(torch.linalg.norm(ga32 - ga64) / torch.linalg.norm(ga64))
+    out["adjoint_T10_n2000"] = {"forward_precision": "fp32", "forward_plus_backward_ms": dt * 1e3,
+                                "forward_kernel_ms": finfo.ms_iter, "forward_iters": finfo.iters,
                                 "adjoint_kernel_ms": ainfo.ms_iter, "adjoint_iters": ainfo.iters,
-                                "adjoint_rel_residual": ainfo.rel_kkt}
+                                "adjoint_rel_residual": ainfo.rel_kkt,
+                                "grad_alpha_rel_diff_vs_fp64_forward": rel}
     return out
 
 

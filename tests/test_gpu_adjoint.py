@@ -87,6 +87,27 @@ def test_autograd_function_matches_adjoint():
     assert _rel(F.grad.cpu().numpy(), ref.F) <= 1e-4
 
 
+def test_fp32_forward_then_adjoint():
+    """The FP32 form as the forward solve (FP64 restarts and checks), then the FP64 adjoint
+    at its solution: the gradients stay within 1e-2 of the reference gradient (the FP32
+    solution is good to relative KKT 1e-7, which moves W* by ~1e-6 relative)."""
+    ff = _gpu()
+    inst = make_multi(5, 40, 2, 2, seed=17)
+    gW = np.zeros((4, 40))
+    gW[-1] = np.random.default_rng(5).normal(size=40)
+    ref = reference_gradient(inst, gW)
+    dev = torch.device("cuda", 0)
+    alpha = torch.tensor(inst["alpha"], device=dev, requires_grad=True)
+    s = torch.tensor(inst["s"], device=dev, requires_grad=True)
+    F = torch.tensor(inst["F"], device=dev, requires_grad=True)
+    rest = {k: v for k, v in inst.items() if k not in ("alpha", "s", "F")}
+    W = ff.FolioFn.apply(alpha, s, F, rest, {"tol": 1e-7, "precision": "fp32"})
+    (torch.tensor(gW, device=dev) * W).sum().backward()
+    assert _rel(alpha.grad.cpu().numpy(), ref.alpha) <= 1e-2
+    assert _rel(s.grad.cpu().numpy(), ref.s) <= 1e-2
+    assert _rel(F.grad.cpu().numpy(), ref.F) <= 1e-2
+
+
 def test_full_size_multi_period_against_device_differences():
     """T = 10, n = 2000, k = 40, m = 40 with l = r^T w_{T-1} (the last decision): the
     adjoint's directional derivatives against central differences of the device solve."""
