@@ -410,6 +410,20 @@ __device__ __forceinline__ void kty_dev(const KG* K, int ldk, int i0, const ldbl
     const gmem_t<KG>* col = (const gmem_t<KG>*)(K + i0 + li);
     double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
     int j = j0;
+    for (; j + 8 <= j1; j += 8) {   // eight loads in flight, summed as two steps of four
+      KG kr[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) kr[u] = gload(col + (size_t)(j + u) * ldk);
+      __builtin_amdgcn_sched_barrier(0);
+      s0 = fma((double)kr[0] * ks[j], yt[j], s0);
+      s1 = fma((double)kr[1] * ks[j + 1], yt[j + 1], s1);
+      s2 = fma((double)kr[2] * ks[j + 2], yt[j + 2], s2);
+      s3 = fma((double)kr[3] * ks[j + 3], yt[j + 3], s3);
+      s0 = fma((double)kr[4] * ks[j + 4], yt[j + 4], s0);
+      s1 = fma((double)kr[5] * ks[j + 5], yt[j + 5], s1);
+      s2 = fma((double)kr[6] * ks[j + 6], yt[j + 6], s2);
+      s3 = fma((double)kr[7] * ks[j + 7], yt[j + 7], s3);
+    }
     for (; j + 4 <= j1; j += 4) {
       const KG k0 = gload(col + (size_t)j * ldk), k1 = gload(col + (size_t)(j + 1) * ldk);
       const KG k2 = gload(col + (size_t)(j + 2) * ldk), k3 = gload(col + (size_t)(j + 3) * ldk);
@@ -506,19 +520,31 @@ __device__ __forceinline__ void rows_dev(const KG* K, int ldk, int i0, const ldb
     if (tr[0] == tr[RB - 1]) {   // all RB rows in one period: one x value per asset
       const ldbl* y1 = x1 + tr[0] * nw;
       const ldbl* y2 = x2 + tr[0] * nw;
-      for (int li = lane; li < nwa; li += 64) {
-        KG kr[RB];   // all RB loads issued before the first use
+      // four assets per lane and step (li, li + 64, li + 128, li + 192: the order of a
+      // one-asset loop), so 4 RB loads are in flight per lane; past the end of the slice
+      // a load repeats li and its product is skipped
+      for (int li = lane; li < nwa; li += 256) {
+        int lk[4];
+        bool in[4];
 #pragma unroll
-        for (int r = 0; r < RB; ++r) kr[r] = gload(rp[r] + li);
+        for (int h = 0; h < 4; ++h) { lk[h] = li + 64 * h; in[h] = lk[h] < nwa; }
+        KG kr[4][RB];
+#pragma unroll
+        for (int h = 0; h < 4; ++h)
+#pragma unroll
+          for (int r = 0; r < RB; ++r) kr[h][r] = gload(rp[r] + (in[h] ? lk[h] : li));
         __builtin_amdgcn_sched_barrier(0);   // keep the conversions behind the loads
-        const double u1 = y1[li], u2 = NX > 1 ? (double)y2[li] : 0.0;
-        double kv[RB];
 #pragma unroll
-        for (int r = 0; r < RB; ++r) kv[r] = (double)kr[r];
+        for (int h = 0; h < 4; ++h) {
+          if (in[h]) {
+            const double v1 = y1[lk[h]], v2 = NX > 1 ? (double)y2[lk[h]] : 0.0;
 #pragma unroll
-        for (int r = 0; r < RB; ++r) {
-          a[r][0] = fma(kv[r], u1, a[r][0]);
-          if (NX > 1) a[r][NX - 1] = fma(kv[r], u2, a[r][NX - 1]);
+            for (int r = 0; r < RB; ++r) {
+              const double kv = (double)kr[h][r];
+              a[r][0] = fma(kv, v1, a[r][0]);
+              if (NX > 1) a[r][NX - 1] = fma(kv, v2, a[r][NX - 1]);
+            }
+          }
         }
       }
     } else {
