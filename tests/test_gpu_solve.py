@@ -279,3 +279,20 @@ def test_full_size_multi_period_kkt(cfg, seed, precision):
     assert abs(K.primal_obj - info.primal_obj) <= 1e-10 * abs(K.primal_obj)
     # feasibility of the returned weights: budgets and exposure bounds
     assert np.all(np.abs(W).sum(axis=1) <= 1.0 + 1e-5)
+
+
+def test_large_single_period_kkt():
+    """n = 200000 (k = 60, m = 80): 782 assets per workgroup, so every workgroup reads its
+    rows from device memory (the wide row products).  Checked through the oracle's
+    independent KKT evaluation of the returned pair and the feasibility of W."""
+    inst = make_single(200000, 60, 80, seed=5)
+    W, info, Y = _run(inst, tol=1e-6)
+    pb = _dual_problem(inst)
+    assert info.status == 0 and info.rel_kkt <= 1e-6
+    K = kkt(pb, W, *Y)
+    assert K.rel_kkt <= 2e-6, (K, info)
+    assert abs(K.primal_obj - info.primal_obj) <= 1e-10 * abs(K.primal_obj)
+    # feasibility of the returned weights: budget and exposure bounds
+    assert np.all(np.abs(W).sum(axis=1) <= 1.0 + 1e-5)
+    AW = W @ pb.A.T
+    assert np.all(AW >= pb.L - 1e-4) and np.all(AW <= pb.U + 1e-4)
