@@ -502,7 +502,7 @@ __device__ __forceinline__ void kty_all(const Ctx& c, const SV& v, const ldbl* y
 template <int NX, class KG>
 __device__ __forceinline__ void rows_dev(const KG* K, int ldk, int i0, const ldbl* ks, const ldbl* x1, const ldbl* x2,
                                       int nw, int nwa, int P, int nr, PutTo q, int off1, int off2) {
-  constexpr int RB = 8;
+  constexpr int RB = 6;   // 70 rows: three steps with every wave busy (8 would leave one wave alone)
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, ntot = P * nr;
   for (int base = wave * RB; base < ntot; base += NWAVE * RB) {
     double a[RB][NX];
