@@ -1115,6 +1115,23 @@ template <class R>
 __host__ __device__ constexpr size_t lds_doubles(size_t count) { return (count * sizeof(R) + 7) / 8; }
 
 // One solve by a team of nwg workgroups; this workgroup is rank wg of the team.
+// Elementwise pass over e in [0, ne) with two elements per thread and step, for per-asset
+// state in device memory: both elements' loads are issued before the first store.  With
+// one element per step every element waits a full memory round trip, because the compiler
+// cannot move a load above a store that may alias it.  Elements are taken in the order
+// of a one-element loop.
+template <class L, class W>
+__device__ __forceinline__ void each2(int tid, int ne, L load, W work) {
+  for (int e = tid; e < ne; e += 2 * TB) {
+    const int e1 = e + TB;
+    const bool two = e1 < ne;
+    const auto a = load(e);
+    const auto b = load(two ? e1 : e);
+    work(a);
+    if (two) work(b);
+  }
+}
+
 template <bool KL, bool SL, class R, bool LS, class KGT = typename default_kg<R>::type>
 __device__ __forceinline__ void solve_body(const DevProblem& p, const DevState& s, const DevControl& ctl, int wg,
                                            int nwg) {
@@ -1586,23 +1603,67 @@ __device__ __forceinline__ void solve_body(const DevProblem& p, const DevState& 
     const long long tcc0 = wall_clock64();
     t_phB += tcc0 - tb0;
     // Phase C: T(z).  Primal: xhat; trades and rows: dual prox.
-    for (int e = c.tid; e < P * c.nwa; e += TB) {
-      const int t = e / c.nwa, li = e % c.nwa;
-      const double b = V.bb(t, li), ab = fabs(b);
-      const double xh = ab > mu[t] ? sgn(b) * (ab - mu[t]) * V.aa(t, li) / V.dc(0, li) : 0.0;
-      V.xb(t, li) = 2.0 * xh - V.xs(t, li);
-      V.Txs.set(t, li, xh);
-    }
-    __syncthreads();
-    for (int e = c.tid; e < Tp * c.nwa; e += TB) {
-      const int t = e / c.nwa, li = e % c.nwa;
-      const double kc = kx_trade(V, V.xb, t, li);
-      const double vs = V.ysC(t, li) + sigma * kc;
-      const double drc = V.drC(t, li);
-      const double bc = trade_offset(V, t, li);
-      const double z = vs / (sigma * drc) - bc;
-      const double pr = prox_cost(z, 1.0 / (sigma * drc * drc), V.ca(t, li), V.cb(t, li), p.d);
-      V.TysC.set(t, li, vs - sigma * drc * bc - sigma * drc * pr);
+    // The plain kernel keeps one element per step: two per step reshuffled its registers and
+    // slowed the multi-period solve (state in device memory) by ~4%.
+    if constexpr (SL || LS) {
+      for (int e = c.tid; e < P * c.nwa; e += TB) {
+        const int t = e / c.nwa, li = e % c.nwa;
+        const double b = V.bb(t, li), ab = fabs(b);
+        const double xh = ab > mu[t] ? sgn(b) * (ab - mu[t]) * V.aa(t, li) / V.dc(0, li) : 0.0;
+        V.xb(t, li) = 2.0 * xh - V.xs(t, li);
+        V.Txs.set(t, li, xh);
+      }
+      __syncthreads();
+      for (int e = c.tid; e < Tp * c.nwa; e += TB) {
+        const int t = e / c.nwa, li = e % c.nwa;
+        const double kc = kx_trade(V, V.xb, t, li);
+        const double vs = V.ysC(t, li) + sigma * kc;
+        const double drc = V.drC(t, li);
+        const double bc = trade_offset(V, t, li);
+        const double z = vs / (sigma * drc) - bc;
+        const double pr = prox_cost(z, 1.0 / (sigma * drc * drc), V.ca(t, li), V.cb(t, li), p.d);
+        V.TysC.set(t, li, vs - sigma * drc * bc - sigma * drc * pr);
+      }
+    } else {   // the same arithmetic, two elements per step
+      struct InX { double b, ia, dci, x; int t, li; };
+      each2(c.tid, P * c.nwa,
+            [&](int e) {
+              InX r;
+              r.t = e / c.nwa;
+              r.li = e - r.t * c.nwa;
+              r.b = V.bb(r.t, r.li);
+              r.ia = V.aa(r.t, r.li);
+              r.dci = V.dc(0, r.li);
+              r.x = V.xs(r.t, r.li);
+              return r;
+            },
+            [&](const InX& r) {
+              const double ab = fabs(r.b);
+              const double xh = ab > mu[r.t] ? sgn(r.b) * (ab - mu[r.t]) * r.ia / r.dci : 0.0;
+              V.xb(r.t, r.li) = 2.0 * xh - r.x;
+              V.Txs.set(r.t, r.li, xh);
+            });
+      __syncthreads();
+      struct InC { double kc, ys, drc, bc, ca, cb; int t, li; };
+      each2(c.tid, Tp * c.nwa,
+            [&](int e) {
+              InC r;
+              r.t = e / c.nwa;
+              r.li = e - r.t * c.nwa;
+              r.kc = kx_trade(V, V.xb, r.t, r.li);
+              r.ys = V.ysC(r.t, r.li);
+              r.drc = V.drC(r.t, r.li);
+              r.bc = trade_offset(V, r.t, r.li);
+              r.ca = V.ca(r.t, r.li);
+              r.cb = V.cb(r.t, r.li);
+              return r;
+            },
+            [&](const InC& r) {
+              const double vs = r.ys + sigma * r.kc;
+              const double z = vs / (sigma * r.drc) - r.bc;
+              const double pr = prox_cost(z, 1.0 / (sigma * r.drc * r.drc), r.ca, r.cb, p.d);
+              V.TysC.set(r.t, r.li, vs - sigma * r.drc * r.bc - sigma * r.drc * pr);
+            });
     }
     for (int e = c.tid; e < P * nr; e += TB) {
       const int j = e % nr;
@@ -1857,13 +1918,39 @@ __device__ __forceinline__ void solve_body(const DevProblem& p, const DevState& 
     {
       const double kk = (double)sc->kk;
       const double a1 = (kk + 1.0) / (kk + 2.0), a0 = 1.0 / (kk + 2.0), rho = ctl.rho;
-      for (int e = c.tid; e < P * c.nwa; e += TB) {
-        const int t = e / c.nwa, li = e % c.nwa;
-        V.xs.set(t, li, a1 * ((1.0 + rho) * V.Txs(t, li) - rho * V.xs(t, li)) + a0 * V.x0s(t, li));
-      }
-      for (int e = c.tid; e < Tp * c.nwa; e += TB) {
-        const int t = e / c.nwa, li = e % c.nwa;
-        V.ysC.set(t, li, a1 * ((1.0 + rho) * V.TysC(t, li) - rho * V.ysC(t, li)) + a0 * V.ys0C(t, li));
+      if constexpr (SL || LS) {
+        for (int e = c.tid; e < P * c.nwa; e += TB) {
+          const int t = e / c.nwa, li = e % c.nwa;
+          V.xs.set(t, li, a1 * ((1.0 + rho) * V.Txs(t, li) - rho * V.xs(t, li)) + a0 * V.x0s(t, li));
+        }
+        for (int e = c.tid; e < Tp * c.nwa; e += TB) {
+          const int t = e / c.nwa, li = e % c.nwa;
+          V.ysC.set(t, li, a1 * ((1.0 + rho) * V.TysC(t, li) - rho * V.ysC(t, li)) + a0 * V.ys0C(t, li));
+        }
+      } else {   // the same arithmetic, two elements per step
+        struct InH { double tz, z, z0; int t, li; };
+        each2(c.tid, P * c.nwa,
+              [&](int e) {
+                InH r;
+                r.t = e / c.nwa;
+                r.li = e - r.t * c.nwa;
+                r.tz = V.Txs(r.t, r.li);
+                r.z = V.xs(r.t, r.li);
+                r.z0 = V.x0s(r.t, r.li);
+                return r;
+              },
+              [&](const InH& r) { V.xs.set(r.t, r.li, a1 * ((1.0 + rho) * r.tz - rho * r.z) + a0 * r.z0); });
+        each2(c.tid, Tp * c.nwa,
+              [&](int e) {
+                InH r;
+                r.t = e / c.nwa;
+                r.li = e - r.t * c.nwa;
+                r.tz = V.TysC(r.t, r.li);
+                r.z = V.ysC(r.t, r.li);
+                r.z0 = V.ys0C(r.t, r.li);
+                return r;
+              },
+              [&](const InH& r) { V.ysC.set(r.t, r.li, a1 * ((1.0 + rho) * r.tz - rho * r.z) + a0 * r.z0); });
       }
       for (int e = c.tid; e < P * nr; e += TB) ys[e] = a1 * ((1.0 + rho) * Tys[e] - rho * ys[e]) + a0 * ys0[e];
       __syncthreads();
