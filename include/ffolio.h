@@ -49,7 +49,8 @@ typedef enum {
   FFO_NOT_CONVERGED = 4,   /* max_iter reached; outputs hold the last iterate         */
   FFO_NUMERIC = 5,         /* NaN/Inf met in an FP64 check; outputs hold the last
                               finite restart point                                    */
-  FFO_INFEASIBLE = 6,      /* reserved: dual iterates diverge (infeasible bounds)     */
+  FFO_INFEASIBLE = 6,      /* the exposure bounds and the budget admit no portfolio:
+                              y_out's exposure part holds a certificate (see ffo_solve) */
   FFO_TIMEOUT = 7          /* time_limit_s reached; outputs hold the last iterate     */
 } ffo_status;
 
@@ -81,6 +82,19 @@ typedef struct {
   double reflection;       /* rho of the reflected Halpern step, in [0, 1] (1.0)      */
   int32_t workgroups;      /* workgroups of the persistent solve kernel, 0 = auto     */
   int32_t verbose;         /* 1: one summary line per solve to stderr; 2: also per-check progress (device printf) */
+  int32_t deterministic;   /* 1: partial sums exchanged through per-workgroup slots and
+                              added in a fixed order, so repeated solves are bitwise
+                              identical (slower); 0 (default): device-scope atomic adds,
+                              whose order varies from run to run                     */
+  int32_t speculative;     /* 1: one exchange per iteration (the multiplier's affine
+                              correction); 0: separate statistics and row exchanges;
+                              -1 (default): 1 for single-period, 0 for multi-period   */
+  int32_t breakpoint_lists;/* 1 (default): publish breakpoint lists with the statistics so
+                              that most multiplier brackets close without extra exchanges;
+                              0: multisection exchanges only (same solution)           */
+  int32_t infeasibility_check; /* 1 (default): at every check, test the exposure-dual
+                              displacement for an infeasibility certificate and stop with
+                              FFO_INFEASIBLE when one is found; 0: never               */
 } ffo_options;
 
 typedef struct {
@@ -130,6 +144,12 @@ void ffo_default_options(ffo_options* opt);
  *            eigendecomposition Omega = V diag(lambda) V^T).  NULL to skip
  *   info     host pointer, filled on every status except FFO_EINVAL
  * Returns FFO_OK when the relative KKT error reached opt->tol_rel_kkt.
+ * FFO_INFEASIBLE (with opt->infeasibility_check): every period has the same feasible set
+ * {w : L <= A w <= U, ||w||_1 <= 1}; the solve found y in R^m with
+ *   sum_j max(U_j y_j, L_j y_j) + max_i |(A^T y)_i| < 0,
+ * which proves that set empty (for feasible w, y^T A w is at most the first term and at
+ * least minus the second).  y_out's y_A part then holds the tested y for every period
+ * (at least one of them is such a certificate); w_out holds the last iterate.
  */
 ffo_status ffo_solve(int64_t n, int64_t k, int64_t m, int64_t T,
                      const double* alpha, const double* F, const double* Omega,
@@ -138,6 +158,27 @@ ffo_status ffo_solve(int64_t n, int64_t k, int64_t m, int64_t T,
                      double GMV, double lambda1, double lambda2, double lambda3,
                      const double* w_target, const ffo_options* opt, void* stream,
                      double* w_out, double* y_out, ffo_info* info);
+
+/*
+ * Warm-started solve: as ffo_solve, but the iteration starts from the caller's point
+ * instead of (w0 in every period, duals 0) (paper Section 4.1 starts every solve at w0;
+ * a warm start serves rolling re-solves, date to date, of nearby problems).
+ *   w_init     [P][n]  starting weights (device; NULL: w0 in every period)
+ *   y_init     [P*m + P*k + T'*n]  starting duals in ffo_solve's y_out layout (device;
+ *                      NULL: zero), e.g. the y_out of a previous solve with the same Omega
+ *   omega_init starting primal weight (e.g. the previous ffo_info.omega; 0: 1)
+ * The Halpern anchor is the starting point, so a start at a solution of the same problem
+ * stops at the first check.  Non-finite w_init / y_init values give FFO_EINVAL.
+ * Everything else (arguments, outputs, statuses) as in ffo_solve.
+ */
+ffo_status ffo_solve_warm(int64_t n, int64_t k, int64_t m, int64_t T,
+                          const double* alpha, const double* F, const double* Omega,
+                          const double* delta, const double* s, const double* q, double d,
+                          const double* A, const double* L, const double* U, const double* w0,
+                          double GMV, double lambda1, double lambda2, double lambda3,
+                          const double* w_target, const double* w_init, const double* y_init,
+                          double omega_init, const ffo_options* opt, void* stream,
+                          double* w_out, double* y_out, ffo_info* info);
 
 /*
  * Adjoint form: gradients of a loss l(W*) of the solution with respect to the expected

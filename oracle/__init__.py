@@ -34,6 +34,7 @@ polish   active-set identification, Newton on the reduced KKT system, and an exa
 brute    enumeration of active sets for tiny instances
 solve    the top-level driver: pdhg -> polish -> certificate
 grad     implicit differentiation of the polished solution
+feasibility  minimal budget of the exposure box (LP) and infeasibility certificates
 """
 from .problem import Problem, normalize  # noqa: F401
 from .solve import solve, OracleResult  # noqa: F401

@@ -7,6 +7,7 @@ if the library or a GPU is missing, the calls raise.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes
 import os
 from dataclasses import dataclass, asdict
@@ -34,7 +35,9 @@ class _Options(ctypes.Structure):
                 ("precision", ctypes.c_int32), ("restart_suff", ctypes.c_double),
                 ("restart_nec", ctypes.c_double), ("restart_art", ctypes.c_double),
                 ("reflection", ctypes.c_double), ("workgroups", ctypes.c_int32),
-                ("verbose", ctypes.c_int32)]
+                ("verbose", ctypes.c_int32), ("deterministic", ctypes.c_int32),
+                ("speculative", ctypes.c_int32), ("breakpoint_lists", ctypes.c_int32),
+                ("infeasibility_check", ctypes.c_int32)]
 
 
 class _Info(ctypes.Structure):
@@ -84,6 +87,10 @@ def lib() -> ctypes.CDLL:
                                 _D, _D, _D, _D, _P, ctypes.POINTER(_Options), _P, _P, _P,
                                 ctypes.POINTER(_Info)]
         L.ffo_solve.restype = ctypes.c_int
+        L.ffo_solve_warm.argtypes = [_I64, _I64, _I64, _I64, _P, _P, _P, _P, _P, _P, _D, _P, _P, _P, _P,
+                                     _D, _D, _D, _D, _P, _P, _P, _D, ctypes.POINTER(_Options), _P, _P, _P,
+                                     ctypes.POINTER(_Info)]
+        L.ffo_solve_warm.restype = ctypes.c_int
         L.ffo_solve_batched.argtypes = [_I64, _P, _I64, _I64, _I64, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P,
                                         _D, _D, _D, _D, _D, ctypes.POINTER(_Options), _P, _P, _P]
         L.ffo_solve_batched.restype = ctypes.c_int
@@ -98,7 +105,22 @@ def lib() -> ctypes.CDLL:
         L.ffo_version.argtypes = []
         L.ffo_version.restype = ctypes.c_char_p
         _lib = L
+        # release the library's cached workspaces (device memory, pinned host buffers,
+        # events) while the HIP runtime is still alive, not in its teardown
+        atexit.register(_release_at_exit)
     return _lib
+
+
+def _release_at_exit():
+    if _lib is None:
+        return
+    try:
+        torch = _torch()
+        if torch.cuda.is_available() and torch.cuda.is_initialized():
+            torch.cuda.synchronize()
+    except Exception:  # pragma: no cover - interpreter shutdown
+        pass
+    _lib.ffo_release()
 
 
 def default_options() -> _Options:
@@ -133,6 +155,8 @@ def solve(alpha, F, Omega, delta, s, q, d, A, L, U, w0, GMV, lambda1, lambda2, l
           w_target=None, *, tol: float = 1e-6, max_iter: int = 1_000_000, time_limit_s: float = 360.0,
           check_every: int = 64, restart=(0.2, 0.8, 0.36), reflection: float = 1.0,
           workgroups: int = 0, verbose: int = 0, return_dual: bool = False, precision="fp64",
+          deterministic: bool = False, speculative: int = -1, breakpoint_lists: bool = True,
+          infeasibility_check: bool = True, w_init=None, y_init=None, omega_init: float = 0.0,
           raise_on_failure: bool = True, device=None, stream=None, out=None):
     """Solve one single-period (w_target is None) or multi-period instance on the GPU.
 
@@ -140,8 +164,10 @@ def solve(alpha, F, Omega, delta, s, q, d, A, L, U, w0, GMV, lambda1, lambda2, l
     delta [n], s and q [T'][n] (T' = 1 or T), A [m][n], L and U [m], w0 and w_target [n].
     Returns (W [P][n] float64 CUDA tensor, Info) or (W, Info, (yA, yF, yC)) with
     ``return_dual``.  Non-OK statuses raise FolioError unless ``raise_on_failure`` is
-    False (NOT_CONVERGED/TIMEOUT/NUMERIC still fill W).  ``precision`` is "fp64" or
-    "fp32" (float32 iterates and matrix copies, float64 reductions and checks).
+    False (NOT_CONVERGED/TIMEOUT/NUMERIC/INFEASIBLE still fill W).  ``precision`` is
+    "fp64" or "fp32" (float32 iterates and matrix copies, float64 reductions and checks).
+    ``w_init`` [P][n], ``y_init`` (tuple yA, yF, yC or the packed vector) and
+    ``omega_init`` start the iteration from a previous solution (ffo_solve_warm).
     """
     torch = _torch()
     if not torch.cuda.is_available():
@@ -179,14 +205,29 @@ def solve(alpha, F, Omega, delta, s, q, d, A, L, U, w0, GMV, lambda1, lambda2, l
     o.workgroups = int(workgroups)
     o.verbose = int(verbose)
     o.precision = PRECISION[precision] if isinstance(precision, str) else int(precision)
+    o.deterministic = int(bool(deterministic))
+    o.speculative = int(speculative)
+    o.breakpoint_lists = int(bool(breakpoint_lists))
+    o.infeasibility_check = int(bool(infeasibility_check))
     info = _Info()
     st = torch.cuda.current_stream(dev) if stream is None else stream
+    args = (n, k, m, T, _ptr(a), _ptr(Fd if k else None), _ptr(Od if k else None), _ptr(dd),
+            _ptr(sd), _ptr(qd), float(d), _ptr(Ad if m else None), _ptr(Ld if m else None),
+            _ptr(Ud if m else None), _ptr(w0d), float(GMV), float(lambda1), float(lambda2),
+            float(lambda3), _ptr(wTd))
+    tail = (ctypes.byref(o), ctypes.c_void_p(st.cuda_stream), _ptr(W), _ptr(Y), ctypes.byref(info))
     with torch.cuda.device(dev):
-        rc = lib().ffo_solve(n, k, m, T, _ptr(a), _ptr(Fd if k else None), _ptr(Od if k else None), _ptr(dd),
-                             _ptr(sd), _ptr(qd), float(d), _ptr(Ad if m else None), _ptr(Ld if m else None),
-                             _ptr(Ud if m else None), _ptr(w0d), float(GMV), float(lambda1), float(lambda2),
-                             float(lambda3), _ptr(wTd), ctypes.byref(o), ctypes.c_void_p(st.cuda_stream),
-                             _ptr(W), _ptr(Y), ctypes.byref(info))
+        if w_init is None and y_init is None and not omega_init:
+            rc = lib().ffo_solve(*args, *tail)
+        else:
+            wi = _dev_f64(w_init, dev).reshape(P, n) if w_init is not None else None
+            if isinstance(y_init, (tuple, list)):
+                yi = torch.cat([_dev_f64(y, dev).reshape(-1) for y in y_init])
+            else:
+                yi = _dev_f64(y_init, dev).reshape(-1) if y_init is not None else None
+            if yi is not None and yi.numel() != P * m + P * k + Tp * n:
+                raise ValueError("y_init must hold P*m + P*k + T'*n values")
+            rc = lib().ffo_solve_warm(*args, _ptr(wi), _ptr(yi), float(omega_init), *tail)
     inf = Info(**{f[0]: getattr(info, f[0]) for f in _Info._fields_})
     if rc == 1 or (rc in (2, 3)) or (rc != 0 and raise_on_failure):
         raise FolioError(rc, lib().ffo_last_error().decode())

@@ -74,8 +74,9 @@ ffo_status get_workspace(int dev, void* stream, size_t bytes, size_t host_bytes,
 
 // C with C C^T = Om (k x k, row-major).  Cholesky first; if a pivot is not positive,
 // cyclic Jacobi eigendecomposition and C = V diag(sqrt(max(lambda, 0))).  Returns false
-// if Om is not symmetric or has an eigenvalue below -1e-10 * max|lambda|.
-bool factor_omega(int k, const double* Om, double* C) {
+// if Om is not symmetric or has an eigenvalue below -1e-10 * max|lambda|.  work: host
+// scratch of 2 k^2 doubles.
+bool factor_omega(int k, const double* Om, double* C, double* work) {
   double amax = 0.0;
   for (int i = 0; i < k * k; ++i) {
     if (!std::isfinite(Om[i])) return false;
@@ -84,7 +85,8 @@ bool factor_omega(int k, const double* Om, double* C) {
   for (int i = 0; i < k; ++i)
     for (int j = 0; j < i; ++j)
       if (std::fabs(Om[i * k + j] - Om[j * k + i]) > 1e-12 * std::max(1.0, amax)) return false;
-  std::vector<double> Lc(k * k, 0.0);
+  double* Lc = work;   // [k*k]
+  std::fill(Lc, Lc + (size_t)k * k, 0.0);
   bool ok = true;
   for (int j = 0; j < k && ok; ++j) {
     double d = Om[j * k + j];
@@ -99,11 +101,14 @@ bool factor_omega(int k, const double* Om, double* C) {
     }
   }
   if (ok) {
-    std::copy(Lc.begin(), Lc.end(), C);
+    std::copy(Lc, Lc + (size_t)k * k, C);
     return true;
   }
   // Jacobi eigendecomposition
-  std::vector<double> a(Om, Om + k * k), v(k * k, 0.0);
+  double* a = work;                   // [k*k]
+  double* v = work + (size_t)k * k;   // [k*k]
+  std::copy(Om, Om + (size_t)k * k, a);
+  std::fill(v, v + (size_t)k * k, 0.0);
   for (int i = 0; i < k; ++i) v[i * k + i] = 1.0;
   for (int sweep = 0; sweep < 100; ++sweep) {
     double off = 0.0;
@@ -206,6 +211,7 @@ ffo_status check_problem_args(int64_t n, int64_t k, int64_t m, int64_t T, const 
   if (!(lambda1 > 0.0) || !std::isfinite(lambda1)) return fail(FFO_EINVAL, "lambda1 must be positive and finite");
   if (!(lambda2 >= 0.0) || !(lambda3 >= 0.0) || !std::isfinite(lambda2) || !std::isfinite(lambda3))
     return fail(FFO_EINVAL, "lambda2 and lambda3 must be nonnegative and finite");
+  if (!std::isfinite(lambda1 * GMV)) return fail(FFO_EINVAL, "lambda1 * GMV must be finite");
   return FFO_OK;
 }
 
@@ -216,6 +222,11 @@ ffo_status check_options(const ffo_options& opt) {
   if (!(opt.time_limit_s > 0.0)) return fail(FFO_EINVAL, "time_limit_s must be positive");
   if (!(opt.reflection >= 0.0 && opt.reflection <= 1.0)) return fail(FFO_EINVAL, "reflection must lie in [0, 1]");
   if (opt.workgroups < 0 || opt.workgroups > 4096) return fail(FFO_EINVAL, "workgroups must lie in [0, 4096]");
+  if (opt.deterministic != 0 && opt.deterministic != 1) return fail(FFO_EINVAL, "deterministic must be 0 or 1");
+  if (opt.speculative < -1 || opt.speculative > 1) return fail(FFO_EINVAL, "speculative must be -1, 0 or 1");
+  if (opt.breakpoint_lists != 0 && opt.breakpoint_lists != 1) return fail(FFO_EINVAL, "breakpoint_lists must be 0 or 1");
+  if (opt.infeasibility_check != 0 && opt.infeasibility_check != 1)
+    return fail(FFO_EINVAL, "infeasibility_check must be 0 or 1");
   return FFO_OK;
 }
 
@@ -227,6 +238,7 @@ std::string bad_values(int flag) {
   if (flag & 8) why += " w0/w_target not finite;";
   if (flag & 16) why += " s and q must be nonnegative and finite;";
   if (flag & 32) why += " need L <= U (no NaN, L < +inf, U > -inf);";
+  if (flag & 64) why += " warm-start data not finite;";
   return "invalid input values:" + why;
 }
 
@@ -252,49 +264,54 @@ ffo_status status_of(int32_t hstat) {
     case ffo::DS_NOT_CONVERGED: return FFO_NOT_CONVERGED;
     case ffo::DS_NUMERIC: return FFO_NUMERIC;
     case ffo::DS_TIMEOUT: return FFO_TIMEOUT;
+    case ffo::DS_INFEASIBLE: return FFO_INFEASIBLE;
     default: return FFO_EDEVICE;
   }
 }
 
-}  // namespace
-
-extern "C" {
-
-void ffo_default_options(ffo_options* o) {
-  if (!o) return;
-  o->tol_rel_kkt = 1e-6;
-  o->max_iter = 1000000;
-  o->time_limit_s = 360.0;
-  o->check_every = 64;
-  o->precision = FFO_FP64;
-  o->restart_suff = 0.2;
-  o->restart_nec = 0.8;
-  o->restart_art = 0.36;
-  o->reflection = 1.0;
-  o->workgroups = 0;
-  o->verbose = 0;
+// Fill `words` 32-bit words with `value` (used instead of hipMemsetAsync so that a caller
+// may record the solve's stream work into a graph).
+__global__ void k_fill(uint32_t* p, int64_t words, uint32_t value) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < words; e += stride) p[e] = value;
 }
 
-const char* ffo_last_error(void) { return g_err.c_str(); }
-
-const char* ffo_version(void) { return "ffolio 0.1 (gfx950)"; }
-
-void ffo_release(void) {
-  std::lock_guard<std::mutex> lk(g_mu);
-  for (auto& kv : g_ws) {
-    if (kv.second.base) hipFree(kv.second.base);
-    if (kv.second.host) hipHostFree(kv.second.host);
-    for (auto& e : kv.second.ev)
-      if (e) hipEventDestroy(e);
-  }
-  g_ws.clear();
+hipError_t fill(void* p, size_t bytes, uint32_t value, hipStream_t hs) {
+  const int64_t words = (int64_t)(bytes / 4);
+  if (words == 0) return hipSuccess;
+  const int blocks = (int)std::min<int64_t>(1024, (words + 255) / 256);
+  hipLaunchKernelGGL(k_fill, dim3(blocks), dim3(256), 0, hs, (uint32_t*)p, words, value);
+  return hipGetLastError();
 }
 
-ffo_status ffo_solve(int64_t n, int64_t k, int64_t m, int64_t T, const double* alpha, const double* F,
-                     const double* Omega, const double* delta, const double* s, const double* q, double d,
-                     const double* A, const double* L, const double* U, const double* w0, double GMV,
-                     double lambda1, double lambda2, double lambda3, const double* w_target,
-                     const ffo_options* opt_in, void* stream, double* w_out, double* y_out, ffo_info* info) {
+// Finite-value check of an optional caller array (warm-start data); sets `bit` in flag.
+__global__ void k_check_finite(const double* x, int64_t cnt, int bit, int* flag) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  int bad = 0;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < cnt; e += stride)
+    if (!isfinite(x[e])) bad = bit;
+  if (bad) atomicOr(flag, bad);
+}
+
+// Device and host memory for one ffo_solve call that the caller (not the workspace
+// cache) provides; events may be null (no timing).
+struct Fixed {
+  char* dev;
+  size_t dev_bytes;
+  char* host;
+  size_t host_bytes;
+  hipEvent_t* ev;   // [3] or null
+};
+
+// The single-instance solve behind ffo_solve and ffo_solve_warm.  w_init / y_init
+// (device, optional): starting weights [P][n] and duals (y_out layout); omega0 > 0: the
+// starting primal weight.  fx: caller-provided memory, or null for the workspace cache.
+ffo_status solve_impl(int64_t n, int64_t k, int64_t m, int64_t T, const double* alpha, const double* F,
+                      const double* Omega, const double* delta, const double* s, const double* q, double d,
+                      const double* A, const double* L, const double* U, const double* w0, double GMV,
+                      double lambda1, double lambda2, double lambda3, const double* w_target,
+                      const double* w_init, const double* y_init, double omega0, const ffo_options* opt_in,
+                      void* stream, double* w_out, double* y_out, ffo_info* info, const Fixed* fx) {
   g_err.clear();
   ffo_options opt;
   ffo_default_options(&opt);
@@ -333,15 +350,15 @@ ffo_status ffo_solve(int64_t n, int64_t k, int64_t m, int64_t T, const double* a
   c.tol = opt.tol_rel_kkt; c.time_limit_s = opt.time_limit_s;
   c.r_suff = opt.restart_suff; c.r_nec = opt.restart_nec; c.r_art = opt.restart_art;
   c.rho = opt.reflection; c.eta_safety = 0.95; c.max_iter = opt.max_iter;
-  c.check_every = opt.check_every; c.xmode = ffo::XM_ATOMIC; c.nwg = nwg; c.npow = 40;
+  c.check_every = opt.check_every; c.nwg = nwg; c.npow = 40;
   c.verbose = opt.verbose; c.nw = nw; c.spin_limit = 1u << 26; c.wall_hz = (double)wall_khz * 1e3;
   c.prec = opt.precision == FFO_FP32 ? ffo::PREC_FP32 : ffo::PREC_FP64;
-  if (const char* e = std::getenv("FFO_XMODE")) c.xmode = std::atoi(e) ? ffo::XM_GATHER : ffo::XM_ATOMIC;
+  c.xmode = opt.deterministic ? ffo::XM_GATHER : ffo::XM_ATOMIC;
   c.vmax = ffo::solve_vmax(p);
-  c.spec = P == 1 ? 1 : 0;
-  if (const char* e = std::getenv("FFO_SPEC")) c.spec = std::atoi(e) ? 1 : 0;
-  c.lists = 1;
-  if (const char* e = std::getenv("FFO_LISTS")) c.lists = std::atoi(e) ? 1 : 0;
+  c.spec = opt.speculative < 0 ? (P == 1 ? 1 : 0) : (opt.speculative ? 1 : 0);
+  c.lists = opt.breakpoint_lists ? 1 : 0;
+  c.infeas = opt.infeasibility_check ? 1 : 0;
+  c.omega0 = omega0;
   // LDS placement: constraint slice and per-asset state in LDS when they fit, the slice
   // first (it is read twice per iteration, by K~^T y and K~ xbar; T=10, n=2000: 69 -> 50 us
   // per iteration against state first).  With the automatic workgroup count, more
@@ -389,37 +406,56 @@ ffo_status ffo_solve(int64_t n, int64_t k, int64_t m, int64_t T, const double* a
   const size_t oblist = carve(c.lists ? (size_t)2 * nwg * P * ffo::LIST_W : 1, 8);
   const size_t oinfo = carve(ffo::INFO_LEN, 8), ostat = carve(1, 4), oflag = carve(1, 4);
   const size_t total = off;
-  const size_t host_bytes = align_up((size_t)std::max<int64_t>(k * k, 1) * 8) * 2 + 4096;
+  // host staging: Omega, its factor, the factorisation's work space, info, two flags
+  const size_t kk = (size_t)std::max<int64_t>(k * k, 1);
+  size_t hoff = 0;
+  auto hcarve = [&](size_t bytes) { const size_t o = hoff; hoff = align_up(hoff + bytes); return o; };
+  const size_t hOm_o = hcarve(kk * 8), hC_o = hcarve(kk * 8), hW_o = hcarve(2 * kk * 8);
+  const size_t hI_o = hcarve(ffo::INFO_LEN * 8), hF_o = hcarve(8);
+  const size_t host_bytes = hoff;
 
-  Workspace* ws = nullptr;
-  if (ffo_status st = get_workspace(dev, stream, total, host_bytes, &ws)) return st;
-  char* B = (char*)ws->base;
+  char* B = nullptr;
+  char* H = nullptr;
+  hipEvent_t* ev = nullptr;
+  if (fx) {
+    if (total > fx->dev_bytes)
+      return fail(FFO_EINVAL, "problem needs " + std::to_string(total) + " bytes of device scratch, more than the " +
+                                  std::to_string(fx->dev_bytes) + " available");
+    if (host_bytes > fx->host_bytes) return fail(FFO_EINVAL, "k too large for the host staging area");
+    B = fx->dev;
+    H = fx->host;
+    ev = fx->ev;
+  } else {
+    Workspace* ws = nullptr;
+    if (ffo_status st = get_workspace(dev, stream, total, host_bytes, &ws)) return st;
+    B = (char*)ws->base;
+    H = (char*)ws->host;
+    ev = ws->ev;
+  }
   auto D = [&](size_t o) { return (double*)(B + o); };
   hipStream_t hs = (hipStream_t)stream;
-  double* hOm = (double*)ws->host;
-  double* hC = hOm + align_up((size_t)std::max<int64_t>(k * k, 1) * 8) / 8;
-  int* hflag = (int*)(hC + align_up((size_t)std::max<int64_t>(k * k, 1) * 8) / 8);
+  double* hOm = (double*)(H + hOm_o);
+  double* hC = (double*)(H + hC_o);
+  double* hW = (double*)(H + hW_o);
+  double* hinfo = (double*)(H + hI_o);
+  int* hflag = (int*)(H + hF_o);
 
-  HIPCHK(hipEventRecord(ws->ev[0], hs));
+  if (ev) HIPCHK(hipEventRecord(ev[0], hs));
   // ---- value validation on the device + Omega to the host (one synchronisation) ----
-  HIPCHK(hipMemsetAsync(B + oflag, 0, 4, hs));
+  HIPCHK(fill(B + oflag, 4, 0u, hs));
   hipLaunchKernelGGL(k_validate, dim3(64), dim3(256), 0, hs, n, (int64_t)Pn, (int64_t)Tpn, n * k, m, alpha, F,
                      delta, s, q, L, U, w0, w_target, (int*)(B + oflag));
+  if (w_init)
+    hipLaunchKernelGGL(k_check_finite, dim3(64), dim3(256), 0, hs, w_init, (int64_t)Pn, 64, (int*)(B + oflag));
+  if (y_init)
+    hipLaunchKernelGGL(k_check_finite, dim3(64), dim3(256), 0, hs, y_init, (int64_t)(P * m + P * k) + (int64_t)Tpn,
+                       64, (int*)(B + oflag));
   HIPCHK(hipGetLastError());
   if (k > 0) HIPCHK(hipMemcpyAsync(hOm, Omega, (size_t)k * k * 8, hipMemcpyDeviceToHost, hs));
   HIPCHK(hipMemcpyAsync(hflag, B + oflag, 4, hipMemcpyDeviceToHost, hs));
   HIPCHK(hipStreamSynchronize(hs));
-  if (*hflag) {
-    std::string why;
-    if (*hflag & 1) why += " alpha not finite;";
-    if (*hflag & 2) why += " F not finite;";
-    if (*hflag & 4) why += " delta must be positive and finite;";
-    if (*hflag & 8) why += " w0/w_target not finite;";
-    if (*hflag & 16) why += " s and q must be nonnegative and finite;";
-    if (*hflag & 32) why += " need L <= U (no NaN, L < +inf, U > -inf);";
-    return fail(FFO_EINVAL, "invalid input values:" + why);
-  }
-  if (k > 0 && !factor_omega((int)k, hOm, hC)) return fail(FFO_EINVAL, "Omega must be symmetric positive semidefinite");
+  if (*hflag) return fail(FFO_EINVAL, bad_values(*hflag));
+  if (k > 0 && !factor_omega((int)k, hOm, hC, hW)) return fail(FFO_EINVAL, "Omega must be symmetric positive semidefinite");
   if (k > 0) HIPCHK(hipMemcpyAsync(D(oC), hC, (size_t)k * k * 8, hipMemcpyHostToDevice, hs));
 
   // ---- setup kernels ----
@@ -444,48 +480,37 @@ ffo_status ffo_solve(int64_t n, int64_t k, int64_t m, int64_t T, const double* a
   sv.xbuf = D(oxb); sv.bar = (unsigned long long*)(B + obar);
   sv.blist = c.lists ? D(oblist) : nullptr;
   sv.info = D(oinfo); sv.status = (int32_t*)(B + ostat); sv.w_out = w_out; sv.y_out = y_out;
-  HIPCHK(hipMemsetAsync(B + oxb, 0, nxbuf * 8, hs));
-  HIPCHK(hipMemsetAsync(B + obar, 0, 8, hs));
-  HIPCHK(hipMemsetAsync(B + oinfo, 0, ffo::INFO_LEN * 8, hs));
-  HIPCHK(hipMemsetAsync(B + ostat, 0xff, 4, hs));
-  HIPCHK(hipEventRecord(ws->ev[1], hs));
+  sv.w_init = w_init; sv.y_init = y_init;
+  HIPCHK(fill(B + oxb, nxbuf * 8, 0u, hs));
+  HIPCHK(fill(B + obar, 8, 0u, hs));
+  HIPCHK(fill(B + oinfo, ffo::INFO_LEN * 8, 0u, hs));
+  HIPCHK(fill(B + ostat, 4, 0xffffffffu, hs));
+  if (ev) HIPCHK(hipEventRecord(ev[1], hs));
   if (int e = ffo::launch_solve(p, sv, c, stream, lds))
     return fail(FFO_EDEVICE, std::string("cooperative launch of the solve kernel failed: ") +
                                  hipGetErrorString((hipError_t)e));
-  HIPCHK(hipEventRecord(ws->ev[2], hs));
-  double hinfo[ffo::INFO_LEN];
-  int32_t hstat = -1;
-  HIPCHK(hipMemcpyAsync(hOm, B + oinfo, ffo::INFO_LEN * 8, hipMemcpyDeviceToHost, hs));
+  if (ev) HIPCHK(hipEventRecord(ev[2], hs));
+  HIPCHK(hipMemcpyAsync(hinfo, B + oinfo, ffo::INFO_LEN * 8, hipMemcpyDeviceToHost, hs));
   HIPCHK(hipMemcpyAsync(hflag, B + ostat, 4, hipMemcpyDeviceToHost, hs));
   HIPCHK(hipStreamSynchronize(hs));
-  std::memcpy(hinfo, hOm, sizeof(hinfo));
-  hstat = *hflag;
+  const int32_t hstat = *hflag;
   float ms_setup = 0.f, ms_iter = 0.f;
-  hipEventElapsedTime(&ms_setup, ws->ev[0], ws->ev[1]);
-  hipEventElapsedTime(&ms_iter, ws->ev[1], ws->ev[2]);
-  ffo_status st;
-  switch (hstat) {
-    case ffo::DS_OK: st = FFO_OK; break;
-    case ffo::DS_NOT_CONVERGED: st = FFO_NOT_CONVERGED; g_err = "iteration limit reached"; break;
-    case ffo::DS_NUMERIC: st = FFO_NUMERIC; g_err = "NaN or Inf in an FP64 check"; break;
-    case ffo::DS_TIMEOUT: st = FFO_TIMEOUT; g_err = "time limit reached"; break;
-    default: st = FFO_EDEVICE; g_err = "solve kernel ended without a result (bounded wait expired)"; break;
+  if (ev) {
+    hipEventElapsedTime(&ms_setup, ev[0], ev[1]);
+    hipEventElapsedTime(&ms_iter, ev[1], ev[2]);
   }
-  if (info) {
-    info->status = st;
-    info->iters = (int64_t)hinfo[ffo::IX_ITERS];
-    info->restarts = (int64_t)hinfo[ffo::IX_RESTARTS];
-    info->rel_kkt = hinfo[ffo::IX_RELKKT];
-    info->rel_pri = hinfo[ffo::IX_RELPRI];
-    info->rel_dual = hinfo[ffo::IX_RELDUAL];
-    info->rel_gap = hinfo[ffo::IX_RELGAP];
-    info->fixed_point_res = hinfo[ffo::IX_FPR];
-    info->primal_obj = hinfo[ffo::IX_POBJ];
-    info->dual_obj = hinfo[ffo::IX_DOBJ];
-    info->omega = hinfo[ffo::IX_OMEGA];
-    info->ms_setup = ms_setup;
-    info->ms_iter = ms_iter;
+  const ffo_status st = status_of(hstat);
+  switch (st) {
+    case FFO_OK: break;
+    case FFO_NOT_CONVERGED: g_err = "iteration limit reached"; break;
+    case FFO_NUMERIC: g_err = "NaN or Inf in an FP64 check"; break;
+    case FFO_TIMEOUT: g_err = "time limit reached"; break;
+    case FFO_INFEASIBLE:
+      g_err = "infeasible: no portfolio meets the exposure bounds within the budget (certificate in y_out)";
+      break;
+    default: g_err = "solve kernel ended without a result (bounded wait expired)"; break;
   }
+  if (info) fill_info(info, st, hinfo, ms_setup, ms_iter);
   if (opt.verbose)
     std::fprintf(stderr,
                  "[ffo] status %d iters %.0f restarts %.0f spec_miss %.0f ms_rounds %.0f exchanges %.0f checks %.0f "
@@ -501,6 +526,66 @@ ffo_status ffo_solve(int64_t n, int64_t k, int64_t m, int64_t T, const double* a
                  hinfo[ffo::IX_T_B1S] * 1e3, hinfo[ffo::IX_T_B2] * 1e3, hinfo[ffo::IX_T_B3] * 1e3,
                  hinfo[ffo::IX_MISS_IN], hinfo[ffo::IX_MISS_OUT]);
   return st;
+}
+
+}  // namespace
+
+extern "C" {
+
+void ffo_default_options(ffo_options* o) {
+  if (!o) return;
+  o->tol_rel_kkt = 1e-6;
+  o->max_iter = 1000000;
+  o->time_limit_s = 360.0;
+  o->check_every = 64;
+  o->precision = FFO_FP64;
+  o->restart_suff = 0.2;
+  o->restart_nec = 0.8;
+  o->restart_art = 0.36;
+  o->reflection = 1.0;
+  o->workgroups = 0;
+  o->verbose = 0;
+  o->deterministic = 0;
+  o->speculative = -1;
+  o->breakpoint_lists = 1;
+  o->infeasibility_check = 1;
+}
+
+const char* ffo_last_error(void) { return g_err.c_str(); }
+
+const char* ffo_version(void) { return "ffolio 0.1 (gfx950)"; }
+
+void ffo_release(void) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  for (auto& kv : g_ws) {
+    if (kv.second.base) hipFree(kv.second.base);
+    if (kv.second.host) hipHostFree(kv.second.host);
+    for (auto& e : kv.second.ev)
+      if (e) hipEventDestroy(e);
+  }
+  g_ws.clear();
+}
+
+ffo_status ffo_solve(int64_t n, int64_t k, int64_t m, int64_t T, const double* alpha, const double* F,
+                     const double* Omega, const double* delta, const double* s, const double* q, double d,
+                     const double* A, const double* L, const double* U, const double* w0, double GMV,
+                     double lambda1, double lambda2, double lambda3, const double* w_target,
+                     const ffo_options* opt_in, void* stream, double* w_out, double* y_out, ffo_info* info) {
+  return solve_impl(n, k, m, T, alpha, F, Omega, delta, s, q, d, A, L, U, w0, GMV, lambda1, lambda2, lambda3,
+                    w_target, nullptr, nullptr, 0.0, opt_in, stream, w_out, y_out, info, nullptr);
+}
+
+ffo_status ffo_solve_warm(int64_t n, int64_t k, int64_t m, int64_t T, const double* alpha, const double* F,
+                          const double* Omega, const double* delta, const double* s, const double* q, double d,
+                          const double* A, const double* L, const double* U, const double* w0, double GMV,
+                          double lambda1, double lambda2, double lambda3, const double* w_target,
+                          const double* w_init, const double* y_init, double omega_init, const ffo_options* opt_in,
+                          void* stream, double* w_out, double* y_out, ffo_info* info) {
+  g_err.clear();
+  if (!(omega_init >= 0.0) || !std::isfinite(omega_init))
+    return fail(FFO_EINVAL, "omega_init must be finite and >= 0 (0: the default start)");
+  return solve_impl(n, k, m, T, alpha, F, Omega, delta, s, q, d, A, L, U, w0, GMV, lambda1, lambda2, lambda3,
+                    w_target, w_init, y_init, omega_init, opt_in, stream, w_out, y_out, info, nullptr);
 }
 
 ffo_status ffo_adjoint(int64_t n, int64_t k, int64_t m, int64_t T, const double* alpha, const double* F,
@@ -596,7 +681,9 @@ ffo_status ffo_adjoint(int64_t n, int64_t k, int64_t m, int64_t T, const double*
   HIPCHK(hipMemcpyAsync(hflag, B + oflag, 4, hipMemcpyDeviceToHost, hs));
   HIPCHK(hipStreamSynchronize(hs));
   if (*hflag) return fail(FFO_EINVAL, bad_values(*hflag));
-  if (k > 0 && !factor_omega((int)k, hOm, hC)) return fail(FFO_EINVAL, "Omega must be symmetric positive semidefinite");
+  std::vector<double> fwork((size_t)2 * std::max<int64_t>(k * k, 1));
+  if (k > 0 && !factor_omega((int)k, hOm, hC, fwork.data()))
+    return fail(FFO_EINVAL, "Omega must be symmetric positive semidefinite");
   if (k > 0) HIPCHK(hipMemcpyAsync(D(oC), hC, (size_t)k * k * 8, hipMemcpyHostToDevice, hs));
   const double g1 = lambda1 * GMV, g2 = lambda2, g3 = lambda3;
   if (ffo::launch_setup(n, k, m, P, Tp, ldk, F, D(oC), A, delta, s, q, w_target, g1, g2, g3, D(oK), D(odr),
@@ -694,6 +781,7 @@ ffo_status ffo_solve_batched(int64_t B, const int64_t* n_b, int64_t n_max, int64
   if (!(lambda1 > 0.0) || !std::isfinite(lambda1)) return fail(FFO_EINVAL, "lambda1 must be positive and finite");
   if (!(lambda2 >= 0.0) || !(lambda3 >= 0.0) || !std::isfinite(lambda2) || !std::isfinite(lambda3))
     return fail(FFO_EINVAL, "lambda2 and lambda3 must be nonnegative and finite");
+  if (!std::isfinite(lambda1 * GMV)) return fail(FFO_EINVAL, "lambda1 * GMV must be finite");
   if (!(opt.tol_rel_kkt > 0.0)) return fail(FFO_EINVAL, "tol_rel_kkt must be positive");
   if (opt.max_iter < 1) return fail(FFO_EINVAL, "max_iter must be >= 1");
   if (opt.check_every < 1) return fail(FFO_EINVAL, "check_every must be >= 1");
@@ -723,7 +811,7 @@ ffo_status ffo_solve_batched(int64_t B, const int64_t* n_b, int64_t n_max, int64
   c0.r_suff = opt.restart_suff; c0.r_nec = opt.restart_nec; c0.r_art = opt.restart_art;
   c0.rho = opt.reflection; c0.eta_safety = 0.95; c0.max_iter = opt.max_iter; c0.check_every = opt.check_every;
   c0.npow = 40; c0.verbose = opt.verbose; c0.spin_limit = 1u << 26; c0.wall_hz = (double)wall_khz * 1e3;
-  c0.prec = prec; c0.spec = 1; c0.lds_k = 0; c0.lds_state = 0;
+  c0.prec = prec; c0.spec = 1; c0.lds_k = 0; c0.lds_state = 0; c0.infeas = opt.infeasibility_check ? 1 : 0;
   c0.vmax = ffo::solve_vmax(p0);
   const int NW_MAX = 2048;   // assets per workgroup at most (bounds the LDS staging)
   const int NW_MIN = 256;    // extra workgroups only while a team keeps at least this many assets each
@@ -832,7 +920,9 @@ ffo_status ffo_solve_batched(int64_t B, const int64_t* n_b, int64_t n_max, int64
   HIPCHK(hipMemcpyAsync(hflag, Bd + oflag, 4, hipMemcpyDeviceToHost, hs));
   HIPCHK(hipStreamSynchronize(hs));
   if (*hflag) return fail(FFO_EINVAL, bad_values(*hflag));
-  if (k > 0 && !factor_omega((int)k, hOm, hC)) return fail(FFO_EINVAL, "Omega must be symmetric positive semidefinite");
+  std::vector<double> fwork((size_t)2 * std::max<int64_t>(k * k, 1));
+  if (k > 0 && !factor_omega((int)k, hOm, hC, fwork.data()))
+    return fail(FFO_EINVAL, "Omega must be symmetric positive semidefinite");
   if (k > 0) HIPCHK(hipMemcpyAsync(D(oC), hC, (size_t)k * k * 8, hipMemcpyHostToDevice, hs));
 
   // ---- setup: shared rows and per-instance scales ----
@@ -915,7 +1005,8 @@ ffo_status ffo_solve_batched(int64_t B, const int64_t* n_b, int64_t n_max, int64
   hipEventElapsedTime(&ms_iter, ws->ev[1], ws->ev[2]);
   ffo_status worst = FFO_OK;
   auto rank = [](ffo_status x) {
-    return x == FFO_EDEVICE ? 4 : x == FFO_NUMERIC ? 3 : x == FFO_TIMEOUT ? 2 : x == FFO_NOT_CONVERGED ? 1 : 0;
+    return x == FFO_EDEVICE ? 5 : x == FFO_NUMERIC ? 4 : x == FFO_INFEASIBLE ? 3 : x == FFO_TIMEOUT ? 2
+           : x == FFO_NOT_CONVERGED ? 1 : 0;
   };
   for (int64_t b = 0; b < B; ++b) {
     const ffo_status st = status_of(hstat[b]);
@@ -947,6 +1038,7 @@ ffo_status ffo_solve_batched(int64_t B, const int64_t* n_b, int64_t n_max, int64
   if (worst == FFO_NOT_CONVERGED) g_err = "iteration limit reached for at least one instance";
   else if (worst == FFO_TIMEOUT) g_err = "time limit reached for at least one instance";
   else if (worst == FFO_NUMERIC) g_err = "NaN or Inf in an FP64 check of at least one instance";
+  else if (worst == FFO_INFEASIBLE) g_err = "at least one instance is infeasible";
   else if (worst == FFO_EDEVICE) g_err = "a team ended without a result (bounded wait expired)";
   return worst;
 }

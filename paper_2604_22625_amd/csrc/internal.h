@@ -12,7 +12,7 @@ enum XMode : int32_t { XM_ATOMIC = 0, XM_GATHER = 1, XM_LOCAL = 2 };
 
 // Status codes written by the device (mirror ffo_status).
 enum DevStatus : int32_t {
-  DS_RUNNING = -1, DS_OK = 0, DS_NOT_CONVERGED = 4, DS_NUMERIC = 5, DS_TIMEOUT = 7,
+  DS_RUNNING = -1, DS_OK = 0, DS_NOT_CONVERGED = 4, DS_NUMERIC = 5, DS_INFEASIBLE = 6, DS_TIMEOUT = 7,
   DS_BARRIER = 100  // a bounded wait expired (device consistency failure)
 };
 
@@ -58,6 +58,8 @@ struct DevState {
   int32_t* status;                    // [1]
   double* w_out;                      // [P][n] unscaled solution
   double* y_out;                      // optional dual output
+  const double* w_init;               // optional [P][n] unscaled starting weights (else w0)
+  const double* y_init;               // optional unscaled starting duals, y_out layout (else 0)
 };
 
 struct DevControl {
@@ -72,6 +74,8 @@ struct DevControl {
   uint32_t spin_limit;
   double wall_hz;       // rate of the device wall clock
   int32_t lists;        // 1: publish breakpoint lists with the statistics (blist non-null)
+  int32_t infeas;       // 1: test the exposure-dual displacement for an infeasibility certificate
+  double omega0;        // starting primal weight (> 0)
 };
 
 // Breakpoint lists: per workgroup and period, a count and LIST_CAP entries

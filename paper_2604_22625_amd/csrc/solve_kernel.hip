@@ -1290,9 +1290,18 @@ __device__ __forceinline__ void solve_body(const DevProblem& p, const DevState& 
       V.w0(0, li) = p.w0[i]; V.wT(0, li) = p.wT ? p.wT[i] : 0.0;
     }
   }
-  for (int e = c.tid; e < P * nr; e += TB) { ys[e] = 0.0; ys0[e] = 0.0; Tys[e] = 0.0; Kx[e] = 0.0; }
+  // starting duals: zero, or the caller's (unscaled, y_out layout) divided by the row scales
+  for (int e = c.tid; e < P * nr; e += TB) {
+    double y = 0.0;
+    if (s.y_init) {
+      const int t = e / nr, j = e % nr;
+      const double yu = j < p.m ? s.y_init[(size_t)t * p.m + j] : s.y_init[(size_t)P * p.m + (size_t)t * p.k + (j - p.m)];
+      y = yu / p.dr[j];
+    }
+    ys[e] = y; ys0[e] = y; Tys[e] = y; Kx[e] = 0.0;
+  }
   if (c.tid == 0) {
-    sc->omega = 1.0; sc->it = 0; sc->kk = 0; sc->restarts = 0; sc->spec_miss = 0; sc->checks = 0;
+    sc->omega = ctl.omega0 > 0.0 ? ctl.omega0 : 1.0; sc->it = 0; sc->kk = 0; sc->restarts = 0; sc->spec_miss = 0; sc->checks = 0;
     sc->miss_in = 0; sc->miss_out = 0;
     sc->r0 = -1.0; sc->rprev = INFINITY; sc->done = 0; sc->status = DS_RUNNING; sc->restart = 0;
     sc->ms_rounds = 0;
@@ -1307,16 +1316,19 @@ __device__ __forceinline__ void solve_body(const DevProblem& p, const DevState& 
     }
   }
   __syncthreads();
-  // initial primal point w0 in every period, duals zero
+  // initial primal point: w0 in every period (paper Section 4.1), or the caller's warm
+  // start; trade duals zero or the caller's.  Scaled coordinates: x = w / dc, y = y_u / dr.
   for (int e = c.tid; e < P * c.nwa; e += TB) {
     const int t = e / c.nwa, li = e % c.nwa, i = c.i0 + li;
-    const double x = V.w0(0, li) / V.dc(0, li);
+    const double x = s.w_init ? s.w_init[(size_t)t * n + i] / p.dc[i] : V.w0(0, li) / V.dc(0, li);
     V.x0s(t, li) = x; V.xs.set(t, li, x); V.Txs.set(t, li, x);
     V.xb(t, li) = 1.0 + 0.25 * (double)((i * 7919 + t * 104729) % 1000) / 1000.0;   // power vector
   }
   for (int e = c.tid; e < Tp * c.nwa; e += TB) {
     const int t = e / c.nwa, li = e % c.nwa;
-    V.ys0C(t, li) = 0.0; V.ysC.set(t, li, 0.0); V.TysC.set(t, li, 0.0);
+    const size_t ix = (size_t)t * n + c.i0 + li;
+    const double y = s.y_init ? s.y_init[(size_t)P * nr + ix] / p.drC[ix] : 0.0;
+    V.ys0C(t, li) = y; V.ysC.set(t, li, y); V.TysC.set(t, li, y);
   }
   __syncthreads();
   const long long t_start = wall_clock64();
@@ -1814,7 +1826,11 @@ __device__ __forceinline__ void solve_body(const DevProblem& p, const DevState& 
       if (*iflag && !multisect_x<LS>(c, P, xv3, xv4, nw, need, dlo, dhi, dmu, &sc->ms_rounds)) goto barrier_fail;
       for (int t = c.tid; t < P; t += TB) next_bracket(dmu[t], dmp[t], dwd[t], dcen[t], dhw[t]);
       __syncthreads();
-      // C2: inner value sum (a'/2 w^2 - b' w), w = sign(b') max(|b'| - mu', 0) / a'
+      // C2: inner value sum (a'/2 w^2 - b' w), w = sign(b') max(|b'| - mu', 0) / a'.
+      // With exposure rows it also carries, per period, max_i |(A^T d)_i| for the
+      // infeasibility test below (d = T(y_A) - y_A, unscaled; staged in Kx, which is not
+      // read again before the next iteration recomputes it).
+      const bool inf_test = ctl.infeas && p.m > 0;
       {
         double iv[1] = {0.0};
         for (int e = c.tid; e < P * c.nwa; e += TB) {
@@ -1824,8 +1840,64 @@ __device__ __forceinline__ void solve_body(const DevProblem& p, const DevState& 
           iv[0] += 0.5 * w * w / ia - b * w;
         }
         wg_sum<1>(c, iv);
-        if (c.tid == 0) put(c, 0, red[RED_OUT]);
-        if (!xsync_x<LS>(c, 1)) goto barrier_fail;
+        const double ivs = red[RED_OUT];
+        __syncthreads();
+        int V2 = 1;
+        if (inf_test) {
+          for (int e = c.tid; e < P * nr; e += TB) {
+            const int j = e % nr;
+            Kx[e] = j < p.m ? Tys[e] - ys[e] : 0.0;
+          }
+          __syncthreads();
+          kty_all(c, Vc, Kx, P, nr, nw, xv1);   // xv1[t][li] = dc_i (A^T d_u)_i
+          const int lane = c.tid & 63, wave = c.tid >> 6;
+          for (int t = wave; t < P; t += NWAVE) {
+            double mx = 0.0;
+            for (int li = lane; li < c.nwa; li += 64) mx = fmax(mx, fabs(xv1[t * nw + li] / Vc.dc(0, li)));
+            mx = wave_max(mx);
+            if (lane == 0) put_max(c, 1 + STW * t, mx);
+          }
+          V2 = 2 + STW * (P - 1);
+          if (c.xmode == XM_GATHER)   // gather mode: every index of the exchange is written
+            for (int j = c.tid; j < V2; j += TB)
+              if (j > 0 && j % STW != 1) put(c, j, 0.0);
+          c.mx_lo = 0;
+          c.mx_hi = V2;
+        }
+        if (c.tid == 0) put(c, 0, ivs);
+        if (!xsync_x<LS>(c, V2)) goto barrier_fail;
+      }
+      // Infeasibility (a Farkas certificate for one period's feasible set, which is the
+      // same in every period): for any y in R^m and feasible w, y^T A w lies between
+      // -||A^T y||_inf (the budget ||w||_1 <= 1) and sum_j max(U_j y_j, L_j y_j) (the box),
+      // so sum_j max(U_j y_j, L_j y_j) + ||A^T y||_inf < 0 proves that no w is feasible.
+      // When the box and the budget do not intersect the exposure duals diverge and
+      // their displacement T(y_A) - y_A tends to such a y.
+      bool infeasible = false;
+      if (inf_test) {
+        lint* infl = iflag + 3;
+        if (c.tid == 0) *infl = 0;
+        __syncthreads();
+        const int lane = c.tid & 63, wave = c.tid >> 6;
+        for (int t = wave; t < P; t += NWAVE) {
+          double sup = 0.0, mag = 0.0;
+          for (int j = lane; j < p.m; j += 64) {
+            const double du = p.dr[j] * Kx[t * nr + j];
+            double term = 0.0;
+            if (du > 0.0) term = isinf(p.U[j]) ? INFINITY : p.U[j] * du;
+            else if (du < 0.0) term = isinf(p.L[j]) ? INFINITY : p.L[j] * du;
+            sup += term;
+            mag += fabs(term);
+          }
+          sup = wave_sum(sup);
+          mag = wave_sum(mag);
+          const double amax = tot[1 + STW * t];
+          if (lane == 0 && amax + mag > 0.0 && sup + amax < -1e-9 * (mag + amax))
+            __hip_atomic_fetch_or(infl, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        }
+        __syncthreads();
+        infeasible = *infl != 0;
+        __syncthreads();
       }
       const double psi = tot[0] + (double)P * p.crisk[0] - c1s[6] - c1s[5] + psi_rows;
       const double rel_pri = sqrt(pres2) / (1.0 + sqrt(clip2));
@@ -1834,7 +1906,9 @@ __device__ __forceinline__ void solve_body(const DevProblem& p, const DevState& 
       const double rel_gap = den > 0.0 ? fabs(phi - psi) / den : 0.0;
       const double relkkt = fmax(rel_pri, fmax(rel_dual, rel_gap));
       const double fpr = sqrt(c1s[0]);
-      const bool nonfinite = c1s[9] > 0.0 || !isfinite(phi) || !isfinite(relkkt);
+      // (fmax drops a NaN operand, so the gap and both objectives are tested themselves)
+      const bool nonfinite = c1s[9] > 0.0 || !isfinite(phi) || !isfinite(psi) || !isfinite(rel_gap) ||
+                             !isfinite(relkkt);
       if (c.tid == 0) {
         sc->checks++;
         sc->restart = 0;
@@ -1846,6 +1920,7 @@ __device__ __forceinline__ void solve_body(const DevProblem& p, const DevState& 
                    sc->it + 1, relkkt, rel_pri, rel_gap, fpr, omega, sc->restarts, sc->spec_miss);
         }
         if (nonfinite) { sc->done = 1; sc->status = DS_NUMERIC; }
+        else if (infeasible) { sc->done = 1; sc->status = DS_INFEASIBLE; }
         else if (relkkt <= ctl.tol) { sc->done = 1; sc->status = DS_OK; }
         else if (c1s[8] > 0.0) { sc->done = 1; sc->status = DS_TIMEOUT; }
         else if (sc->it + 1 >= ctl.max_iter) { sc->done = 1; sc->status = DS_NOT_CONVERGED; }
@@ -1880,10 +1955,12 @@ __device__ __forceinline__ void solve_body(const DevProblem& p, const DevState& 
           double* yA = s.y_out;
           double* yF = s.y_out + (size_t)P * p.m;
           double* yC = s.y_out + (size_t)P * nr;
+          // infeasible: the exposure part holds the certificate direction d of the test
+          const bool cert = sc->status == DS_INFEASIBLE;
           if (c.wg == 0)
             for (int e = c.tid; e < P * nr; e += TB) {
               const int t = e / nr, j = e % nr;
-              const double yu = p.dr[j] * (bad ? ys0[e] : Tys[e]);
+              const double yu = p.dr[j] * (bad ? ys0[e] : (cert && j < p.m ? Kx[e] : Tys[e]));
               if (j < p.m) yA[(size_t)t * p.m + j] = yu; else yF[(size_t)t * p.k + (j - p.m)] = yu;
             }
           for (int e = c.tid; e < Tp * c.nwa; e += TB) {

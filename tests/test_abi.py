@@ -30,6 +30,7 @@ def test_default_options():
     assert o.tol_rel_kkt == 1e-6 and o.check_every == 64 and o.time_limit_s == 360.0
     assert (o.restart_suff, o.restart_nec, o.restart_art) == (0.2, 0.8, 0.36)
     assert o.reflection == 1.0 and o.precision == 0
+    assert (o.deterministic, o.speculative, o.breakpoint_lists, o.infeasibility_check) == (0, -1, 1, 1)
 
 
 def _call(**over):
@@ -68,6 +69,7 @@ def _call(**over):
     (dict(l1=0.0), "lambda1"),
     (dict(l2=-1.0), "lambda2"),
     (dict(l3=float("nan")), "lambda2 and lambda3"),
+    (dict(l1=1e200, GMV=1e200), "lambda1 * GMV"),
 ])
 def test_invalid_arguments_rejected_on_host(over, needle):
     rc, msg = _call(**over)
@@ -79,7 +81,9 @@ def test_invalid_options_rejected_on_host():
     lib = ff.lib()
     fake = ctypes.c_void_p(0x1000)
     for field, val in (("tol_rel_kkt", 0.0), ("max_iter", 0), ("check_every", 0), ("reflection", 1.5),
-                       ("precision", 7), ("precision", 2), ("time_limit_s", -1.0)):   # bf16 rows: batched only
+                       ("precision", 7), ("precision", 2), ("time_limit_s", -1.0),   # bf16 rows: batched only
+                       ("deterministic", 2), ("speculative", -2), ("speculative", 2), ("breakpoint_lists", -1),
+                       ("infeasibility_check", 2), ("workgroups", -1)):
         o = ff.default_options()
         setattr(o, field, val)
         info = ff._Info()
@@ -132,3 +136,23 @@ def test_batched_rejects_invalid_arguments(kw, needle):
     rc, msg = _call_batched(**kw)
     assert rc == 1, (rc, msg)
     assert needle in msg, msg
+
+
+@pytest.mark.parametrize("omega", [-1.0, float("nan"), float("inf")])
+def test_warm_start_rejects_bad_primal_weight(omega):
+    lib = ff.lib()
+    fake = ctypes.c_void_p(0x1000)
+    info = ff._Info()
+    rc = lib.ffo_solve_warm(10, 2, 1, 0, fake, fake, fake, fake, fake, fake, 1.5, fake, fake, fake, fake, 1e9,
+                            1e-9, 1.0, 1.0, None, fake, fake, omega, None, None, fake, None, ctypes.byref(info))
+    assert rc == 1
+    assert "omega_init" in lib.ffo_last_error().decode()
+
+
+def test_warm_start_checks_problem_arguments_first():
+    lib = ff.lib()
+    fake = ctypes.c_void_p(0x1000)
+    info = ff._Info()
+    rc = lib.ffo_solve_warm(0, 2, 1, 0, fake, fake, fake, fake, fake, fake, 1.5, fake, fake, fake, fake, 1e9,
+                            1e-9, 1.0, 1.0, None, fake, fake, 1.0, None, None, fake, None, ctypes.byref(info))
+    assert rc == 1 and "n must" in lib.ffo_last_error().decode()

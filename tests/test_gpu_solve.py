@@ -133,43 +133,40 @@ def test_iteration_limit_returns_last_iterate():
     assert np.abs(W.cpu().numpy()).sum() <= 1.0 + 1e-12
 
 
-def test_gather_mode_is_bitwise_repeatable(monkeypatch):
+def test_deterministic_mode_is_bitwise_repeatable():
     ff = _gpu()
-    monkeypatch.setenv("FFO_XMODE", "1")
     inst = make_config(0)
-    W1, i1 = ff.solve_instance(inst, tol=1e-7)
-    W2, i2 = ff.solve_instance(inst, tol=1e-7)
+    W1, i1 = ff.solve_instance(inst, tol=1e-7, deterministic=True)
+    W2, i2 = ff.solve_instance(inst, tol=1e-7, deterministic=True)
     assert i1.iters == i2.iters
     assert torch.equal(W1, W2)
 
 
 @pytest.mark.parametrize("T,n,wg,tol", [(0, 500, 0, 1e-8), (0, 500, 6, 1e-8), (6, 120, 0, 1e-8), (6, 120, 5, 1e-8),
                                         (10, 300, 7, 1e-9)])
-def test_breakpoint_lists_match_multisection(monkeypatch, T, n, wg, tol):
+def test_breakpoint_lists_match_multisection(T, n, wg, tol):
     """The multiplier finished from the published breakpoint lists (default) and by
-    multisection exchanges alone (FFO_LISTS=0) give the same solution; both meet the
+    multisection exchanges alone (breakpoint_lists=0) give the same solution; both meet the
     oracle's bars.  Several workgroups make the lists cross workgroup boundaries.  (The
     T=10 case needs relative KKT 1e-9 for 1e-6 in the weights: at 1e-8 either path is
     1.9e-6 away, the weak strong convexity noted in the module docstring.)"""
     inst = make_config(0) if T == 0 else make_multi(T, n, 4, 6, seed=50 + T)
     ref = oracle.solve(inst, tol=1e-10)
     out = {}
-    for lists in ("0", "1"):
-        monkeypatch.setenv("FFO_LISTS", lists)
-        W, info, Y = _run(inst, tol=tol, workgroups=wg)
+    for lists in (False, True):
+        W, info, Y = _run(inst, tol=tol, workgroups=wg, breakpoint_lists=lists)
         _check(inst, W, info, Y, ref, tol, w_tol=1e-6)
         out[lists] = W
-    assert np.max(np.abs(out["0"] - out["1"])) <= 1e-6
+    assert np.max(np.abs(out[False] - out[True])) <= 1e-6
 
 
-def test_gather_mode_multi_period_bitwise_repeatable(monkeypatch):
-    """Lists are gathered in arrival order and then sorted: repeated solves in gather
-    mode (fixed-order sums) stay bitwise identical."""
+def test_deterministic_mode_multi_period_bitwise_repeatable():
+    """Lists are gathered in arrival order and then sorted: repeated solves in the
+    deterministic mode (fixed-order sums) stay bitwise identical."""
     ff = _gpu()
-    monkeypatch.setenv("FFO_XMODE", "1")
     inst = make_multi(6, 120, 4, 6, seed=56)
-    W1, i1 = ff.solve_instance(inst, tol=1e-8, workgroups=5)
-    W2, i2 = ff.solve_instance(inst, tol=1e-8, workgroups=5)
+    W1, i1 = ff.solve_instance(inst, tol=1e-8, workgroups=5, deterministic=True)
+    W2, i2 = ff.solve_instance(inst, tol=1e-8, workgroups=5, deterministic=True)
     assert i1.iters == i2.iters
     assert torch.equal(W1, W2)
 

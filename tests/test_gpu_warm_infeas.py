@@ -1,0 +1,202 @@
+"""GPU: warm-started re-solves, infeasibility certificates, and the time-limit and
+non-finite statuses, through the C ABI (ffo_solve_warm, ffo_solve).
+
+Warm starts (rolling re-solves from date to date) must reach the same solution as the
+oracle's with fewer iterations than a cold start; infeasible exposure boxes (paper
+Section 2.1 eq. 2-3: no w with L <= A w <= U and ||w||_1 <= 1) must stop with
+FFO_INFEASIBLE and a certificate that the oracle verifies, and never on feasible markets.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from oracle.feasibility import certificate_value, is_feasible, min_budget
+from oracle.problem import normalize, kkt, objective
+from synth import make_config, make_multi, make_single
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2604_22625_amd as ff
+    return ff
+
+
+def _solve(inst, **kw):
+    ff = _gpu()
+    print(f"[case] n={inst['alpha'].shape[-1]} T={inst.get('T', 0)} "
+          f"kw={ {k: v for k, v in kw.items() if k not in ('w_init', 'y_init')} }", flush=True)
+    kw.setdefault("time_limit_s", 30.0)
+    kw.setdefault("max_iter", 200000)
+    W, info, Y = ff.solve_instance(inst, return_dual=True, **kw)
+    torch.cuda.synchronize()
+    return W, info, Y
+
+
+def _np(Y):
+    return tuple(y.cpu().numpy() for y in Y)
+
+
+def _check_against_oracle(inst, W, info, Y, ref, tol, w_tol):
+    pb = normalize(inst, factor=np.linalg.cholesky(inst["Omega"]))
+    assert info.status == 0, info
+    K = kkt(pb, W, *Y)
+    assert K.rel_kkt <= 2.0 * tol, K
+    assert np.max(np.abs(W - ref.W)) <= w_tol
+    assert abs(objective(pb, W) - ref.phi) <= 2.0 * tol * abs(ref.phi)
+
+
+def _next_date(inst, seed, scale=0.05):
+    """The same market one date later: expected returns moved by a small fraction."""
+    rng = np.random.default_rng(seed)
+    out = dict(inst)
+    out["alpha"] = inst["alpha"] * (1.0 + scale * rng.normal(size=inst["alpha"].shape))
+    return out
+
+
+# ------------------------------------------------------------------ warm starts
+
+def test_warm_start_at_the_solution_stops_at_the_first_check():
+    inst = make_config(0)
+    W, info, Y = _solve(inst, tol=1e-8)
+    W2, info2, Y2 = _solve(inst, tol=1e-8, w_init=W, y_init=Y, omega_init=info.omega)
+    assert info2.status == 0 and info2.iters <= 64
+    ref = oracle.solve(inst, tol=1e-10)
+    _check_against_oracle(inst, W2.cpu().numpy(), info2, _np(Y2), ref, 1e-8, 1e-6)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_rolling_resolve_single_period(precision):
+    base = make_config(0)
+    W, info, Y = _solve(base, tol=1e-7, precision=precision)
+    nxt = _next_date(base, seed=1)
+    _, cold, _ = _solve(nxt, tol=1e-7, precision=precision)
+    W2, warm, Y2 = _solve(nxt, tol=1e-7, precision=precision, w_init=W, y_init=Y, omega_init=info.omega)
+    print(f"cold {cold.iters} warm {warm.iters}", flush=True)
+    assert warm.iters < cold.iters
+    ref = oracle.solve(nxt, tol=1e-10)
+    _check_against_oracle(nxt, W2.cpu().numpy(), warm, _np(Y2), ref, 1e-7, 5e-6)
+
+
+def test_rolling_resolve_multi_period():
+    base = make_multi(6, 120, 4, 6, seed=61)
+    W, info, Y = _solve(base, tol=1e-8)
+    nxt = _next_date(base, seed=2)
+    _, cold, _ = _solve(nxt, tol=1e-8)
+    W2, warm, Y2 = _solve(nxt, tol=1e-8, w_init=W, y_init=Y, omega_init=info.omega)
+    print(f"cold {cold.iters} warm {warm.iters}", flush=True)
+    assert warm.iters < cold.iters
+    ref = oracle.solve(nxt, tol=1e-10)
+    _check_against_oracle(nxt, W2.cpu().numpy(), warm, _np(Y2), ref, 1e-8, 1e-6)
+
+
+def test_warm_start_weights_only_matches_oracle():
+    inst = make_single(300, 10, 8, seed=12)
+    w_init = np.tile(inst["w0"] * 0.5, (1, 1))
+    W, info, Y = _solve(inst, tol=1e-8, w_init=w_init)
+    ref = oracle.solve(inst, tol=1e-10)
+    _check_against_oracle(inst, W.cpu().numpy(), info, _np(Y), ref, 1e-8, 1e-6)
+
+
+def test_warm_start_rejects_non_finite_values():
+    ff = _gpu()
+    inst = make_config(0)
+    bad = np.tile(inst["w0"], (1, 1))
+    bad[0, 7] = np.nan
+    with pytest.raises(ff.FolioError) as e:
+        ff.solve_instance(inst, w_init=bad)
+    assert e.value.status == 1 and "warm-start" in str(e.value)
+
+
+# ------------------------------------------------------------------ infeasibility
+
+def _infeasible_single():
+    inst = make_config(0)
+    out = dict(inst)
+    out["L"] = inst["L"].copy()
+    out["U"] = inst["U"].copy()
+    out["L"][0] = out["U"][0] = 1.5        # a one-hot sector row above the gross budget
+    return out
+
+
+@pytest.mark.parametrize("deterministic", [False, True])
+def test_infeasible_sector_bound_is_certified(deterministic):
+    inst = _infeasible_single()
+    assert not is_feasible(inst) and min_budget(inst) > 1.0
+    W, info, (yA, yF, yC) = _solve(inst, tol=1e-6, raise_on_failure=False, deterministic=deterministic)
+    assert info.status == 6, info
+    assert info.iters <= 20000
+    vals = [certificate_value(inst, y) for y in yA.cpu().numpy()]
+    assert min(vals) < 0.0, vals
+    assert np.all(np.isfinite(W.cpu().numpy()))
+
+
+def test_infeasible_multi_period_is_certified():
+    inst = make_multi(5, 200, 4, 8, seed=63)
+    inst = dict(inst)
+    m_sec = 5
+    # two sectors each held at >= 0.6 of gross exposure: impossible within ||w||_1 <= 1
+    inst["L"] = inst["L"].copy(); inst["U"] = inst["U"].copy()
+    inst["L"][:2] = 0.6
+    inst["U"][:2] = 0.7
+    assert m_sec <= inst["A"].shape[0] and not is_feasible(inst)
+    W, info, (yA, _, _) = _solve(inst, tol=1e-6, raise_on_failure=False)
+    assert info.status == 6, info
+    vals = [certificate_value(inst, y) for y in yA.cpu().numpy()]
+    assert min(vals) < 0.0, vals
+
+
+def test_infeasibility_check_off_runs_to_the_limit():
+    inst = _infeasible_single()
+    _, info, _ = _solve(inst, tol=1e-6, raise_on_failure=False, infeasibility_check=False, max_iter=2048)
+    assert info.status == 4 and info.iters == 2048
+
+
+def test_binding_raises_on_infeasible():
+    ff = _gpu()
+    with pytest.raises(ff.FolioError) as e:
+        ff.solve_instance(_infeasible_single(), tol=1e-6)
+    assert e.value.status == 6
+
+
+def test_tight_but_feasible_box_is_not_flagged():
+    # the sector row pinned at a value the budget can just reach (min budget 0.95)
+    inst = make_config(0)
+    inst = dict(inst)
+    inst["L"] = inst["L"].copy(); inst["U"] = inst["U"].copy()
+    inst["L"][0] = inst["U"][0] = 0.95
+    mb = min_budget(inst)
+    assert mb <= 1.0
+    W, info, Y = _solve(inst, tol=1e-7)
+    assert info.status == 0
+    ref = oracle.solve(inst, tol=1e-10)
+    _check_against_oracle(inst, W.cpu().numpy(), info, _np(Y), ref, 1e-7, 5e-6)
+
+
+# ------------------------------------------------------------------ other statuses
+
+def test_time_limit_returns_the_last_iterate():
+    inst = make_config(1, seed=2)
+    W, info, _ = _solve(inst, tol=1e-9, time_limit_s=1e-5, raise_on_failure=False)
+    assert info.status == 7, info
+    W = W.cpu().numpy()
+    assert np.all(np.isfinite(W)) and np.abs(W).sum() <= 1.0 + 1e-12
+
+
+def test_overflowing_dual_start_is_reported_non_finite():
+    # a finite but enormous starting trade dual overflows the conjugate of the impact
+    # cost in the FP64 check: the solve stops with FFO_NUMERIC and returns the last
+    # finite restart point (here the starting weights)
+    inst = make_config(0)
+    n, m, k = inst["alpha"].shape[1], inst["A"].shape[0], inst["F"].shape[1]
+    y_init = np.zeros(m + k + n)
+    y_init[m + k:] = 1e300
+    W, info, _ = _solve(inst, tol=1e-6, y_init=y_init, raise_on_failure=False)
+    assert info.status == 5, info
+    W = W.cpu().numpy()
+    assert np.all(np.isfinite(W))
+    np.testing.assert_allclose(W[0], inst["w0"], rtol=1e-15, atol=0)
