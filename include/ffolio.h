@@ -181,6 +181,28 @@ ffo_status ffo_solve_warm(int64_t n, int64_t k, int64_t m, int64_t T,
                           double* w_out, double* y_out, ffo_info* info);
 
 /*
+ * Allocation-free solve, for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid allocation).  Same
+ * arguments, outputs and statuses as ffo_solve; it runs the same kernels, but its
+ * workspace is one static device array of 32 MiB per GPU (held until the process ends)
+ * instead of the library's cache, and it calls no hipMalloc, hipFree or other allocating
+ * routine (the first call on a device takes the array's device address and creates three
+ * timing events).  A problem whose workspace exceeds 32 MiB (about the constraint rows,
+ * (m+k) x n doubles, plus a dozen vectors of P*n doubles; n = 5000 with m + k = 140 uses
+ * 7 MB) returns FFO_EINVAL before any device work.  Every call on a GPU shares that
+ * GPU's array and the library's static host staging area, so calls are serialised by a
+ * lock; calls that overlap on one GPU from different processes are not supported.  The
+ * result is read back through a synchronous copy into static (pageable) host memory.
+ */
+ffo_status ffo_solve_noalloc(int64_t n, int64_t k, int64_t m, int64_t T,
+                             const double* alpha, const double* F, const double* Omega,
+                             const double* delta, const double* s, const double* q, double d,
+                             const double* A, const double* L, const double* U, const double* w0,
+                             double GMV, double lambda1, double lambda2, double lambda3,
+                             const double* w_target, const ffo_options* opt, void* stream,
+                             double* w_out, double* y_out, ffo_info* info);
+
+/*
  * Adjoint form: gradients of a loss l(W*) of the solution with respect to the expected
  * returns, the spread coefficients and the factor loadings (A, L, U, Omega, delta, q
  * held fixed).  The problem arguments are those of the ffo_solve call that produced

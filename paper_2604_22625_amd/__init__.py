@@ -91,6 +91,8 @@ def lib() -> ctypes.CDLL:
                                      _D, _D, _D, _D, _P, _P, _P, _D, ctypes.POINTER(_Options), _P, _P, _P,
                                      ctypes.POINTER(_Info)]
         L.ffo_solve_warm.restype = ctypes.c_int
+        L.ffo_solve_noalloc.argtypes = L.ffo_solve.argtypes
+        L.ffo_solve_noalloc.restype = ctypes.c_int
         L.ffo_solve_batched.argtypes = [_I64, _P, _I64, _I64, _I64, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P,
                                         _D, _D, _D, _D, _D, ctypes.POINTER(_Options), _P, _P, _P]
         L.ffo_solve_batched.restype = ctypes.c_int
@@ -157,7 +159,7 @@ def solve(alpha, F, Omega, delta, s, q, d, A, L, U, w0, GMV, lambda1, lambda2, l
           workgroups: int = 0, verbose: int = 0, return_dual: bool = False, precision="fp64",
           deterministic: bool = False, speculative: int = -1, breakpoint_lists: bool = True,
           infeasibility_check: bool = True, w_init=None, y_init=None, omega_init: float = 0.0,
-          raise_on_failure: bool = True, device=None, stream=None, out=None):
+          noalloc: bool = False, raise_on_failure: bool = True, device=None, stream=None, out=None):
     """Solve one single-period (w_target is None) or multi-period instance on the GPU.
 
     Arrays follow include/ffolio.h: alpha [P][n] (P = 1 or T-1), F [n][k], Omega [k][k],
@@ -168,6 +170,7 @@ def solve(alpha, F, Omega, delta, s, q, d, A, L, U, w0, GMV, lambda1, lambda2, l
     "fp64" or "fp32" (float32 iterates and matrix copies, float64 reductions and checks).
     ``w_init`` [P][n], ``y_init`` (tuple yA, yF, yC or the packed vector) and
     ``omega_init`` start the iteration from a previous solution (ffo_solve_warm).
+    ``noalloc`` calls the allocation-free entry point (ffo_solve_noalloc; no warm start).
     """
     torch = _torch()
     if not torch.cuda.is_available():
@@ -217,7 +220,11 @@ def solve(alpha, F, Omega, delta, s, q, d, A, L, U, w0, GMV, lambda1, lambda2, l
             float(lambda3), _ptr(wTd))
     tail = (ctypes.byref(o), ctypes.c_void_p(st.cuda_stream), _ptr(W), _ptr(Y), ctypes.byref(info))
     with torch.cuda.device(dev):
-        if w_init is None and y_init is None and not omega_init:
+        if noalloc:
+            if w_init is not None or y_init is not None or omega_init:
+                raise ValueError("the allocation-free entry point takes no warm start")
+            rc = lib().ffo_solve_noalloc(*args, *tail)
+        elif w_init is None and y_init is None and not omega_init:
             rc = lib().ffo_solve(*args, *tail)
         else:
             wi = _dev_f64(w_init, dev).reshape(P, n) if w_init is not None else None

@@ -528,6 +528,48 @@ ffo_status solve_impl(int64_t n, int64_t k, int64_t m, int64_t T, const double* 
   return st;
 }
 
+// ---- memory of the allocation-free entry point (ffo_solve_noalloc) ----
+// One static device array per GPU (each device holds its own copy of `scratch` for the
+// life of the process).  Host code never passes `scratch` itself to a kernel or a copy:
+// its device address comes from hipGetSymbolAddress, once per device, with that device
+// current, and is kept in g_static[dev].ptr.
+constexpr size_t kScratchBytes = (size_t)32 << 20;
+__device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+// host staging of that entry point: Omega, its factor and the factorisation's work space
+// (k <= 128), the info record and the flags, in static host memory (no allocation)
+constexpr size_t kStaticHostBytes = (size_t)4 * 128 * 128 * 8 + 16384;
+alignas(256) unsigned char g_static_host[kStaticHostBytes];
+
+struct StaticSlot {
+  bool ready = false;
+  void* ptr = nullptr;       // device address of `scratch` on this device
+  hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
+};
+constexpr int kMaxDevices = 64;
+StaticSlot g_static[kMaxDevices];
+std::mutex g_static_mu;      // serialises the entry point (one static host staging area)
+
+// Set-up of the current device for the allocation-free entry point: the device address
+// of `scratch` and three timing events, taken once per device.
+ffo_status static_slot(int dev, StaticSlot** out) {
+  if (dev < 0 || dev >= kMaxDevices) return fail(FFO_EDEVICE, "device index beyond the static slots");
+  StaticSlot& sl = g_static[dev];
+  if (!sl.ready) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || ptr == nullptr)
+      return fail(FFO_EDEVICE, std::string("hipGetSymbolAddress of the static scratch failed: ") +
+                                   hipGetErrorString(e));
+    for (auto& ev : sl.ev)
+      if (!ev && hipEventCreate(&ev) != hipSuccess) return fail(FFO_EDEVICE, "hipEventCreate failed");
+    sl.ptr = ptr;
+    sl.ready = true;
+  }
+  *out = &sl;
+  return FFO_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -573,6 +615,22 @@ ffo_status ffo_solve(int64_t n, int64_t k, int64_t m, int64_t T, const double* a
                      const ffo_options* opt_in, void* stream, double* w_out, double* y_out, ffo_info* info) {
   return solve_impl(n, k, m, T, alpha, F, Omega, delta, s, q, d, A, L, U, w0, GMV, lambda1, lambda2, lambda3,
                     w_target, nullptr, nullptr, 0.0, opt_in, stream, w_out, y_out, info, nullptr);
+}
+
+ffo_status ffo_solve_noalloc(int64_t n, int64_t k, int64_t m, int64_t T, const double* alpha, const double* F,
+                             const double* Omega, const double* delta, const double* s, const double* q, double d,
+                             const double* A, const double* L, const double* U, const double* w0, double GMV,
+                             double lambda1, double lambda2, double lambda3, const double* w_target,
+                             const ffo_options* opt_in, void* stream, double* w_out, double* y_out, ffo_info* info) {
+  g_err.clear();
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lk(g_static_mu);
+  StaticSlot* sl = nullptr;
+  if (ffo_status st = static_slot(dev, &sl)) return st;
+  const Fixed fx{(char*)sl->ptr, kScratchBytes, (char*)g_static_host, kStaticHostBytes, sl->ev};
+  return solve_impl(n, k, m, T, alpha, F, Omega, delta, s, q, d, A, L, U, w0, GMV, lambda1, lambda2, lambda3,
+                    w_target, nullptr, nullptr, 0.0, opt_in, stream, w_out, y_out, info, &fx);
 }
 
 ffo_status ffo_solve_warm(int64_t n, int64_t k, int64_t m, int64_t T, const double* alpha, const double* F,
