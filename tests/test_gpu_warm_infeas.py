@@ -174,8 +174,15 @@ def test_tight_but_feasible_box_is_not_flagged():
     assert 0.95 <= mb <= 1.0
     W, info, Y = _solve(inst, tol=1e-7)
     assert info.status == 0
-    ref = oracle.solve(inst, tol=1e-10)
-    _check_against_oracle(inst, W.cpu().numpy(), info, _np(Y), ref, 1e-7, 5e-6)
+    # the oracle's active-set polish does not certify this degenerate box, so the pair is
+    # checked through the oracle's own KKT evaluation and the feasibility of W
+    pb = normalize(inst, factor=np.linalg.cholesky(inst["Omega"]))
+    Wn = W.cpu().numpy()
+    K = kkt(pb, Wn, *_np(Y))
+    assert K.rel_kkt <= 2e-7, K
+    AW = Wn @ pb.A.T
+    assert np.all(AW >= pb.L - 1e-6) and np.all(AW <= pb.U + 1e-6)
+    assert np.abs(Wn).sum() <= 1.0 + 1e-12
 
 
 # ------------------------------------------------------------------ other statuses
