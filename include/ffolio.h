@@ -95,6 +95,13 @@ typedef struct {
   int32_t infeasibility_check; /* 1 (default): at every check, test the exposure-dual
                               displacement for an infeasibility certificate and stop with
                               FFO_INFEASIBLE when one is found; 0: never               */
+  int32_t batched_form;    /* ffo_solve_batched only.  1: the team form (each instance runs
+                              the solve kernel's loop on its own team of workgroups);
+                              2: the lockstep form (every unconverged instance advances one
+                              iteration per step, the products over the shared rows run as
+                              float64 matrix-core GEMMs; FFO_FP64 only); 0 (default): the
+                              lockstep form when it applies (FFO_FP64, m + k <= 128),
+                              else the team form                                      */
 } ffo_options;
 
 typedef struct {

@@ -528,6 +528,315 @@ ffo_status solve_impl(int64_t n, int64_t k, int64_t m, int64_t T, const double* 
   return st;
 }
 
+// ---- lockstep batched form (kernels in lockstep.hip) ----
+
+// Tunables of the lockstep form: slot groups per K~^T y tile, assets per K~ x chunk,
+// threads of the per-instance workgroups.  They change the speed, and the rounding of
+// some sums, never the method.
+struct LsTune {
+  int gpt = 2, ch = 256, threads = 512;
+};
+
+// Autotuned choices, cached per shape for the life of the process.
+std::mutex g_tune_mu;
+std::map<std::tuple<int64_t, int64_t, int64_t, int64_t, int>, LsTune> g_tune;
+
+struct LsBuffers {
+  hipStream_t ps = nullptr;   // private stream (graph capture needs a non-null stream)
+  hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+};
+std::map<std::tuple<int, void*>, LsBuffers> g_ls;
+
+ffo_status ls_buffers(int dev, void* stream, LsBuffers** out) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  LsBuffers& b = g_ls[std::make_tuple(dev, stream)];
+  if (!b.ps && hipStreamCreateWithFlags(&b.ps, hipStreamNonBlocking) != hipSuccess)
+    return fail(FFO_EDEVICE, "hipStreamCreateWithFlags failed");
+  for (auto& e : b.ev)
+    if (!e && hipEventCreate(&e) != hipSuccess) return fail(FFO_EDEVICE, "hipEventCreate failed");
+  *out = &b;
+  return FFO_OK;
+}
+
+// One lockstep iteration (check = 0) or the checked iteration and the check (check = 1)
+// on stream ps; grids from the tile capacities.
+hipError_t ls_enqueue_iter(const ffo::LsShared& S, const LsTune& tu, int gA, int gC, int check, hipStream_t ps) {
+  int e = ffo::ls_launch_kty(S, S.yh, S.R, gA, ps);
+  if (!e) e = ffo::ls_launch_primal(S, check, tu.threads, ps);
+  if (!e) e = ffo::ls_launch_kx(S, S.xbar, gC, ps);
+  if (!e) e = ffo::ls_launch_dual(S, check ? 1 : 0, ps);
+  if (check) {
+    if (!e) e = ffo::ls_launch_kty(S, S.yhT, S.R, gA, ps);
+    if (!e) e = ffo::ls_launch_kx(S, S.Tx, gC, ps);
+    if (!e) e = ffo::ls_launch_check(S, tu.threads, ps);
+    if (!e) e = ffo::ls_launch_compact(S, ps);
+  }
+  return (hipError_t)e;
+}
+
+// Graph of `iters` iterations (the last one checked when `check`).
+hipError_t ls_graph(const ffo::LsShared& S, const LsTune& tu, int gA, int gC, int iters, bool check, hipStream_t ps,
+                    hipGraphExec_t* exec) {
+  hipGraph_t g = nullptr;
+  hipError_t e = hipStreamBeginCapture(ps, hipStreamCaptureModeThreadLocal);
+  if (e != hipSuccess) return e;
+  hipError_t le = hipSuccess;
+  for (int it = 0; it < iters && le == hipSuccess; ++it)
+    le = ls_enqueue_iter(S, tu, gA, gC, check && it == iters - 1 ? 1 : 0, ps);
+  e = hipStreamEndCapture(ps, &g);
+  if (le != hipSuccess) { if (g) hipGraphDestroy(g); return le; }
+  if (e != hipSuccess) return e;
+  e = hipGraphInstantiate(exec, g, nullptr, nullptr, 0);
+  hipGraphDestroy(g);
+  return e;
+}
+
+// Initial state, slot lists, and the power iteration for every instance's step size.
+hipError_t ls_start(const ffo::LsShared& S, const LsTune& tu, int gA, int gC, const int32_t* hact, int32_t* hcnt,
+                    hipStream_t ps) {
+  hipError_t e = hipMemcpyAsync(S.act, hact, (size_t)S.B * 4, hipMemcpyHostToDevice, ps);
+  if (e != hipSuccess) return e;
+  hcnt[0] = S.B; hcnt[1] = hcnt[2] = hcnt[3] = 0;
+  if ((e = hipMemcpyAsync(S.cnt, hcnt, 16, hipMemcpyHostToDevice, ps)) != hipSuccess) return e;
+  int r = ffo::ls_launch_init(S, ps);
+  if (!r) r = ffo::ls_launch_compact(S, ps);
+  for (int pw = 0; pw < 40 && !r; ++pw) {
+    r = ffo::ls_launch_kx(S, S.xbar, gC, ps);
+    if (!r) r = ffo::ls_launch_dual(S, 2, ps);
+    if (!r) r = ffo::ls_launch_kty(S, S.yhT, S.R, gA, ps);
+    if (!r) r = ffo::ls_launch_power(S, 1, ps);
+  }
+  if (!r) r = ffo::ls_launch_power(S, 2, ps);
+  return (hipError_t)r;
+}
+
+ffo_status batched_lockstep(int64_t B, const int64_t* n_b, int64_t n_max, int64_t k, int64_t m, const double* F,
+                            const double* Omega, const double* delta, const double* A, const int64_t* offs,
+                            const double* alpha, const double* s, const double* q, const double* w0,
+                            const double* L, const double* U, double d, double GMV, double lambda1, double lambda2,
+                            double lambda3, const ffo_options& opt, void* stream, double* w_out, ffo_info* infos) {
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  hipDeviceProp_t prop;
+  HIPCHK(hipGetDeviceProperties(&prop, dev));
+  int wall_khz = 0;
+  if (hipDeviceGetAttribute(&wall_khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess || wall_khz <= 0)
+    wall_khz = 100000;
+  const int nr = (int)(m + k);
+  const int ldk = (int)((n_max + 63) / 64 * 64);
+  const int nrp = (nr + 15) / 16 * 16;
+  const int64_t N = offs[B];
+  const int ce = opt.check_every;
+  const size_t lds_total = (size_t)std::min<size_t>(prop.sharedMemPerBlock, 160 * 1024);
+
+  // slots: instances by decreasing n_b (ties by index)
+  std::vector<int32_t> order(B);
+  for (int64_t b = 0; b < B; ++b) order[b] = (int32_t)b;
+  std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return n_b[a] > n_b[b]; });
+
+  // tunables: cached per shape, tuned on first use unless the deterministic mode asks
+  // for the fixed defaults
+  const auto key = std::make_tuple(B, n_max, (int64_t)nr, N, ce);
+  LsTune tu;
+  bool tuned = opt.deterministic != 0;
+  if (!tuned) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tune.find(key);
+    if (it != g_tune.end()) { tu = it->second; tuned = true; }
+  }
+  // capacities for the largest tunables (gpt = 1, ch = 128)
+  const int64_t Gmax = (B + 15) / 16;
+  const int64_t nab = (n_max + 63) / 64;
+  const int64_t maxA = nab * Gmax, nchunk_max = (n_max + 127) / 128, maxC = Gmax * nchunk_max;
+  const int gA = (int)std::min<int64_t>(maxA, 2048), gC = (int)std::min<int64_t>(maxC, 2048);
+
+  // ---- workspace ----
+  size_t off = 0;
+  auto carve = [&](size_t cnt, size_t elt) { const size_t o = off; off = align_up(off + cnt * elt); return o; };
+  const size_t oK = carve((size_t)nr * ldk, 8), oKT = carve((size_t)n_max * nrp, 8), odrs = carve((size_t)B * nr, 8);
+  const size_t odc = carve(n_max, 8), odrC = carve(n_max, 8), oar = carve(n_max, 8), ocv = carve(n_max, 8);
+  const size_t oca = carve(N, 8), ocb = carve(N, 8), onb64 = carve(B, 8), onb32 = carve(B, 4), ooffs = carve(B + 1, 8);
+  const size_t oC = carve(std::max<int64_t>(k * k, 1), 8);
+  size_t ov[10];
+  for (auto& o : ov) o = carve(N, 8);
+  size_t orow[5];
+  for (auto& o : orow) o = carve((size_t)B * nrp, 8);
+  const size_t opart = carve((size_t)nchunk_max * B * nrp, 8);
+  const size_t oinst = carve(B, sizeof(ffo::LsInst)), oact = carve(B, 4), ocnt = carve(4, 4);
+  const size_t otA = carve((size_t)3 * maxA, 4), otC = carve((size_t)2 * maxC, 4);
+  const size_t oinfo = carve((size_t)B * ffo::INFO_LEN, 8), ostat = carve(B, 4), oclk = carve(1, 8), oflag = carve(1, 4);
+  const size_t total = off;
+  size_t hoff = 0;
+  auto hcarve = [&](size_t bytes) { const size_t o = hoff; hoff = align_up(hoff + bytes); return o; };
+  const size_t kk2 = (size_t)std::max<int64_t>(k * k, 1);
+  const size_t hOm_o = hcarve(kk2 * 8), hC_o = hcarve(kk2 * 8), hW_o = hcarve(2 * kk2 * 8), hflag_o = hcarve(4);
+  const size_t hnb_o = hcarve((size_t)B * 8), hnb32_o = hcarve((size_t)B * 4), hoffs_o = hcarve((size_t)(B + 1) * 8);
+  const size_t hact_o = hcarve((size_t)B * 4), hcnt_o = hcarve(16), hinfo_o = hcarve((size_t)B * ffo::INFO_LEN * 8);
+  const size_t hstat_o = hcarve((size_t)B * 4);
+  Workspace* ws = nullptr;
+  if (ffo_status st = get_workspace(dev, stream, total, hoff, &ws, 3)) return st;
+  LsBuffers* lb = nullptr;
+  if (ffo_status st = ls_buffers(dev, stream, &lb)) return st;
+  char* Bd = (char*)ws->base;
+  char* Hb = (char*)ws->host;
+  auto D = [&](size_t o) { return (double*)(Bd + o); };
+  hipStream_t hs = (hipStream_t)stream, ps = lb->ps;
+  double* hOm = (double*)(Hb + hOm_o);
+  double* hC = (double*)(Hb + hC_o);
+  int* hflag = (int*)(Hb + hflag_o);
+  int32_t* hact = (int32_t*)(Hb + hact_o);
+  int32_t* hcnt = (int32_t*)(Hb + hcnt_o);
+
+  // ---- validation, Omega, setup (on the caller's stream) ----
+  HIPCHK(hipEventRecord(ws->ev[0], hs));
+  std::memcpy(Hb + hnb_o, n_b, (size_t)B * 8);
+  std::memcpy(Hb + hoffs_o, offs, (size_t)(B + 1) * 8);
+  for (int64_t b = 0; b < B; ++b) ((int32_t*)(Hb + hnb32_o))[b] = (int32_t)n_b[b];
+  for (int64_t b = 0; b < B; ++b) hact[b] = order[b];
+  HIPCHK(hipMemcpyAsync(Bd + onb64, Hb + hnb_o, (size_t)B * 8, hipMemcpyHostToDevice, hs));
+  HIPCHK(hipMemcpyAsync(Bd + onb32, Hb + hnb32_o, (size_t)B * 4, hipMemcpyHostToDevice, hs));
+  HIPCHK(hipMemcpyAsync(Bd + ooffs, Hb + hoffs_o, (size_t)(B + 1) * 8, hipMemcpyHostToDevice, hs));
+  HIPCHK(fill(Bd + oflag, 4, 0u, hs));
+  hipLaunchKernelGGL(k_validate, dim3(64), dim3(256), 0, hs, n_max, (int64_t)0, (int64_t)0, n_max * k, (int64_t)0,
+                     (const double*)nullptr, F, delta, (const double*)nullptr, (const double*)nullptr,
+                     (const double*)nullptr, (const double*)nullptr, (const double*)nullptr, (const double*)nullptr,
+                     (int*)(Bd + oflag));
+  hipLaunchKernelGGL(k_validate_packed, dim3(64), dim3(256), 0, hs, N, B * m, alpha, s, q, w0, L, U, (int*)(Bd + oflag));
+  HIPCHK(hipGetLastError());
+  if (k > 0) HIPCHK(hipMemcpyAsync(hOm, Omega, (size_t)k * k * 8, hipMemcpyDeviceToHost, hs));
+  HIPCHK(hipMemcpyAsync(hflag, Bd + oflag, 4, hipMemcpyDeviceToHost, hs));
+  HIPCHK(hipStreamSynchronize(hs));
+  if (*hflag) return fail(FFO_EINVAL, bad_values(*hflag));
+  if (k > 0 && !factor_omega((int)k, hOm, hC, (double*)(Hb + hW_o)))
+    return fail(FFO_EINVAL, "Omega must be symmetric positive semidefinite");
+  if (k > 0) HIPCHK(hipMemcpyAsync(D(oC), hC, (size_t)k * k * 8, hipMemcpyHostToDevice, hs));
+  const double g1 = lambda1 * GMV;
+  if (ffo::launch_setup_batch(B, (const int64_t*)(Bd + onb64), n_max, k, m, ldk, F, D(oC), A, delta, N, s, q, g1,
+                              lambda2, lambda3, D(oK), D(odrs), D(odc), D(odrC), D(oar), D(ocv), D(oca), D(ocb), hs))
+    return fail(FFO_EDEVICE, "setup kernel launch failed");
+
+  ffo::LsShared S{};
+  S.B = (int)B; S.nr = nr; S.m = (int)m; S.k = (int)k; S.n_max = (int)n_max; S.ldk = ldk; S.nrp = nrp;
+  S.nr4 = (nr + 3) / 4;
+  S.g1 = g1; S.d = d; S.tol = opt.tol_rel_kkt; S.rho = opt.reflection; S.time_limit_s = opt.time_limit_s;
+  S.wall_hz = (double)wall_khz * 1e3; S.r_suff = opt.restart_suff; S.r_nec = opt.restart_nec;
+  S.r_art = opt.restart_art; S.max_iter = opt.max_iter;
+  S.KD = D(oK); S.KDT = D(oKT); S.drs = D(odrs); S.dc = D(odc); S.arisk = D(oar); S.drC = D(odrC);
+  S.alpha = alpha; S.ca = D(oca); S.cb = D(ocb); S.w0 = w0; S.L = m ? L : nullptr; S.U = m ? U : nullptr;
+  S.offs = (const int64_t*)(Bd + ooffs); S.nb = (const int32_t*)(Bd + onb32);
+  S.x = D(ov[0]); S.x0 = D(ov[1]); S.yC = D(ov[2]); S.yC0 = D(ov[3]); S.xbar = D(ov[4]); S.R = D(ov[5]);
+  S.Tx = D(ov[6]); S.TyC = D(ov[7]); S.gb = D(ov[8]); S.ga = D(ov[9]);
+  S.y = D(orow[0]); S.y0 = D(orow[1]); S.Ty = D(orow[2]); S.yh = D(orow[3]); S.yhT = D(orow[4]);
+  S.part = D(opart); S.inst = (ffo::LsInst*)(Bd + oinst); S.act = (int32_t*)(Bd + oact);
+  S.cnt = (int32_t*)(Bd + ocnt); S.tileA = (int32_t*)(Bd + otA); S.tileC = (int32_t*)(Bd + otC);
+  S.w_out = w_out; S.info = D(oinfo); S.status = (int32_t*)(Bd + ostat);
+  S.clock0 = (unsigned long long*)(Bd + oclk);
+  // (b, 1/a) pairs of an instance in LDS up to this many assets (else device memory)
+  S.lds_cap = (int)std::min<int64_t>(n_max, (int64_t)((lds_total - 16 * 12 * 8 - 512) / 16));
+  if (ffo::ls_launch_transpose(S, D(oKT), hs)) return fail(FFO_EDEVICE, "transpose kernel launch failed");
+  HIPCHK(fill(Bd + oinfo, (size_t)B * ffo::INFO_LEN * 8, 0u, hs));
+  HIPCHK(hipEventRecord(lb->ev[0], hs));
+  HIPCHK(hipStreamWaitEvent(ps, lb->ev[0], 0));
+
+  auto apply = [&](const LsTune& t) {
+    S.gpt = t.gpt; S.ch = t.ch; S.nchunk = (int)((n_max + t.ch - 1) / t.ch);
+  };
+  // ---- autotuning: time 16 plain iterations per candidate (coordinate descent over the
+  // per-instance threads, the chunk size and the groups per tile), then start afresh ----
+  int tuned_candidates = 0;
+  if (!tuned) {
+    const int cand_threads[3] = {256, 512, 1024}, cand_ch[3] = {128, 256, 512}, cand_gpt[3] = {1, 2, 4};
+    auto time_of = [&](const LsTune& t, float* ms) -> hipError_t {
+      apply(t);
+      hipError_t e = ls_start(S, t, gA, gC, hact, hcnt, ps);
+      if (e != hipSuccess) return e;
+      hipGraphExec_t ex = nullptr;
+      if ((e = ls_graph(S, t, gA, gC, 16, false, ps, &ex)) != hipSuccess) return e;
+      float best = 1e30f;
+      for (int rep = 0; rep < 2 && e == hipSuccess; ++rep) {
+        hipEventRecord(lb->ev[1], ps);
+        e = hipGraphLaunch(ex, ps);
+        hipEventRecord(lb->ev[2], ps);
+        if (e == hipSuccess) e = hipEventSynchronize(lb->ev[2]);
+        float t1 = 0.f;
+        hipEventElapsedTime(&t1, lb->ev[1], lb->ev[2]);
+        best = std::min(best, t1);
+      }
+      hipGraphExecDestroy(ex);
+      *ms = best;
+      ++tuned_candidates;
+      return e;
+    };
+    LsTune cur;
+    float cur_ms = 0.f;
+    HIPCHK(time_of(cur, &cur_ms));
+    for (int dim = 0; dim < 3; ++dim) {
+      const int* cand = dim == 0 ? cand_threads : dim == 1 ? cand_ch : cand_gpt;
+      for (int ci = 0; ci < 3; ++ci) {
+        LsTune t = cur;
+        int& f = dim == 0 ? t.threads : dim == 1 ? t.ch : t.gpt;
+        if (f == cand[ci]) continue;
+        f = cand[ci];
+        float ms = 0.f;
+        HIPCHK(time_of(t, &ms));
+        if (ms < 0.97f * cur_ms) { cur = t; cur_ms = ms; }
+      }
+    }
+    tu = cur;
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune[key] = tu;
+  }
+  apply(tu);
+
+  // ---- the solve: start, then replays of one checked graph ----
+  HIPCHK(hipEventRecord(ws->ev[1], ps));
+  HIPCHK(ls_start(S, tu, gA, gC, hact, hcnt, ps));
+  hipGraphExec_t ex = nullptr;
+  HIPCHK(ls_graph(S, tu, gA, gC, ce, true, ps, &ex));
+  const int64_t max_replays = (opt.max_iter + ce - 1) / ce + 1;
+  int64_t replays = 0;
+  hipError_t le = hipSuccess;
+  for (; replays < max_replays; ++replays) {
+    le = hipGraphLaunch(ex, ps);
+    if (le != hipSuccess) break;
+    le = hipMemcpyAsync(hcnt, S.cnt, 4, hipMemcpyDeviceToHost, ps);
+    if (le != hipSuccess) break;
+    le = hipStreamSynchronize(ps);
+    if (le != hipSuccess || hcnt[0] == 0) { ++replays; break; }
+  }
+  hipGraphExecDestroy(ex);
+  if (le != hipSuccess) return fail(FFO_EDEVICE, std::string("lockstep replay failed: ") + hipGetErrorString(le));
+  HIPCHK(hipEventRecord(ws->ev[2], ps));
+  double* hinfo = (double*)(Hb + hinfo_o);
+  int32_t* hstat = (int32_t*)(Hb + hstat_o);
+  HIPCHK(hipMemcpyAsync(hinfo, S.info, (size_t)B * ffo::INFO_LEN * 8, hipMemcpyDeviceToHost, ps));
+  HIPCHK(hipMemcpyAsync(hstat, S.status, (size_t)B * 4, hipMemcpyDeviceToHost, ps));
+  HIPCHK(hipStreamSynchronize(ps));
+  float ms_setup = 0.f, ms_iter = 0.f;
+  hipEventElapsedTime(&ms_setup, ws->ev[0], ws->ev[1]);
+  hipEventElapsedTime(&ms_iter, ws->ev[1], ws->ev[2]);
+  ffo_status worst = FFO_OK;
+  auto rank = [](ffo_status x) {
+    return x == FFO_EDEVICE ? 5 : x == FFO_NUMERIC ? 4 : x == FFO_INFEASIBLE ? 3 : x == FFO_TIMEOUT ? 2
+           : x == FFO_NOT_CONVERGED ? 1 : 0;
+  };
+  for (int64_t b = 0; b < B; ++b) {
+    const ffo_status st = status_of(hstat[b]);
+    fill_info(&infos[b], st, hinfo + (size_t)b * ffo::INFO_LEN, ms_setup, ms_iter);
+    if (rank(st) > rank(worst)) worst = st;
+  }
+  if (opt.verbose)
+    std::fprintf(stderr, "[ffo lockstep] B %lld replays %lld (x %d iterations) tune threads %d ch %d gpt %d "
+                         "(%d candidates timed) | setup+tune %.3f ms solve %.3f ms\n",
+                 (long long)B, (long long)replays, ce, tu.threads, tu.ch, tu.gpt, tuned_candidates, ms_setup,
+                 ms_iter);
+  if (worst == FFO_NOT_CONVERGED) g_err = "iteration limit reached for at least one instance";
+  else if (worst == FFO_TIMEOUT) g_err = "time limit reached for at least one instance";
+  else if (worst == FFO_NUMERIC) g_err = "NaN or Inf in an FP64 check of at least one instance";
+  else if (worst == FFO_EDEVICE) g_err = "an instance ended without a result";
+  return worst;
+}
+
 // ---- memory of the allocation-free entry point (ffo_solve_noalloc) ----
 // One static device array per GPU (each device holds its own copy of `scratch` for the
 // life of the process).  Host code never passes `scratch` itself to a kernel or a copy:
@@ -591,6 +900,7 @@ void ffo_default_options(ffo_options* o) {
   o->speculative = -1;
   o->breakpoint_lists = 1;
   o->infeasibility_check = 1;
+  o->batched_form = 0;
 }
 
 const char* ffo_last_error(void) { return g_err.c_str(); }
@@ -606,6 +916,12 @@ void ffo_release(void) {
       if (e) hipEventDestroy(e);
   }
   g_ws.clear();
+  for (auto& kv : g_ls) {
+    for (auto& e : kv.second.ev)
+      if (e) hipEventDestroy(e);
+    if (kv.second.ps) hipStreamDestroy(kv.second.ps);
+  }
+  g_ls.clear();
 }
 
 ffo_status ffo_solve(int64_t n, int64_t k, int64_t m, int64_t T, const double* alpha, const double* F,
@@ -847,6 +1163,16 @@ ffo_status ffo_solve_batched(int64_t B, const int64_t* n_b, int64_t n_max, int64
   if (!(opt.reflection >= 0.0 && opt.reflection <= 1.0)) return fail(FFO_EINVAL, "reflection must lie in [0, 1]");
   if (opt.precision != FFO_FP64 && opt.precision != FFO_FP32 && opt.precision != FFO_FP32_BF16K)
     return fail(FFO_EINVAL, "ffo_solve_batched takes FFO_FP64, FFO_FP32 or FFO_FP32_BF16K");
+  if (opt.batched_form < 0 || opt.batched_form > 2) return fail(FFO_EINVAL, "batched_form must be 0, 1 or 2");
+  {
+    const bool ls_ok = opt.precision == FFO_FP64 && m + k >= 1 && m + k <= 128 && B <= 65536 && n_max <= (1 << 22);
+    if (opt.batched_form == 2 && !ls_ok)
+      return fail(FFO_EINVAL, "the lockstep batched form needs FFO_FP64, 1 <= m + k <= 128, B <= 65536 and "
+                              "n_max <= 2^22");
+    if (opt.batched_form == 2 || (opt.batched_form == 0 && ls_ok))
+      return batched_lockstep(B, n_b, n_max, k, m, F, Omega, delta, A, offs, alpha, s, q, w0, L, U, d, GMV, lambda1,
+                              lambda2, lambda3, opt, stream, w_out, infos);
+  }
 
   int dev = 0;
   HIPCHK(hipGetDevice(&dev));

@@ -152,4 +152,64 @@ int launch_setup(int64_t n, int64_t k, int64_t m, int64_t P, int64_t Tp, int ldk
                  double* cvec, double* ca, double* cb, double* bF, double* crisk_dev,
                  void* stream);
 
+// ---------------------------------------------------------------------------------
+// Lockstep batched form (lockstep.hip): every unconverged instance advances by one
+// iteration per step; K~^T Y and K~ Xbar over the shared rows run as FP64 MFMA GEMMs.
+// Instances sit in "slots" 0..nact-1 (sorted by decreasing n_b, compacted at checks);
+// slots form groups of 16 (the MFMA tile height).
+struct LsInst {
+  double omega, eta, mu, r0, rprev, lam;   // primal weight, step, last multiplier, restart refs, power est.
+  double kvr;                              // power iteration: sum of squares of the row products
+  int64_t it, kk, restarts, checks;        // iterations, iterations since restart, restarts, checks
+  int32_t done, status;                    // status: DevStatus (DS_RUNNING while active)
+  int32_t mu_passes, pad;                  // multiplier passes in the last step (diagnostic)
+};
+
+struct LsShared {
+  int32_t B, nr, m, k, n_max, ldk, nrp;     // nrp: nr rounded up to 16
+  int32_t ch;                               // assets per K~ xbar chunk (multiple of 16)
+  int32_t gpt;                              // slot groups per K~^T y tile
+  int32_t nchunk;                           // ceil(n_max / ch)
+  int32_t lds_cap;                          // largest n_b whose (b, 1/a) pair fits in LDS
+  int32_t nr4;                              // ceil(nr / 4)
+  double g1, d, tol, rho, time_limit_s, wall_hz, r_suff, r_nec, r_art;
+  int64_t max_iter;
+  const double* KD;     // [nr][ldk]   K diag(dc) (rows unscaled), zero beyond n_max
+  const double* KDT;    // [n_max][nrp] its transpose, zero-padded rows
+  const double* drs;    // [B][nr]     per-instance row scales
+  const double *dc, *arisk, *drC;           // [n_max]
+  const double *alpha, *ca, *cb, *w0;       // packed [N]
+  const double *L, *U;                      // [B][m]
+  const int64_t* offs;                      // [B+1]
+  const int32_t* nb;                        // [B]
+  double *x, *x0, *yC, *yC0, *xbar, *R, *Tx, *TyC, *gb, *ga;   // packed [N]
+  double *y, *y0, *Ty, *yh, *yhT;           // [B][nrp]
+  double* part;                             // [nchunk][B][nrp] partial row sums (by slot)
+  LsInst* inst;                             // [B]
+  int32_t* act;                             // [B] slot -> instance
+  int32_t* cnt;                             // [0] nact, [1] K~^T y tiles, [2] K~ x tiles, [3] groups
+  int32_t* tileA;                           // [2][...] (asset block, first group)
+  int32_t* tileC;                           // [2][...] (chunk, group)
+  double* w_out;                            // packed [N]
+  double* info;                             // [B][INFO_LEN]
+  int32_t* status;                          // [B]
+  unsigned long long* clock0;               // wall clock at the start
+};
+
+// Lockstep launchers (lockstep.hip); each returns a hipError_t value (0 = success).
+// Phases of one iteration: kty (R = K~^T y over the rows), primal (per instance: prox,
+// multiplier, trade duals; check = 1: keep T(z) for the check), kx (partial K~ xbar),
+// dual (row duals; check = 1 keeps T(y)).  A check then runs kty on T(y), kx on T(x),
+// check (KKT, restarts, Halpern/restart apply) and compact.
+int ls_launch_init(const LsShared& S, void* stream);
+int ls_launch_kty(const LsShared& S, const double* yin, double* Rout, int grid, void* stream);
+int ls_launch_primal(const LsShared& S, int check, int threads, void* stream);
+int ls_launch_kx(const LsShared& S, const double* xin, int grid, void* stream);
+int ls_launch_dual(const LsShared& S, int mode, void* stream);
+int ls_launch_check(const LsShared& S, int threads, void* stream);
+int ls_launch_compact(const LsShared& S, void* stream);
+int ls_launch_power(const LsShared& S, int step, void* stream);   // step 0: rows, 1: assets
+int ls_launch_transpose(const LsShared& S, double* KDT, void* stream);
+size_t ls_primal_lds(const LsShared& S);
+
 }  // namespace ffo

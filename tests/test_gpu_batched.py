@@ -1,7 +1,10 @@
 """GPU parity of the batched form (ffo_solve_batched): every instance of a batch on one
 shared universe against the FP64 oracle on that instance alone, and against the plain
-single-instance solver.  Teams of one workgroup exchange through LDS; larger instances
-get teams of several workgroups (device-scope exchange), so both paths are covered."""
+single-instance solver.  Both batched forms are covered: the lockstep form (every
+unconverged instance advances one iteration per step, the products over the shared rows
+as FP64 matrix-core GEMMs, per-instance multipliers and checks, compaction) and the team
+form (teams of one workgroup exchange through LDS; larger instances get teams of several
+workgroups with a device-scope exchange)."""
 import numpy as np
 import pytest
 
@@ -54,21 +57,25 @@ def _check_against_oracle(batch, W, infos, b, tol, w_tol, obj_tol):
 BARS = {"fp64": (1e-10, 1e-5), "fp32": (1e-7, 2e-5)}
 
 
-@pytest.mark.parametrize("precision", ["fp64", "fp32"])
-def test_small_batch_matches_oracle(precision):
+FORMS = [("fp64", "lockstep"), ("fp64", "teams"), ("fp32", "teams")]
+
+
+@pytest.mark.parametrize("precision,form", FORMS)
+def test_small_batch_matches_oracle(precision, form):
     tol, w_tol = BARS[precision]
     batch = make_batch(8, 4, 6, seed=3, n_lo=40, n_hi=700)
-    W, infos = _solve_batched(batch, tol=tol, precision=precision)
+    W, infos = _solve_batched(batch, tol=tol, precision=precision, form=form)
     for b in range(8):
         _check_against_oracle(batch, W, infos, b, tol, w_tol=w_tol, obj_tol=1e-6)
 
 
-@pytest.mark.parametrize("precision", ["fp64", "fp32"])
-def test_multi_workgroup_teams_match_oracle(precision):
-    # n_b >= 512 is split over several workgroups when spare ones exist
+@pytest.mark.parametrize("precision,form", FORMS)
+def test_multi_workgroup_teams_match_oracle(precision, form):
+    # team form: n_b >= 512 is split over several workgroups when spare ones exist;
+    # lockstep form: several K~ x chunks per instance
     tol, w_tol = BARS[precision]
     batch = make_batch(3, 4, 6, seed=5, n_lo=900, n_hi=2600, n_max=2600)
-    W, infos = _solve_batched(batch, tol=tol, precision=precision)
+    W, infos = _solve_batched(batch, tol=tol, precision=precision, form=form)
     for b in range(3):
         _check_against_oracle(batch, W, infos, b, tol, w_tol=w_tol, obj_tol=1e-6)
 
@@ -91,10 +98,11 @@ def test_bf16_rows_batch_states_its_error():
         assert rel > 0.0   # the rounded rows do change the problem
 
 
-def test_batched_agrees_with_plain_solver():
+@pytest.mark.parametrize("form", ["lockstep", "teams"])
+def test_batched_agrees_with_plain_solver(form):
     ff = _gpu()
     batch = make_batch(5, 4, 6, seed=9, n_lo=100, n_hi=3000, n_max=3000)
-    W, infos = _solve_batched(batch, tol=1e-9)
+    W, infos = _solve_batched(batch, tol=1e-9, form=form)
     for b in range(5):
         inst = batch_instance(batch, b)
         Wp, ip = ff.solve_instance(inst, tol=1e-9)
@@ -103,21 +111,22 @@ def test_batched_agrees_with_plain_solver():
         assert np.max(np.abs(W[lo:hi] - Wp.cpu().numpy()[0])) <= 1e-5
 
 
-def test_single_asset_and_tiny_instances():
+@pytest.mark.parametrize("form", ["lockstep", "teams"])
+def test_single_asset_and_tiny_instances(form):
     batch = make_batch(4, 2, 1, seed=11, n_lo=1, n_hi=6, n_max=6)
-    W, infos = _solve_batched(batch, tol=1e-9)
+    W, infos = _solve_batched(batch, tol=1e-9, form=form)
     for b in range(4):
         _check_against_oracle(batch, W, infos, b, 1e-9, w_tol=1e-5, obj_tol=1e-8)
 
 
-@pytest.mark.parametrize("precision", ["fp64", "fp32"])
-def test_full_batch_256(precision):
+@pytest.mark.parametrize("precision,form", FORMS)
+def test_full_batch_256(precision, form):
     """The 256-instance batch (n_b log-uniform in [500, 8000], k = 40, m = 30): every
     instance converges; the three smallest against the oracle, the three largest against
     the plain solver."""
     ff = _gpu()
     batch = make_config(3)
-    W, infos = _solve_batched(batch, tol=1e-6, precision=precision)
+    W, infos = _solve_batched(batch, tol=1e-6, precision=precision, form=form)
     assert all(i.status == 0 and i.rel_kkt <= 1e-6 for i in infos)
     nb = np.asarray(batch["n_b"])
     for b in range(len(nb)):
@@ -133,3 +142,55 @@ def test_full_batch_256(precision):
         pb = normalize(inst)
         # two solves to relative KKT 1e-6 of the same instance: objectives within 4e-6
         assert abs(objective(pb, W[lo:hi][None, :]) - objective(pb, Wp.cpu().numpy())) <= 4e-6 * abs(ip.primal_obj)
+
+
+# ---------------------------------------------------------------- lockstep form only
+
+def test_lockstep_many_groups_with_compaction():
+    """40 instances (three slot groups) of uneven sizes: instances converge at different
+    checks and leave the slot list while the others continue; each against the oracle
+    (every fifth) and all against the team form."""
+    batch = make_batch(40, 4, 6, seed=13, n_lo=30, n_hi=1500, n_max=1500)
+    W, infos = _solve_batched(batch, tol=1e-10, form="lockstep")
+    Wt, it = _solve_batched(batch, tol=1e-10, form="teams")
+    iters = [i.iters for i in infos]
+    assert len(set(iters)) > 3, iters     # they did finish at different checks
+    offs = np.asarray(batch["offs"])
+    for b in range(40):
+        assert infos[b].status == 0 and infos[b].rel_kkt <= 1e-10, (b, infos[b])
+        assert np.max(np.abs(W[offs[b]:offs[b + 1]] - Wt[offs[b]:offs[b + 1]])) <= 1e-6
+    for b in range(0, 40, 5):
+        _check_against_oracle(batch, W, infos, b, 1e-10, w_tol=1e-5, obj_tol=1e-6)
+
+
+def test_lockstep_is_bitwise_repeatable():
+    """The lockstep form sums in a fixed order everywhere (no atomics): with the fixed
+    tunables of the deterministic mode two solves agree bit for bit."""
+    batch = make_batch(20, 4, 6, seed=17, n_lo=50, n_hi=900, n_max=900)
+    W1, i1 = _solve_batched(batch, tol=1e-8, form="lockstep", deterministic=True)
+    W2, i2 = _solve_batched(batch, tol=1e-8, form="lockstep", deterministic=True)
+    assert [i.iters for i in i1] == [i.iters for i in i2]
+    np.testing.assert_array_equal(W1, W2)
+
+
+def test_lockstep_instances_beyond_the_lds_pairs():
+    """n_b above the LDS capacity for the (b, 1/a) pairs (about 9,000 assets): those
+    instances keep them in device memory; against the plain solver."""
+    ff = _gpu()
+    batch = make_batch(3, 4, 6, seed=19, n_lo=9500, n_hi=12000, n_max=12000)
+    W, infos = _solve_batched(batch, tol=1e-8, form="lockstep")
+    for b in range(3):
+        inst = batch_instance(batch, b)
+        Wp, ip = ff.solve_instance(inst, tol=1e-8)
+        lo, hi = int(batch["offs"][b]), int(batch["offs"][b + 1])
+        assert infos[b].status == 0 and ip.status == 0
+        assert np.max(np.abs(W[lo:hi] - Wp.cpu().numpy()[0])) <= 1e-5
+
+
+def test_lockstep_many_rows():
+    """m + k = 100 rows (7 row blocks of 16, 25 MFMA steps per K~^T y tile) against the
+    oracle."""
+    batch = make_batch(6, 60, 40, seed=23, n_lo=200, n_hi=900, n_max=900)
+    W, infos = _solve_batched(batch, tol=1e-9, form="lockstep")
+    for b in range(6):
+        _check_against_oracle(batch, W, infos, b, 1e-9, w_tol=1e-5, obj_tol=1e-6)
