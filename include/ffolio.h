@@ -102,6 +102,15 @@ typedef struct {
                               float64 matrix-core GEMMs; FFO_FP64 only); 0 (default): the
                               lockstep form when it applies (FFO_FP64, m + k <= 128),
                               else the team form                                      */
+  int32_t autotune;        /* lockstep form only.  1 (default): on the first solve of a shape
+                              the library times a few tile sizes and kernel arrangements and
+                              keeps the fastest for later solves of that shape; -1: fixed
+                              defaults (the element passes as kernels of their own); 0:
+                              fixed defaults with the element passes fused into the two
+                              matrix-core kernels.  The choice changes
+                              speed and the rounding order of some sums, not the method;
+                              deterministic = 1 keeps the fixed defaults (-1 unless 0 is
+                              given)                                                   */
 } ffo_options;
 
 typedef struct {

@@ -37,7 +37,8 @@ class _Options(ctypes.Structure):
                 ("reflection", ctypes.c_double), ("workgroups", ctypes.c_int32),
                 ("verbose", ctypes.c_int32), ("deterministic", ctypes.c_int32),
                 ("speculative", ctypes.c_int32), ("breakpoint_lists", ctypes.c_int32),
-                ("infeasibility_check", ctypes.c_int32), ("batched_form", ctypes.c_int32)]
+                ("infeasibility_check", ctypes.c_int32), ("batched_form", ctypes.c_int32),
+                ("autotune", ctypes.c_int32)]
 
 
 class _Info(ctypes.Structure):
@@ -256,8 +257,8 @@ def solve_instance(inst: dict, **kw):
 
 def solve_batched(batch: dict, *, tol: float = 1e-6, max_iter: int = 1_000_000, time_limit_s: float = 360.0,
                   check_every: int = 64, restart=(0.2, 0.8, 0.36), reflection: float = 1.0, verbose: int = 0,
-                  precision="fp64", form="auto", deterministic: bool = False, raise_on_failure: bool = True,
-                  device=None, stream=None, out=None):
+                  precision="fp64", form="auto", deterministic: bool = False, autotune: int = 1,
+                  raise_on_failure: bool = True, device=None, stream=None, out=None):
     """Solve a batch of single-period instances on one shared universe (layout of
     ``synth.make_batch``: n_b, offs, n_max, F, Omega, delta, A shared; alpha, s, q, w0
     packed; L, U [B][m]).  ``form``: "lockstep" (every unconverged instance advances one
@@ -296,6 +297,7 @@ def solve_batched(batch: dict, *, tol: float = 1e-6, max_iter: int = 1_000_000, 
     o.verbose = int(verbose)
     o.precision = PRECISION[precision] if isinstance(precision, str) else int(precision)
     o.batched_form = {"auto": 0, "teams": 1, "lockstep": 2}[form]
+    o.autotune = int(autotune)
     o.deterministic = int(bool(deterministic))
     infos = (_Info * B)()
     st = torch.cuda.current_stream(dev) if stream is None else stream

@@ -534,7 +534,7 @@ ffo_status solve_impl(int64_t n, int64_t k, int64_t m, int64_t T, const double* 
 // threads of the per-instance workgroups.  They change the speed, and the rounding of
 // some sums, never the method.
 struct LsTune {
-  int gpt = 2, ch = 256, threads = 512;
+  int gpt = 2, ch = 256, threads = 512, fused = 0;
 };
 
 // Autotuned choices, cached per shape for the life of the process.
@@ -561,9 +561,15 @@ ffo_status ls_buffers(int dev, void* stream, LsBuffers** out) {
 // One lockstep iteration (check = 0) or the checked iteration and the check (check = 1)
 // on stream ps; grids from the tile capacities.
 hipError_t ls_enqueue_iter(const ffo::LsShared& S, const LsTune& tu, int gA, int gC, int check, hipStream_t ps) {
-  int e = ffo::ls_launch_kty(S, S.yh, S.R, gA, ps);
-  if (!e) e = ffo::ls_launch_primal(S, check, tu.threads, ps);
-  if (!e) e = ffo::ls_launch_kx(S, S.xbar, gC, ps);
+  const int gE = (int)std::min<int64_t>(2048, (S.N + ffo::LS_EW - 1) / ffo::LS_EW + S.B);
+  int e = 0;
+  if (tu.fused) {
+    e = ffo::ls_launch_step_fused(S, check, tu.threads, gA, gC, ps);
+  } else {
+    e = ffo::ls_launch_kty(S, S.yh, S.R, gA, ps);
+    if (!e) e = ffo::ls_launch_primal(S, check, tu.threads, gE, ps);
+    if (!e) e = ffo::ls_launch_kx(S, S.xbar, gC, ps);
+  }
   if (!e) e = ffo::ls_launch_dual(S, check ? 1 : 0, ps);
   if (check) {
     if (!e) e = ffo::ls_launch_kty(S, S.yhT, S.R, gA, ps);
@@ -596,8 +602,8 @@ hipError_t ls_start(const ffo::LsShared& S, const LsTune& tu, int gA, int gC, co
                     hipStream_t ps) {
   hipError_t e = hipMemcpyAsync(S.act, hact, (size_t)S.B * 4, hipMemcpyHostToDevice, ps);
   if (e != hipSuccess) return e;
-  hcnt[0] = S.B; hcnt[1] = hcnt[2] = hcnt[3] = 0;
-  if ((e = hipMemcpyAsync(S.cnt, hcnt, 16, hipMemcpyHostToDevice, ps)) != hipSuccess) return e;
+  hcnt[0] = S.B; hcnt[1] = hcnt[2] = hcnt[3] = hcnt[4] = 0;
+  if ((e = hipMemcpyAsync(S.cnt, hcnt, 20, hipMemcpyHostToDevice, ps)) != hipSuccess) return e;
   int r = ffo::ls_launch_init(S, ps);
   if (!r) r = ffo::ls_launch_compact(S, ps);
   for (int pw = 0; pw < 40 && !r; ++pw) {
@@ -638,7 +644,8 @@ ffo_status batched_lockstep(int64_t B, const int64_t* n_b, int64_t n_max, int64_
   // for the fixed defaults
   const auto key = std::make_tuple(B, n_max, (int64_t)nr, N, ce);
   LsTune tu;
-  bool tuned = opt.deterministic != 0;
+  if (opt.autotune == 0) tu.fused = 1;
+  bool tuned = opt.deterministic != 0 || opt.autotune <= 0;
   if (!tuned) {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     auto it = g_tune.find(key);
@@ -648,6 +655,8 @@ ffo_status batched_lockstep(int64_t B, const int64_t* n_b, int64_t n_max, int64_
   const int64_t Gmax = (B + 15) / 16;
   const int64_t nab = (n_max + 63) / 64;
   const int64_t maxA = nab * Gmax, nchunk_max = (n_max + 127) / 128, maxC = Gmax * nchunk_max;
+  int64_t maxE = 0;
+  for (int64_t b = 0; b < B; ++b) maxE += (n_b[b] + ffo::LS_EW - 1) / ffo::LS_EW;
   const int gA = (int)std::min<int64_t>(maxA, 2048), gC = (int)std::min<int64_t>(maxC, 2048);
 
   // ---- workspace ----
@@ -662,8 +671,10 @@ ffo_status batched_lockstep(int64_t B, const int64_t* n_b, int64_t n_max, int64_
   size_t orow[5];
   for (auto& o : orow) o = carve((size_t)B * nrp, 8);
   const size_t opart = carve((size_t)nchunk_max * B * nrp, 8);
-  const size_t oinst = carve(B, sizeof(ffo::LsInst)), oact = carve(B, 4), ocnt = carve(4, 4);
-  const size_t otA = carve((size_t)3 * maxA, 4), otC = carve((size_t)2 * maxC, 4);
+  const size_t oinst = carve(B, sizeof(ffo::LsInst)), oact = carve(B, 4), ocnt = carve(8, 4);
+  const size_t otA = carve((size_t)3 * maxA, 4), otC = carve((size_t)3 * maxC, 4);
+  const size_t otE = carve((size_t)2 * maxE, 4), oeoff = carve(B, 4), oest = carve((size_t)8 * maxE, 8);
+  const size_t oest2 = carve((size_t)8 * nab * B, 8);
   const size_t oinfo = carve((size_t)B * ffo::INFO_LEN, 8), ostat = carve(B, 4), oclk = carve(1, 8), oflag = carve(1, 4);
   const size_t total = off;
   size_t hoff = 0;
@@ -671,7 +682,7 @@ ffo_status batched_lockstep(int64_t B, const int64_t* n_b, int64_t n_max, int64_
   const size_t kk2 = (size_t)std::max<int64_t>(k * k, 1);
   const size_t hOm_o = hcarve(kk2 * 8), hC_o = hcarve(kk2 * 8), hW_o = hcarve(2 * kk2 * 8), hflag_o = hcarve(4);
   const size_t hnb_o = hcarve((size_t)B * 8), hnb32_o = hcarve((size_t)B * 4), hoffs_o = hcarve((size_t)(B + 1) * 8);
-  const size_t hact_o = hcarve((size_t)B * 4), hcnt_o = hcarve(16), hinfo_o = hcarve((size_t)B * ffo::INFO_LEN * 8);
+  const size_t hact_o = hcarve((size_t)B * 4), hcnt_o = hcarve(32), hinfo_o = hcarve((size_t)B * ffo::INFO_LEN * 8);
   const size_t hstat_o = hcarve((size_t)B * 4);
   Workspace* ws = nullptr;
   if (ffo_status st = get_workspace(dev, stream, total, hoff, &ws, 3)) return st;
@@ -729,6 +740,8 @@ ffo_status batched_lockstep(int64_t B, const int64_t* n_b, int64_t n_max, int64_
   S.y = D(orow[0]); S.y0 = D(orow[1]); S.Ty = D(orow[2]); S.yh = D(orow[3]); S.yhT = D(orow[4]);
   S.part = D(opart); S.inst = (ffo::LsInst*)(Bd + oinst); S.act = (int32_t*)(Bd + oact);
   S.cnt = (int32_t*)(Bd + ocnt); S.tileA = (int32_t*)(Bd + otA); S.tileC = (int32_t*)(Bd + otC);
+  S.tileE = (int32_t*)(Bd + otE); S.eoff = (int32_t*)(Bd + oeoff); S.estat = D(oest); S.N = N;
+  S.estat2 = D(oest2);
   S.w_out = w_out; S.info = D(oinfo); S.status = (int32_t*)(Bd + ostat);
   S.clock0 = (unsigned long long*)(Bd + oclk);
   // (b, 1/a) pairs of an instance in LDS up to this many assets (else device memory)
@@ -738,15 +751,16 @@ ffo_status batched_lockstep(int64_t B, const int64_t* n_b, int64_t n_max, int64_
   HIPCHK(hipEventRecord(lb->ev[0], hs));
   HIPCHK(hipStreamWaitEvent(ps, lb->ev[0], 0));
 
-  auto apply = [&](const LsTune& t) {
+  auto apply = [&](LsTune& t) {
+    if (t.fused) t.ch = 128;   // the fused K~ x kernel runs 128-asset chunks
     S.gpt = t.gpt; S.ch = t.ch; S.nchunk = (int)((n_max + t.ch - 1) / t.ch);
   };
   // ---- autotuning: time 16 plain iterations per candidate (coordinate descent over the
   // per-instance threads, the chunk size and the groups per tile), then start afresh ----
   int tuned_candidates = 0;
   if (!tuned) {
-    const int cand_threads[3] = {256, 512, 1024}, cand_ch[3] = {128, 256, 512}, cand_gpt[3] = {1, 2, 4};
-    auto time_of = [&](const LsTune& t, float* ms) -> hipError_t {
+    const int cand_threads[3] = {256, 512, 512}, cand_ch[3] = {128, 256, 256}, cand_gpt[3] = {1, 2, 4};
+    auto time_of = [&](LsTune t, float* ms) -> hipError_t {
       apply(t);
       hipError_t e = ls_start(S, t, gA, gC, hact, hcnt, ps);
       if (e != hipSuccess) return e;
@@ -770,16 +784,17 @@ ffo_status batched_lockstep(int64_t B, const int64_t* n_b, int64_t n_max, int64_
     LsTune cur;
     float cur_ms = 0.f;
     HIPCHK(time_of(cur, &cur_ms));
-    for (int dim = 0; dim < 3; ++dim) {
-      const int* cand = dim == 0 ? cand_threads : dim == 1 ? cand_ch : cand_gpt;
+    const int cand_fused[3] = {0, 1, 1};
+    for (int dim = 0; dim < 4; ++dim) {
+      const int* cand = dim == 0 ? cand_fused : dim == 1 ? cand_threads : dim == 2 ? cand_ch : cand_gpt;
       for (int ci = 0; ci < 3; ++ci) {
         LsTune t = cur;
-        int& f = dim == 0 ? t.threads : dim == 1 ? t.ch : t.gpt;
+        int& f = dim == 0 ? t.fused : dim == 1 ? t.threads : dim == 2 ? t.ch : t.gpt;
         if (f == cand[ci]) continue;
         f = cand[ci];
         float ms = 0.f;
         HIPCHK(time_of(t, &ms));
-        if (ms < 0.97f * cur_ms) { cur = t; cur_ms = ms; }
+        if (ms < 0.95f * cur_ms) { cur = t; cur_ms = ms; }
       }
     }
     tu = cur;
@@ -826,10 +841,10 @@ ffo_status batched_lockstep(int64_t B, const int64_t* n_b, int64_t n_max, int64_
     if (rank(st) > rank(worst)) worst = st;
   }
   if (opt.verbose)
-    std::fprintf(stderr, "[ffo lockstep] B %lld replays %lld (x %d iterations) tune threads %d ch %d gpt %d "
+    std::fprintf(stderr, "[ffo lockstep] B %lld replays %lld (x %d iterations) tune fused %d threads %d ch %d gpt %d "
                          "(%d candidates timed) | setup+tune %.3f ms solve %.3f ms\n",
-                 (long long)B, (long long)replays, ce, tu.threads, tu.ch, tu.gpt, tuned_candidates, ms_setup,
-                 ms_iter);
+                 (long long)B, (long long)replays, ce, tu.fused, tu.threads, tu.ch, tu.gpt, tuned_candidates,
+                 ms_setup, ms_iter);
   if (worst == FFO_NOT_CONVERGED) g_err = "iteration limit reached for at least one instance";
   else if (worst == FFO_TIMEOUT) g_err = "time limit reached for at least one instance";
   else if (worst == FFO_NUMERIC) g_err = "NaN or Inf in an FP64 check of at least one instance";
@@ -901,6 +916,7 @@ void ffo_default_options(ffo_options* o) {
   o->breakpoint_lists = 1;
   o->infeasibility_check = 1;
   o->batched_form = 0;
+  o->autotune = 1;
 }
 
 const char* ffo_last_error(void) { return g_err.c_str(); }
@@ -1164,6 +1180,7 @@ ffo_status ffo_solve_batched(int64_t B, const int64_t* n_b, int64_t n_max, int64
   if (opt.precision != FFO_FP64 && opt.precision != FFO_FP32 && opt.precision != FFO_FP32_BF16K)
     return fail(FFO_EINVAL, "ffo_solve_batched takes FFO_FP64, FFO_FP32 or FFO_FP32_BF16K");
   if (opt.batched_form < 0 || opt.batched_form > 2) return fail(FFO_EINVAL, "batched_form must be 0, 1 or 2");
+  if (opt.autotune < -1 || opt.autotune > 1) return fail(FFO_EINVAL, "autotune must be -1, 0 or 1");
   {
     const bool ls_ok = opt.precision == FFO_FP64 && m + k >= 1 && m + k <= 128 && B <= 65536 && n_max <= (1 << 22);
     if (opt.batched_form == 2 && !ls_ok)

@@ -157,6 +157,8 @@ int launch_setup(int64_t n, int64_t k, int64_t m, int64_t P, int64_t Tp, int ldk
 // iteration per step; K~^T Y and K~ Xbar over the shared rows run as FP64 MFMA GEMMs.
 // Instances sit in "slots" 0..nact-1 (sorted by decreasing n_b, compacted at checks);
 // slots form groups of 16 (the MFMA tile height).
+constexpr int LS_EW = 1024;   // assets per element tile of the lockstep form's elementwise passes
+
 struct LsInst {
   double omega, eta, mu, r0, rprev, lam;   // primal weight, step, last multiplier, restart refs, power est.
   double kvr;                              // power iteration: sum of squares of the row products
@@ -172,6 +174,7 @@ struct LsShared {
   int32_t nchunk;                           // ceil(n_max / ch)
   int32_t lds_cap;                          // largest n_b whose (b, 1/a) pair fits in LDS
   int32_t nr4;                              // ceil(nr / 4)
+  int64_t N;                                // total assets of the batch
   double g1, d, tol, rho, time_limit_s, wall_hz, r_suff, r_nec, r_art;
   int64_t max_iter;
   const double* KD;     // [nr][ldk]   K diag(dc) (rows unscaled), zero beyond n_max
@@ -187,9 +190,14 @@ struct LsShared {
   double* part;                             // [nchunk][B][nrp] partial row sums (by slot)
   LsInst* inst;                             // [B]
   int32_t* act;                             // [B] slot -> instance
-  int32_t* cnt;                             // [0] nact, [1] K~^T y tiles, [2] K~ x tiles, [3] groups
+  int32_t* cnt;                             // [0] nact, [1] K~^T y tiles, [2] K~ x tiles, [3] groups,
+                                            // [4] element tiles
   int32_t* tileA;                           // [2][...] (asset block, first group)
-  int32_t* tileC;                           // [2][...] (chunk, group)
+  int32_t* tileC;                           // [3][...] (chunk, first group, end group)
+  int32_t* tileE;                           // [2][...] (slot, element chunk) of the elementwise passes
+  int32_t* eoff;                            // [B] first element tile of each slot
+  double* estat;                            // [tiles][8] per-tile sums of the first pass
+  double* estat2;                           // [64-asset blocks][B][8] the same sums, fused form
   double* w_out;                            // packed [N]
   double* info;                             // [B][INFO_LEN]
   int32_t* status;                          // [B]
@@ -197,15 +205,19 @@ struct LsShared {
 };
 
 // Lockstep launchers (lockstep.hip); each returns a hipError_t value (0 = success).
-// Phases of one iteration: kty (R = K~^T y over the rows), primal (per instance: prox,
-// multiplier, trade duals; check = 1: keep T(z) for the check), kx (partial K~ xbar),
-// dual (row duals; check = 1 keeps T(y)).  A check then runs kty on T(y), kx on T(x),
+// Phases of one iteration: kty (R = K~^T y over the rows), primal (prox inputs over
+// element tiles, the multiplier per instance, then T(x), xbar and the trade duals over
+// element tiles; check = 1: keep T(z) for the check), kx (partial K~ xbar), dual (row
+// duals; check = 1 keeps T(y)).  A check then runs kty on T(y), kx on T(x),
 // check (KKT, restarts, Halpern/restart apply) and compact.
 int ls_launch_init(const LsShared& S, void* stream);
 int ls_launch_kty(const LsShared& S, const double* yin, double* Rout, int grid, void* stream);
-int ls_launch_primal(const LsShared& S, int check, int threads, void* stream);
+int ls_launch_primal(const LsShared& S, int check, int threads, int gridE, void* stream);
 int ls_launch_kx(const LsShared& S, const double* xin, int grid, void* stream);
 int ls_launch_dual(const LsShared& S, int mode, void* stream);
+// Fused form of kty + primal + kx: prox inputs in the K~^T y epilogue, the multiplier,
+// then T(x), xbar, trade duals and Halpern in the K~ xbar staging loop.
+int ls_launch_step_fused(const LsShared& S, int check, int threads, int gA, int gC, void* stream);
 int ls_launch_check(const LsShared& S, int threads, void* stream);
 int ls_launch_compact(const LsShared& S, void* stream);
 int ls_launch_power(const LsShared& S, int step, void* stream);   // step 0: rows, 1: assets

@@ -78,21 +78,33 @@ constexpr int RED_DOUBLES = 16 * 12;   // bsum scratch (up to 16 waves x 12 valu
 // point right of the root lands left of it.  The start is mu_prev (the previous
 // iteration's multiplier), whose S and slope the caller summed in its first pass.
 // sb / sa: signed b and 1/a (LDS or device memory).  Returns the number of passes.
-__device__ int l1_multiplier(const double* sb, const double* sa, int n, double S0, double A0, double C0,
-                             double mp, double Sp, double Ap, double Cp, double* red, double& mu) {
+template <class PT>
+__device__ int l1_multiplier(PT sb, PT sa, int n, double S0, double A0, double C0, double mp, double Sp, double Ap,
+                             double Cp, double* red, double& mu) {
   mu = 0.0;
   if (!(S0 > 1.0)) return 0;
   double m, Sm, Am, Cm;
   if (mp > 0.0 && Ap > 0.0) { m = mp; Sm = Sp; Am = Ap; Cm = Cp; }
   else { m = 0.0; Sm = S0; Am = A0; Cm = C0; }
+  const int nt = blockDim.x;
   int passes = 0;
   for (; passes < 100; ++passes) {
     double mn = m + (Sm - 1.0) / Am;
     if (!(mn > 0.0)) mn = 0.0;
     double v[3] = {0.0, 0.0, 0.0};
-    for (int i = threadIdx.x; i < n; i += blockDim.x) {
-      const double ab = fabs(sb[i]);
-      if (ab > mn) { const double ia = sa[i]; v[0] = fma(ab - mn, ia, v[0]); v[1] += ia; v[2] += 1.0; }
+    for (int i0 = threadIdx.x; i0 < n; i0 += 4 * nt) {   // four pairs per thread and step
+      double bq[4], aq[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int i = i0 + u * nt;
+        bq[u] = i < n ? sb[i] : 0.0;
+        aq[u] = i < n ? sa[i] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const double ab = fabs(bq[u]);
+        if (ab > mn) { v[0] = fma(ab - mn, aq[u], v[0]); v[1] += aq[u]; v[2] += 1.0; }
+      }
     }
     bsum<3>(v, red);
     const bool from_left = Sm >= 1.0;
@@ -103,6 +115,8 @@ __device__ int l1_multiplier(const double* sb, const double* sa, int n, double S
   mu = m;
   return passes + 1;
 }
+
+typedef __attribute__((address_space(3))) double ldbl;
 
 // ---------------------------------------------------------------------------------
 // Initial state: x = w0 / dc (w0 in every instance, paper Section 4.1), duals zero, the
@@ -142,6 +156,7 @@ __global__ __launch_bounds__(256) void k_init(LsShared S) {
 //   K~ x tiles: (chunk of ch assets, group) for every chunk the group's largest
 //     instance reaches.
 constexpr int CT = 1024;
+constexpr int EW = LS_EW;   // assets per element tile (256 threads x 4)
 
 __device__ int block_excl_scan(int v, int* sh, int& total) {
   const int t = threadIdx.x;
@@ -203,34 +218,72 @@ __global__ __launch_bounds__(CT) void k_compact(LsShared S) {
     tA += tot;
     __syncthreads();
   }
-  // K~ x tiles
+  // K~ x tiles: chunks of ch assets, runs of gpt groups that reach the chunk
+  const int nchk = G > 0 ? (nfirst(0) + S.ch - 1) / S.ch : 0;
   int tC = 0;
-  for (int g0 = 0; g0 < G; g0 += CT) {
-    const int g = g0 + t;
-    const int nc = g < G ? (nfirst(g) + S.ch - 1) / S.ch : 0;
+  for (int c0 = 0; c0 < nchk; c0 += CT) {
+    const int c = c0 + t;
+    int Gc = 0, nt = 0;
+    if (c < nchk) {
+      int lo = 0, hi = G;
+      while (lo < hi) {
+        const int mid = (lo + hi) / 2;
+        if (nfirst(mid) > c * S.ch) lo = mid + 1; else hi = mid;
+      }
+      Gc = lo;
+      nt = (Gc + S.gpt - 1) / S.gpt;
+    }
     int tot = 0;
-    const int pos = block_excl_scan(nc, sh, tot);
-    for (int q = 0; q < nc; ++q) {
-      S.tileC[2 * (tC + pos + q)] = q;
-      S.tileC[2 * (tC + pos + q) + 1] = g;
+    const int pos = block_excl_scan(nt, sh, tot);
+    for (int q = 0; q < nt; ++q) {
+      const int e = tC + pos + q;
+      S.tileC[3 * e] = c;
+      S.tileC[3 * e + 1] = q * S.gpt;
+      S.tileC[3 * e + 2] = min(Gc, (q + 1) * S.gpt);
     }
     tC += tot;
     __syncthreads();
   }
-  if (t == 0) { S.cnt[0] = nact; S.cnt[1] = tA; S.cnt[2] = tC; S.cnt[3] = G; }
+  // element tiles of the elementwise passes: (slot, chunk of EW assets), slot-major
+  int tE = 0;
+  for (int s0 = 0; s0 < nact; s0 += CT) {
+    const int sl = s0 + t;
+    const int ne = sl < nact ? (S.nb[S.act[sl]] + EW - 1) / EW : 0;
+    int tot = 0;
+    const int pos = block_excl_scan(ne, sh, tot);
+    if (sl < nact) S.eoff[sl] = tE + pos;
+    for (int q = 0; q < ne; ++q) {
+      S.tileE[2 * (tE + pos + q)] = sl;
+      S.tileE[2 * (tE + pos + q) + 1] = q;
+    }
+    tE += tot;
+    __syncthreads();
+  }
+  if (t == 0) { S.cnt[0] = nact; S.cnt[1] = tA; S.cnt[2] = tC; S.cnt[3] = G; S.cnt[4] = tE; }
 }
 
 // ---------------------------------------------------------------------------------
 // R[b][i] = sum_r yin[b][r] KD[r][i] for the slots of each tile's groups and the tile's
 // 64 assets (four waves of 16).  The wave keeps its 16 columns of KD in registers and
 // runs over the tile's groups; per group one MFMA per 4 rows.
-template <int NR4>
+constexpr int GPT_MAX = 4;
+
+// PRE: instead of R, the epilogue forms the prox inputs of the primal step from R (as
+// k_pre does) and writes per-(asset block, slot) sums of S and its slope to estat2.
+template <int NR4, bool PRE>
 __global__ __launch_bounds__(256) void k_kty(LsShared S, const double* __restrict__ yin, double* __restrict__ Rout) {
+  extern __shared__ double ys[];   // [gpt * 16][nrp + 1] dual rows of the tile's slots
+  __shared__ int s_b[GPT_MAX * 16], s_n[GPT_MAX * 16];
+  __shared__ int64_t s_o[GPT_MAX * 16];
+  __shared__ double s_tau[GPT_MAX * 16], s_mp[GPT_MAX * 16];
+  __shared__ double s_st[4][16][6];   // per wave and slot of the group: the six sums
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int nact = S.cnt[0], ntile = S.cnt[1];
   const int rq = lane >> 4, cl = lane & 15;
+  const int ld = S.nrp + 1;
   for (int tile = blockIdx.x; tile < ntile; tile += gridDim.x) {
     const int ab = S.tileA[3 * tile], g0 = S.tileA[3 * tile + 1], g1 = S.tileA[3 * tile + 2];
+    const int ns = (g1 - g0) * 16;
     const int i = ab * 64 + wave * 16 + cl;
     double kb[NR4];
 #pragma unroll
@@ -238,26 +291,92 @@ __global__ __launch_bounds__(256) void k_kty(LsShared S, const double* __restric
       const int r = 4 * q + rq;
       kb[q] = (q < S.nr4 && r < S.nr && i < S.n_max) ? S.KD[(size_t)r * S.ldk + i] : 0.0;
     }
+    double dci = 1.0, drci = 1.0, ari = 1.0;
+    if (PRE && i < S.n_max) { dci = S.dc[i]; drci = S.drC[i]; ari = S.arisk[i]; }
+    if (threadIdx.x < ns) {
+      const int sl = 16 * g0 + threadIdx.x;
+      const int b = sl < nact ? S.act[sl] : -1;
+      s_b[threadIdx.x] = b;
+      s_n[threadIdx.x] = b >= 0 ? S.nb[b] : 0;
+      s_o[threadIdx.x] = b >= 0 ? S.offs[b] : 0;
+      if (PRE) {
+        s_tau[threadIdx.x] = b >= 0 ? S.inst[b].eta / S.inst[b].omega : 1.0;
+        s_mp[threadIdx.x] = b >= 0 ? S.inst[b].mu : 0.0;
+      }
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < ns * S.nrp; e += blockDim.x) {
+      const int sl = e / S.nrp, r = e - sl * S.nrp;
+      const int b = s_b[sl];
+      ys[sl * ld + r] = (b >= 0 && r < S.nr) ? yin[(size_t)b * S.nrp + r] : 0.0;
+    }
+    __syncthreads();
     for (int g = g0; g < g1; ++g) {
-      const int sa = 16 * g + cl;               // A-operand row: slot
-      const int ba = sa < nact ? S.act[sa] : -1;
-      const double* yrow = yin + (size_t)(ba < 0 ? 0 : ba) * S.nrp;
+      const double* yr = ys + ((g - g0) * 16 + cl) * ld;   // A-operand row: slot 16 g + cl
       d4 acc = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
       for (int q = 0; q < NR4; ++q) {
-        const int r = 4 * q + rq;
-        const double a = (ba >= 0 && q < S.nr4 && r < S.nr) ? yrow[r] : 0.0;
+        const double a = q < S.nr4 ? yr[4 * q + rq] : 0.0;
         acc = mfma(a, kb[q], acc);
+      }
+      if (!PRE) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int sl = (g - g0) * 16 + 4 * j + rq;   // output row: slot 16 g + 4 j + rq
+          if (i < s_n[sl]) Rout[s_o[sl] + i] = acc[j];
+        }
+        continue;
+      }
+      double yc[4], xv[4], al[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int sl = (g - g0) * 16 + 4 * j + rq;
+        const bool in = i < s_n[sl];
+        const int64_t oi = s_o[sl] + i;
+        yc[j] = in ? S.yC[oi] : 0.0;
+        xv[j] = in ? S.x[oi] : 0.0;
+        al[j] = in ? S.alpha[oi] : 0.0;
       }
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
-        const int s = 16 * g + 4 * j + rq;
-        if (s < nact) {
-          const int b = S.act[s];
-          if (i < S.nb[b]) Rout[S.offs[b] + i] = acc[j];
+        const int sl = (g - g0) * 16 + 4 * j + rq;
+        double st[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+        if (i < s_n[sl]) {
+          const double tau = s_tau[sl], mp = s_mp[sl];
+          const double Ry = acc[j] + dci * drci * yc[j];
+          const double v = xv[j] - tau * Ry;
+          const double a = 1.0 / (tau * dci * dci) + ari;
+          const double bv = v / (tau * dci) + al[j];
+          const double ia = 1.0 / a, abv = fabs(bv);
+          const int64_t oi = s_o[sl] + i;
+          S.gb[oi] = bv;
+          S.ga[oi] = ia;
+          if (abv > 0.0) { st[0] = abv * ia; st[1] = ia; st[2] = 1.0; }
+          if (abv > mp) { st[3] = (abv - mp) * ia; st[4] = ia; st[5] = 1.0; }
+        }
+        // sum over the 16 assets of this wave (lanes with the same rq), fixed order
+#pragma unroll
+        for (int q = 0; q < 6; ++q) {
+          double x = st[q];
+          x += __shfl_xor(x, 1, 64);
+          x += __shfl_xor(x, 2, 64);
+          x += __shfl_xor(x, 4, 64);
+          x += __shfl_xor(x, 8, 64);
+          if (cl == 0) s_st[wave][4 * j + rq][q] = x;
         }
       }
+      __syncthreads();
+      if (threadIdx.x < 16 * 6) {
+        const int sl16 = threadIdx.x / 6, q = threadIdx.x % 6;
+        const int s = 16 * g + sl16;
+        if (s < nact) {
+          const double t = s_st[0][sl16][q] + s_st[1][sl16][q] + s_st[2][sl16][q] + s_st[3][sl16][q];
+          S.estat2[((size_t)ab * S.B + s) * 8 + q] = t;
+        }
+      }
+      __syncthreads();
     }
+    __syncthreads();
   }
 }
 
@@ -265,110 +384,241 @@ __global__ __launch_bounds__(256) void k_kty(LsShared S, const double* __restric
 // Partial row sums part[c][s][r] = sum_{i in chunk c, i < n_b} KD[r][i] xin[b][i] for the
 // 16 slots s of the tile's group; wave w owns row block w (16 rows), the chunk's inputs
 // are staged in LDS (row stride ch + 1).
-template <int NRB>
-__global__ __launch_bounds__(64 * NRB) void k_kx(LsShared S, const double* __restrict__ xin) {
-  extern __shared__ double xs[];   // [16][ch + 1]
+// POST: the staged inputs are formed here from the prox inputs (as k_post does): T(x),
+// xbar = 2 T(x) - x (the A operand), the trade duals and the Halpern step, or (check)
+// T(x), T(y_C) kept.
+template <int NRB, int CH, bool POST>
+__global__ __launch_bounds__(64 * NRB) void k_kx(LsShared S, const double* __restrict__ xin, int check) {
+  __shared__ double xs[16 * (CH + 1)];   // the group's inputs over the chunk, row stride CH + 1
+  __shared__ int64_t s_off[16];
+  __shared__ int s_n[16];
+  __shared__ double s_sig[16], s_mu[16], s_a1[16], s_a0[16];
   const int lane = threadIdx.x & 63, rb = threadIdx.x >> 6;
   const int nact = S.cnt[0], ntile = S.cnt[2];
-  const int ch = S.ch, ld = ch + 1;
+  constexpr int ld = CH + 1;
   const int rq = lane >> 4, cl = lane & 15;
+  const int r = rb * 16 + cl;   // B-operand column: row of KD
+  const int nt = blockDim.x;
+  const double rho = S.rho;
   for (int tile = blockIdx.x; tile < ntile; tile += gridDim.x) {
-    const int c = S.tileC[2 * tile], g = S.tileC[2 * tile + 1];
-    const int i0 = c * ch;
-    for (int e = threadIdx.x; e < 16 * ch; e += blockDim.x) {
-      const int sl = e / ch, ii = e - sl * ch;
-      const int s = 16 * g + sl;
-      double v = 0.0;
-      if (s < nact) {
-        const int b = S.act[s];
-        if (i0 + ii < S.nb[b]) v = xin[S.offs[b] + i0 + ii];
-      }
-      xs[sl * ld + ii] = v;
-    }
-    __syncthreads();
-    d4 acc = {0.0, 0.0, 0.0, 0.0};
-    const int r = rb * 16 + cl;   // B-operand column: row of KD
-    const int iend = min(ch, S.n_max - i0);
-    for (int kk = 0; kk < iend; kk += 4) {
-      const int ii = kk + rq;
-      const double a = ii < iend ? xs[cl * ld + ii] : 0.0;      // A[slot cl][asset rq]
-      const double bo = ii < iend ? S.KDT[(size_t)(i0 + ii) * S.nrp + r] : 0.0;
-      acc = mfma(a, bo, acc);
-    }
+    const int c = S.tileC[3 * tile], g0 = S.tileC[3 * tile + 1], g1 = S.tileC[3 * tile + 2];
+    const int i0 = c * CH;
+    // this wave's block of 16 rows over the chunk, kept in registers for all groups
+    double bk[CH / 4];
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int s = 16 * g + 4 * j + rq;
-      if (s < nact) S.part[((size_t)c * S.B + s) * S.nrp + rb * 16 + cl] = acc[j];
+    for (int q = 0; q < CH / 4; ++q) {
+      const int ii = i0 + 4 * q + rq;
+      bk[q] = ii < S.n_max ? S.KDT[(size_t)ii * S.nrp + r] : 0.0;
     }
-    __syncthreads();
+    for (int g = g0; g < g1; ++g) {
+      if (threadIdx.x < 16) {
+        const int s = 16 * g + threadIdx.x;
+        const int b = s < nact ? S.act[s] : -1;
+        s_n[threadIdx.x] = b >= 0 ? S.nb[b] : 0;
+        s_off[threadIdx.x] = b >= 0 ? S.offs[b] : 0;
+        if (POST && b >= 0) {
+          const LsInst I = S.inst[b];
+          const double kk = (double)I.kk;
+          s_sig[threadIdx.x] = I.eta * I.omega;
+          s_mu[threadIdx.x] = I.mu;
+          s_a1[threadIdx.x] = (kk + 1.0) / (kk + 2.0);
+          s_a0[threadIdx.x] = 1.0 / (kk + 2.0);
+        }
+      }
+      __syncthreads();
+      if (!POST) {
+        for (int e = threadIdx.x; e < 16 * CH; e += nt) {
+          const int sl = e / CH, ii = e - sl * CH;
+          xs[sl * ld + ii] = i0 + ii < s_n[sl] ? xin[s_off[sl] + i0 + ii] : 0.0;
+        }
+      } else {
+        for (int e0 = threadIdx.x; e0 < 16 * CH; e0 += 4 * nt) {
+          double bvv[4], iav[4], dcv[4], xo[4], drc[4], yco[4], w0v[4], cav[4], cbv[4], x0v[4], y0v[4];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const int e = e0 + u * nt;
+            const int sl = e / CH, ii = e - sl * CH;
+            const bool in = e < 16 * CH && i0 + ii < s_n[sl];
+            const int64_t oi = in ? s_off[sl] + i0 + ii : 0;
+            const int i = i0 + ii;
+            bvv[u] = in ? S.gb[oi] : 0.0;
+            iav[u] = in ? S.ga[oi] : 0.0;
+            dcv[u] = in ? S.dc[i] : 1.0;
+            xo[u] = in ? S.x[oi] : 0.0;
+            drc[u] = in ? S.drC[i] : 1.0;
+            yco[u] = in ? S.yC[oi] : 0.0;
+            w0v[u] = in ? S.w0[oi] : 0.0;
+            cav[u] = in ? S.ca[oi] : 0.0;
+            cbv[u] = in ? S.cb[oi] : 0.0;
+            x0v[u] = in && !check ? S.x0[oi] : 0.0;
+            y0v[u] = in && !check ? S.yC0[oi] : 0.0;
+          }
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const int e = e0 + u * nt;
+            if (e >= 16 * CH) break;
+            const int sl = e / CH, ii = e - sl * CH;
+            double xb = 0.0;
+            if (i0 + ii < s_n[sl]) {
+              const int64_t oi = s_off[sl] + i0 + ii;
+              const double mu = s_mu[sl], sigma = s_sig[sl];
+              const double bv = bvv[u], ia = iav[u], dci = dcv[u], abv = fabs(bv);
+              const double xh = abv > mu ? sgn(bv) * (abv - mu) * ia / dci : 0.0;
+              xb = 2.0 * xh - xo[u];
+              const double dr = drc[u];
+              const double vs = yco[u] + sigma * (dr * dci * xb);
+              const double z = vs / (sigma * dr) - w0v[u];
+              const double pr = prox_cost(z, 1.0 / (sigma * dr * dr), cav[u], cbv[u], S.d);
+              const double ty = vs - sigma * dr * w0v[u] - sigma * dr * pr;
+              if (check) {
+                S.Tx[oi] = xh;
+                S.TyC[oi] = ty;
+              } else {
+                const double a1 = s_a1[sl], a0 = s_a0[sl];
+                S.x[oi] = a1 * ((1.0 + rho) * xh - rho * xo[u]) + a0 * x0v[u];
+                S.yC[oi] = a1 * ((1.0 + rho) * ty - rho * yco[u]) + a0 * y0v[u];
+              }
+            }
+            xs[sl * ld + ii] = xb;
+          }
+        }
+      }
+      __syncthreads();
+      d4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int q = 0; q < CH / 4; ++q) acc = mfma(xs[cl * ld + 4 * q + rq], bk[q], acc);   // A[slot cl][asset]
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int s = 16 * g + 4 * j + rq;
+        if (s < nact) S.part[((size_t)c * S.B + s) * S.nrp + r] = acc[j];
+      }
+      __syncthreads();
+    }
   }
 }
 
 // ---------------------------------------------------------------------------------
-// Row duals per slot (one wave per slot, lanes over rows).  The group's chunks of
+// Row duals per slot (one workgroup per slot, threads over rows).  The group's chunks of
 // partial sums are added in chunk order: Kx = dr_b * sum_c part[c][s][r] = (K~_b xbar)_r.
 // mode 0: T(y) and the reflected Halpern step (y, yh = dr y); then it, kk advance.
 // mode 1: T(y) kept in Ty and yhT = dr T(y) (a check follows).
 // mode 2: power iteration: u = Kx, yhT = dr u (input of K~^T u), inst.kvr = ||u||^2.
-__global__ __launch_bounds__(256) void k_dual(LsShared S, int mode) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int g = blockIdx.x;
-  const int nact = S.cnt[0];
-  if (g >= S.cnt[3]) return;
+__global__ __launch_bounds__(128) void k_dual(LsShared S, int mode) {
+  __shared__ double red[2];
+  const int slot = blockIdx.x;
+  if (slot >= S.cnt[0]) return;
+  const int b = S.act[slot];
+  const int g = slot / 16;
   const int nch = (S.nb[S.act[16 * g]] + S.ch - 1) / S.ch;
-  for (int sl = wave; sl < 16; sl += 4) {
-    const int s = 16 * g + sl;
-    if (s >= nact) break;
-    const int b = S.act[s];
-    const LsInst I = S.inst[b];
-    const double sigma = I.eta * I.omega;
-    const double kk = (double)I.kk;
-    const double a1 = (kk + 1.0) / (kk + 2.0), a0 = 1.0 / (kk + 2.0), rho = S.rho;
-    double kv = 0.0;
-    for (int r = lane; r < S.nr; r += 64) {
-      double sum = 0.0;
-      for (int c = 0; c < nch; ++c) sum += S.part[((size_t)c * S.B + s) * S.nrp + r];
-      const double dr = S.drs[(size_t)b * S.nr + r];
-      const double kx = dr * sum;
-      const size_t e = (size_t)b * S.nrp + r;
-      if (mode == 2) {
-        S.yhT[e] = dr * kx;
-        kv = fma(kx, kx, kv);
-        continue;
-      }
-      const double vs = S.y[e] + sigma * kx;
-      double ty;
-      if (r < S.m) {
-        const double sd = sigma * dr;
-        ty = vs - sd * fmin(fmax(vs / sd, S.L[(size_t)b * S.m + r]), S.U[(size_t)b * S.m + r]);
-      } else {
-        ty = 2.0 * S.g1 * vs / (sigma * dr * dr + 2.0 * S.g1);   // G^T c = 0 (single period)
-      }
-      if (mode == 1) {
-        S.Ty[e] = ty;
-        S.yhT[e] = dr * ty;
-      } else {
-        const double yn = a1 * ((1.0 + rho) * ty - rho * S.y[e]) + a0 * S.y0[e];
-        S.y[e] = yn;
-        S.yh[e] = dr * yn;
-      }
+  const LsInst I = S.inst[b];
+  const double sigma = I.eta * I.omega;
+  const double kk = (double)I.kk;
+  const double a1 = (kk + 1.0) / (kk + 2.0), a0 = 1.0 / (kk + 2.0), rho = S.rho;
+  double kv = 0.0;
+  for (int r = threadIdx.x; r < S.nr; r += blockDim.x) {
+    const double* pc = S.part + (size_t)slot * S.nrp + r;
+    const size_t cstride = (size_t)S.B * S.nrp;
+    double sum = 0.0;
+    int c = 0;
+    for (; c + 8 <= nch; c += 8) {
+      double v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v[u] = pc[(size_t)(c + u) * cstride];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) sum += v[u];
     }
+    for (; c < nch; ++c) sum += pc[(size_t)c * cstride];
+    const double dr = S.drs[(size_t)b * S.nr + r];
+    const double kx = dr * sum;
+    const size_t e = (size_t)b * S.nrp + r;
     if (mode == 2) {
-      kv = wsum(kv);
-      if (lane == 0) S.inst[b].kvr = kv;
-    } else if (mode == 0 && lane == 0) {
-      S.inst[b].kk = I.kk + 1;
-      S.inst[b].it = I.it + 1;
+      S.yhT[e] = dr * kx;
+      kv = fma(kx, kx, kv);
+      continue;
     }
+    const double vs = S.y[e] + sigma * kx;
+    double ty;
+    if (r < S.m) {
+      const double sd = sigma * dr;
+      ty = vs - sd * fmin(fmax(vs / sd, S.L[(size_t)b * S.m + r]), S.U[(size_t)b * S.m + r]);
+    } else {
+      ty = 2.0 * S.g1 * vs / (sigma * dr * dr + 2.0 * S.g1);   // G^T c = 0 (single period)
+    }
+    if (mode == 1) {
+      S.Ty[e] = ty;
+      S.yhT[e] = dr * ty;
+    } else {
+      const double yn = a1 * ((1.0 + rho) * ty - rho * S.y[e]) + a0 * S.y0[e];
+      S.y[e] = yn;
+      S.yh[e] = dr * yn;
+    }
+  }
+  if (mode == 2) {
+    kv = wsum(kv);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = kv;
+    __syncthreads();
+    if (threadIdx.x == 0) S.inst[b].kvr = red[0] + (blockDim.x > 64 ? red[1] : 0.0);
+  } else if (mode == 0 && threadIdx.x == 0) {
+    S.inst[b].kk = I.kk + 1;
+    S.inst[b].it = I.it + 1;
   }
 }
 
 // ---------------------------------------------------------------------------------
-// Primal step per instance (one workgroup per slot): prox inputs from R = K~^T y,
-// the exact budget multiplier, T(x), xbar = 2 T(x) - x, the trade duals T(y_C), and
-// (check == 0) the reflected Halpern step on x and y_C, or (check == 1) T(x), T(y_C)
-// kept for the check.
-__global__ void k_primal(LsShared S, int check) {
+// Primal step, in three kernels:
+//   k_pre  (element tiles): prox inputs b, 1/a from R = K~^T y and the tile's sums of
+//          S and its slope at 0 and at the previous multiplier;
+//   k_mu   (one workgroup per instance): the exact budget multiplier;
+//   k_post (element tiles): T(x), xbar = 2 T(x) - x, the trade duals T(y_C), and either
+//          the reflected Halpern step on x and y_C (check == 0) or T(x), T(y_C) kept for
+//          the check.
+__global__ __launch_bounds__(256) void k_pre(LsShared S) {
+  __shared__ double red[RED_DOUBLES];
+  const int ntile = S.cnt[4];
+  for (int tile = blockIdx.x; tile < ntile; tile += gridDim.x) {
+    const int slot = S.tileE[2 * tile], ec = S.tileE[2 * tile + 1];
+    const int b = S.act[slot];
+    const int64_t o = S.offs[b];
+    const int n = S.nb[b];
+    const double eta = S.inst[b].eta, omega = S.inst[b].omega, mp = S.inst[b].mu;
+    const double tau = eta / omega;
+    const int iend = min(n, (ec + 1) * EW);
+    double acc[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};   // S0, A0, C0, S(mp), A(mp), C(mp)
+    double Rv[4], yc[4], xv[4], al[4], dcv[4], drc[4], ar[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int i = ec * EW + threadIdx.x + u * 256;
+      const bool in = i < iend;
+      Rv[u] = in ? S.R[o + i] : 0.0;
+      yc[u] = in ? S.yC[o + i] : 0.0;
+      xv[u] = in ? S.x[o + i] : 0.0;
+      al[u] = in ? S.alpha[o + i] : 0.0;
+      dcv[u] = in ? S.dc[i] : 1.0;
+      drc[u] = in ? S.drC[i] : 1.0;
+      ar[u] = in ? S.arisk[i] : 1.0;
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int i = ec * EW + threadIdx.x + u * 256;
+      if (i < iend) {
+        const double dci = dcv[u];
+        const double Ry = Rv[u] + dci * drc[u] * yc[u];
+        const double v = xv[u] - tau * Ry;
+        const double a = 1.0 / (tau * dci * dci) + ar[u];
+        const double bv = v / (tau * dci) + al[u];
+        const double ia = 1.0 / a, ab = fabs(bv);
+        S.gb[o + i] = bv;
+        S.ga[o + i] = ia;
+        if (ab > 0.0) { acc[0] = fma(ab, ia, acc[0]); acc[1] += ia; acc[2] += 1.0; }
+        if (ab > mp) { acc[3] = fma(ab - mp, ia, acc[3]); acc[4] += ia; acc[5] += 1.0; }
+      }
+    }
+    bsum<6>(acc, red);
+    if (threadIdx.x < 6) S.estat[(size_t)tile * 8 + threadIdx.x] = acc[threadIdx.x];
+  }
+}
+
+__global__ __launch_bounds__(512) void k_mu(LsShared S, int fused) {
   extern __shared__ double lds[];
   double* red = lds;
   const int slot = blockIdx.x;
@@ -376,55 +626,118 @@ __global__ void k_primal(LsShared S, int check) {
   const int b = S.act[slot];
   const int64_t o = S.offs[b];
   const int n = S.nb[b];
-  const bool in_lds = n <= S.lds_cap;
-  double* sb = in_lds ? lds + RED_DOUBLES : S.gb + o;
-  double* sa = in_lds ? lds + RED_DOUBLES + n : S.ga + o;
-  const LsInst I = S.inst[b];
-  const double tau = I.eta / I.omega, sigma = I.eta * I.omega;
-  const double mp = I.mu;
-  // pass 1: signed b and 1/a, S and its slope at 0 and at the previous multiplier
-  double acc[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};   // S0, A0, C0, S(mp), A(mp), C(mp)
-  for (int i = threadIdx.x; i < n; i += blockDim.x) {
-    const double dci = S.dc[i];
-    const double Ry = S.R[o + i] + dci * S.drC[i] * S.yC[o + i];
-    const double v = S.x[o + i] - tau * Ry;
-    const double a = 1.0 / (tau * dci * dci) + S.arisk[i];
-    const double bv = v / (tau * dci) + S.alpha[o + i];
-    const double ia = 1.0 / a, ab = fabs(bv);
-    sb[i] = bv;
-    sa[i] = ia;
-    if (ab > 0.0) { acc[0] = fma(ab, ia, acc[0]); acc[1] += ia; acc[2] += 1.0; }
-    if (ab > mp) { acc[3] = fma(ab - mp, ia, acc[3]); acc[4] += ia; acc[5] += 1.0; }
+  const double mp = S.inst[b].mu;
+  // the first pass's sums for this instance, added in tile order: element tiles (split
+  // form) or 64-asset blocks (fused form)
+  double acc[6];
+  if (!fused) {
+    const int t0 = S.eoff[slot], nt = (n + EW - 1) / EW;
+#pragma unroll
+    for (int q = 0; q < 6; ++q) {
+      double v = 0.0;
+      for (int t = 0; t < nt; ++t) v += S.estat[(size_t)(t0 + t) * 8 + q];
+      acc[q] = v;
+    }
+  } else {
+    const int nab = (n + 63) / 64;
+    double v[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int t = threadIdx.x; t < nab; t += blockDim.x) {   // per thread in block order, then
+#pragma unroll                                              // a fixed-order workgroup sum
+      for (int q = 0; q < 6; ++q) v[q] += S.estat2[((size_t)t * S.B + slot) * 8 + q];
+    }
+    bsum<6>(v, red);
+#pragma unroll
+    for (int q = 0; q < 6; ++q) acc[q] = v[q];
   }
-  bsum<6>(acc, red);
+  // the (b, 1/a) pairs move to LDS when they fit (every multiplier pass reads them)
+  const bool in_lds = n <= S.lds_cap;
   double mu = 0.0;
-  const int passes = l1_multiplier(sb, sa, n, acc[0], acc[1], acc[2], mp, acc[3], acc[4], acc[5], red, mu);
-  // pass 2
-  const double kk = (double)I.kk;
-  const double a1 = (kk + 1.0) / (kk + 2.0), a0 = 1.0 / (kk + 2.0), rho = S.rho;
-  for (int i = threadIdx.x; i < n; i += blockDim.x) {
-    const double bv = sb[i], ia = sa[i], dci = S.dc[i], ab = fabs(bv);
-    const double xh = ab > mu ? sgn(bv) * (ab - mu) * ia / dci : 0.0;
-    const double xo = S.x[o + i];
-    const double xb = 2.0 * xh - xo;
-    S.xbar[o + i] = xb;
-    const double drc = S.drC[i];
-    const double yco = S.yC[o + i], w0 = S.w0[o + i];
-    const double vs = yco + sigma * (drc * dci * xb);
-    const double z = vs / (sigma * drc) - w0;
-    const double pr = prox_cost(z, 1.0 / (sigma * drc * drc), S.ca[o + i], S.cb[o + i], S.d);
-    const double ty = vs - sigma * drc * w0 - sigma * drc * pr;
-    if (check) {
-      S.Tx[o + i] = xh;
-      S.TyC[o + i] = ty;
+  int passes = 0;
+  if (acc[0] > 1.0) {
+    const double* gb = S.gb + o;
+    const double* ga = S.ga + o;
+    if (in_lds) {
+      ldbl* sb = (ldbl*)(lds + RED_DOUBLES);
+      ldbl* sa = sb + n;
+      const int nt = blockDim.x;
+      for (int i0 = threadIdx.x; i0 < n; i0 += 4 * nt) {
+        double bq[4], aq[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int i = i0 + u * nt;
+          bq[u] = i < n ? gb[i] : 0.0;
+          aq[u] = i < n ? ga[i] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int i = i0 + u * nt;
+          if (i < n) { sb[i] = bq[u]; sa[i] = aq[u]; }
+        }
+      }
+      __syncthreads();
+      passes = l1_multiplier((const ldbl*)sb, (const ldbl*)sa, n, acc[0], acc[1], acc[2], mp, acc[3], acc[4],
+                             acc[5], red, mu);
     } else {
-      S.x[o + i] = a1 * ((1.0 + rho) * xh - rho * xo) + a0 * S.x0[o + i];
-      S.yC[o + i] = a1 * ((1.0 + rho) * ty - rho * yco) + a0 * S.yC0[o + i];
+      passes = l1_multiplier(gb, ga, n, acc[0], acc[1], acc[2], mp, acc[3], acc[4], acc[5], red, mu);
     }
   }
   if (threadIdx.x == 0) {
     S.inst[b].mu = mu;
     S.inst[b].mu_passes = passes;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_post(LsShared S, int check) {
+  const int ntile = S.cnt[4];
+  for (int tile = blockIdx.x; tile < ntile; tile += gridDim.x) {
+    const int slot = S.tileE[2 * tile], ec = S.tileE[2 * tile + 1];
+    const int b = S.act[slot];
+    const int64_t o = S.offs[b];
+    const int n = S.nb[b];
+    const LsInst I = S.inst[b];
+    const double sigma = I.eta * I.omega, mu = I.mu;
+    const double kk = (double)I.kk;
+    const double a1 = (kk + 1.0) / (kk + 2.0), a0 = 1.0 / (kk + 2.0), rho = S.rho;
+    const int iend = min(n, (ec + 1) * EW);
+    double bvv[4], iav[4], dcv[4], xo[4], drc[4], yco[4], w0v[4], cav[4], cbv[4], x0v[4], y0v[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int i = ec * EW + threadIdx.x + u * 256;
+      const bool in = i < iend;
+      bvv[u] = in ? S.gb[o + i] : 0.0;
+      iav[u] = in ? S.ga[o + i] : 0.0;
+      dcv[u] = in ? S.dc[i] : 1.0;
+      xo[u] = in ? S.x[o + i] : 0.0;
+      drc[u] = in ? S.drC[i] : 1.0;
+      yco[u] = in ? S.yC[o + i] : 0.0;
+      w0v[u] = in ? S.w0[o + i] : 0.0;
+      cav[u] = in ? S.ca[o + i] : 0.0;
+      cbv[u] = in ? S.cb[o + i] : 0.0;
+      x0v[u] = in && !check ? S.x0[o + i] : 0.0;
+      y0v[u] = in && !check ? S.yC0[o + i] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int i = ec * EW + threadIdx.x + u * 256;
+      if (i < iend) {
+        const double bv = bvv[u], ia = iav[u], dci = dcv[u], ab = fabs(bv);
+        const double xh = ab > mu ? sgn(bv) * (ab - mu) * ia / dci : 0.0;
+        const double xb = 2.0 * xh - xo[u];
+        S.xbar[o + i] = xb;
+        const double dr = drc[u];
+        const double vs = yco[u] + sigma * (dr * dci * xb);
+        const double z = vs / (sigma * dr) - w0v[u];
+        const double pr = prox_cost(z, 1.0 / (sigma * dr * dr), cav[u], cbv[u], S.d);
+        const double ty = vs - sigma * dr * w0v[u] - sigma * dr * pr;
+        if (check) {
+          S.Tx[o + i] = xh;
+          S.TyC[o + i] = ty;
+        } else {
+          S.x[o + i] = a1 * ((1.0 + rho) * xh - rho * xo[u]) + a0 * x0v[u];
+          S.yC[o + i] = a1 * ((1.0 + rho) * ty - rho * yco[u]) + a0 * y0v[u];
+        }
+      }
+    }
   }
 }
 
@@ -471,7 +784,7 @@ __global__ __launch_bounds__(256) void k_power(LsShared S, int step) {
 // step of this iteration, or the restart to T(z)).  Inputs: Tx, TyC, Ty from the
 // check-mode steps, R = K~^T T(y) over the rows, part = partial sums of K T(x) (with
 // KD = K diag(dc), so K T(x) = A w and G^T w unscaled).
-__global__ void k_check(LsShared S) {
+__global__ __launch_bounds__(512) void k_check(LsShared S) {
   extern __shared__ double lds[];
   double* red = lds;
   __shared__ int s_dec;
@@ -681,35 +994,67 @@ int ls_launch_compact(const LsShared& S, void* stream) {
   return (int)hipGetLastError();
 }
 
+template <bool PRE>
+static int launch_kty_t(const LsShared& S, const double* yin, double* Rout, int grid, hipStream_t st) {
+  const size_t lds = (size_t)GPT_MAX * 16 * (S.nrp + 1) * sizeof(double);
+  if (S.gpt > GPT_MAX) return (int)hipErrorInvalidValue;
+  if (S.nr4 <= 8) hipLaunchKernelGGL((k_kty<8, PRE>), dim3(grid), dim3(256), lds, st, S, yin, Rout);
+  else if (S.nr4 <= 16) hipLaunchKernelGGL((k_kty<16, PRE>), dim3(grid), dim3(256), lds, st, S, yin, Rout);
+  else if (S.nr4 <= 24) hipLaunchKernelGGL((k_kty<24, PRE>), dim3(grid), dim3(256), lds, st, S, yin, Rout);
+  else if (S.nr4 <= 32) hipLaunchKernelGGL((k_kty<32, PRE>), dim3(grid), dim3(256), lds, st, S, yin, Rout);
+  else return (int)hipErrorInvalidValue;
+  return (int)hipGetLastError();
+}
+
 int ls_launch_kty(const LsShared& S, const double* yin, double* Rout, int grid, void* stream) {
-  hipStream_t st = (hipStream_t)stream;
-  if (S.nr4 <= 8) hipLaunchKernelGGL(k_kty<8>, dim3(grid), dim3(256), 0, st, S, yin, Rout);
-  else if (S.nr4 <= 16) hipLaunchKernelGGL(k_kty<16>, dim3(grid), dim3(256), 0, st, S, yin, Rout);
-  else if (S.nr4 <= 24) hipLaunchKernelGGL(k_kty<24>, dim3(grid), dim3(256), 0, st, S, yin, Rout);
-  else if (S.nr4 <= 32) hipLaunchKernelGGL(k_kty<32>, dim3(grid), dim3(256), 0, st, S, yin, Rout);
+  return launch_kty_t<false>(S, yin, Rout, grid, (hipStream_t)stream);
+}
+
+template <bool POST>
+static int launch_kx_t(const LsShared& S, const double* xin, int check, int grid, hipStream_t st) {
+  const int nrb = S.nrp / 16;   // one wave per block of 16 rows
+  const dim3 blk(64 * nrb);
+  if (POST && S.ch != 128) return (int)hipErrorInvalidValue;   // the fused form runs 128-asset chunks
+  if (POST) {
+    if (nrb <= 2) hipLaunchKernelGGL((k_kx<2, 128, true>), dim3(grid), blk, 0, st, S, xin, check);
+    else if (nrb <= 5) hipLaunchKernelGGL((k_kx<5, 128, true>), dim3(grid), blk, 0, st, S, xin, check);
+    else if (nrb <= 8) hipLaunchKernelGGL((k_kx<8, 128, true>), dim3(grid), blk, 0, st, S, xin, check);
+    else return (int)hipErrorInvalidValue;
+    return (int)hipGetLastError();
+  }
+  if (S.ch == 256 && nrb <= 2) hipLaunchKernelGGL((k_kx<2, 256, POST>), dim3(grid), blk, 0, st, S, xin, check);
+  else if (S.ch == 256 && nrb <= 5) hipLaunchKernelGGL((k_kx<5, 256, POST>), dim3(grid), blk, 0, st, S, xin, check);
+  else if (S.ch == 256 && nrb <= 8) hipLaunchKernelGGL((k_kx<8, 256, POST>), dim3(grid), blk, 0, st, S, xin, check);
+  else if (S.ch == 128 && nrb <= 2) hipLaunchKernelGGL((k_kx<2, 128, POST>), dim3(grid), blk, 0, st, S, xin, check);
+  else if (S.ch == 128 && nrb <= 5) hipLaunchKernelGGL((k_kx<5, 128, POST>), dim3(grid), blk, 0, st, S, xin, check);
+  else if (S.ch == 128 && nrb <= 8) hipLaunchKernelGGL((k_kx<8, 128, POST>), dim3(grid), blk, 0, st, S, xin, check);
   else return (int)hipErrorInvalidValue;
   return (int)hipGetLastError();
 }
 
 int ls_launch_kx(const LsShared& S, const double* xin, int grid, void* stream) {
+  return launch_kx_t<false>(S, xin, 0, grid, (hipStream_t)stream);
+}
+
+int ls_launch_step_fused(const LsShared& S, int check, int threads, int gA, int gC, void* stream) {
   hipStream_t st = (hipStream_t)stream;
-  const size_t lds = (size_t)16 * (S.ch + 1) * sizeof(double);
-  const int nrb = S.nrp / 16;   // one wave per block of 16 rows
-  if (nrb <= 2) hipLaunchKernelGGL(k_kx<2>, dim3(grid), dim3(64 * nrb), lds, st, S, xin);
-  else if (nrb <= 5) hipLaunchKernelGGL(k_kx<5>, dim3(grid), dim3(64 * nrb), lds, st, S, xin);
-  else if (nrb <= 8) hipLaunchKernelGGL(k_kx<8>, dim3(grid), dim3(64 * nrb), lds, st, S, xin);
-  else if (nrb <= 16) hipLaunchKernelGGL(k_kx<16>, dim3(grid), dim3(64 * nrb), lds, st, S, xin);
-  else return (int)hipErrorInvalidValue;
-  return (int)hipGetLastError();
+  int e = launch_kty_t<true>(S, S.yh, nullptr, gA, st);
+  if (e) return e;
+  hipLaunchKernelGGL(k_mu, dim3(S.B), dim3(threads), ls_primal_lds(S), st, S, 1);
+  if ((e = (int)hipGetLastError())) return e;
+  return launch_kx_t<true>(S, nullptr, check, gC, st);
 }
 
 int ls_launch_dual(const LsShared& S, int mode, void* stream) {
-  hipLaunchKernelGGL(k_dual, dim3((S.B + 15) / 16), dim3(256), 0, (hipStream_t)stream, S, mode);
+  hipLaunchKernelGGL(k_dual, dim3(S.B), dim3(S.nr <= 64 ? 64 : 128), 0, (hipStream_t)stream, S, mode);
   return (int)hipGetLastError();
 }
 
-int ls_launch_primal(const LsShared& S, int check, int threads, void* stream) {
-  hipLaunchKernelGGL(k_primal, dim3(S.B), dim3(threads), ls_primal_lds(S), (hipStream_t)stream, S, check);
+int ls_launch_primal(const LsShared& S, int check, int threads, int gridE, void* stream) {
+  hipStream_t st = (hipStream_t)stream;
+  hipLaunchKernelGGL(k_pre, dim3(gridE), dim3(256), 0, st, S);
+  hipLaunchKernelGGL(k_mu, dim3(S.B), dim3(threads), ls_primal_lds(S), st, S, 0);
+  hipLaunchKernelGGL(k_post, dim3(gridE), dim3(256), 0, st, S, check);
   return (int)hipGetLastError();
 }
 

@@ -146,12 +146,14 @@ def test_full_batch_256(precision, form):
 
 # ---------------------------------------------------------------- lockstep form only
 
-def test_lockstep_many_groups_with_compaction():
+@pytest.mark.parametrize("autotune", [1, 0, -1])
+def test_lockstep_many_groups_with_compaction(autotune):
     """40 instances (three slot groups) of uneven sizes: instances converge at different
     checks and leave the slot list while the others continue; each against the oracle
-    (every fifth) and all against the team form."""
+    (every fifth) and all against the team form.  autotune 0 / -1: the fused and the
+    separate element passes with fixed tiles; 1: the tuned choice."""
     batch = make_batch(40, 4, 6, seed=13, n_lo=30, n_hi=1500, n_max=1500)
-    W, infos = _solve_batched(batch, tol=1e-10, form="lockstep")
+    W, infos = _solve_batched(batch, tol=1e-10, form="lockstep", autotune=autotune)
     Wt, it = _solve_batched(batch, tol=1e-10, form="teams")
     iters = [i.iters for i in infos]
     assert len(set(iters)) > 3, iters     # they did finish at different checks
@@ -173,12 +175,13 @@ def test_lockstep_is_bitwise_repeatable():
     np.testing.assert_array_equal(W1, W2)
 
 
-def test_lockstep_instances_beyond_the_lds_pairs():
-    """n_b above the LDS capacity for the (b, 1/a) pairs (about 9,000 assets): those
+@pytest.mark.parametrize("autotune", [0, -1])
+def test_lockstep_instances_beyond_the_lds_pairs(autotune):
+    """n_b above the LDS capacity for the (b, 1/a) pairs (about 10,000 assets): those
     instances keep them in device memory; against the plain solver."""
     ff = _gpu()
-    batch = make_batch(3, 4, 6, seed=19, n_lo=9500, n_hi=12000, n_max=12000)
-    W, infos = _solve_batched(batch, tol=1e-8, form="lockstep")
+    batch = make_batch(3, 4, 6, seed=19, n_lo=10500, n_hi=12000, n_max=12000)
+    W, infos = _solve_batched(batch, tol=1e-8, form="lockstep", autotune=autotune)
     for b in range(3):
         inst = batch_instance(batch, b)
         Wp, ip = ff.solve_instance(inst, tol=1e-8)
@@ -187,10 +190,11 @@ def test_lockstep_instances_beyond_the_lds_pairs():
         assert np.max(np.abs(W[lo:hi] - Wp.cpu().numpy()[0])) <= 1e-5
 
 
-def test_lockstep_many_rows():
+@pytest.mark.parametrize("autotune", [0, -1])
+def test_lockstep_many_rows(autotune):
     """m + k = 100 rows (7 row blocks of 16, 25 MFMA steps per K~^T y tile) against the
     oracle."""
     batch = make_batch(6, 60, 40, seed=23, n_lo=200, n_hi=900, n_max=900)
-    W, infos = _solve_batched(batch, tol=1e-9, form="lockstep")
+    W, infos = _solve_batched(batch, tol=1e-9, form="lockstep", autotune=autotune)
     for b in range(6):
         _check_against_oracle(batch, W, infos, b, 1e-9, w_tol=1e-5, obj_tol=1e-6)
