@@ -75,6 +75,12 @@ def parse():
     ap.add_argument("--workgroups", type=int, default=0)
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the comparison legs (T=20 solve, FP32 form, batched form, adjoint)")
+    ap.add_argument("--paper-grid", action="store_true",
+                    help="only run the paper's benchmark shape (Section 4.1): the 5 x 5 lambda grid x the dates, "
+                         "single-period and multi-period (T=10), and print Count / SGM1 per grid point in the layout "
+                         "of the paper's Table 1 (one JSON line)")
+    ap.add_argument("--paper-n", type=int, default=1000, help="assets per paper-shaped instance")
+    ap.add_argument("--paper-dates", type=int, default=21, help="dates per grid point (the paper: 21)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only copy a float64 buffer of MIB MiB three times on the GPU (one read and one write "
                          "of MIB MiB each) and exit: the known-size reference that scales rocprofv3's "
@@ -111,6 +117,50 @@ def result_error(inst, W, ref):
     pb = normalize(inst)
     Wn = W.cpu().numpy() if hasattr(W, "cpu") else np.asarray(W)
     return float(np.max(np.abs(Wn - ref["W"]))), float(abs(objective(pb, Wn) - ref["phi"]) / abs(ref["phi"]))
+
+
+def sgm1(times):
+    """Shifted geometric mean of solve times with a shift of 1 s (paper Section 4.1)."""
+    t = np.asarray(times, dtype=np.float64)
+    return float(np.exp(np.mean(np.log(t + 1.0))) - 1.0)
+
+
+def paper_grid(ff, torch, a):
+    """Count / SGM1 over the paper's grid (Section 4.1, Table 1 layout): for each
+    (lambda2 = lambda3, lambda1) and each model, the dates solved to the relative KKT
+    tolerance within the 360 s limit, and the shifted geometric mean of their solve times.
+    Inputs are built on the host and moved to the device before each timed solve."""
+    from synth import LAMBDA1_GRID, LAMBDA23_GRID, paper_instance
+    dev = torch.device("cuda", 0)
+    keys = ("alpha", "F", "Omega", "delta", "s", "q", "A", "L", "U", "w0", "w_target")
+    rows = []
+    for l23 in LAMBDA23_GRID:
+        for l1 in LAMBDA1_GRID:
+            row = {"lambda23": l23, "lambda1": l1}
+            for model, T in (("single", 0), ("multi", 10)):
+                times, solved, iters = [], 0, []
+                for date in range(a.paper_dates):
+                    inst = paper_instance(date, n=a.paper_n, lambda1=l1, lambda23=l23, T=T)
+                    d = dict(inst)
+                    for kk in keys:
+                        if d.get(kk) is not None:
+                            d[kk] = torch.as_tensor(d[kk], dtype=torch.float64, device=dev).contiguous()
+                    torch.cuda.synchronize()
+                    t0 = time.perf_counter()
+                    _, info = ff.solve_instance(d, tol=a.tol, time_limit_s=360.0, raise_on_failure=False)
+                    torch.cuda.synchronize()
+                    times.append(time.perf_counter() - t0)
+                    solved += int(info.status == 0)
+                    iters.append(info.iters)
+                row[model] = {"count": solved, "of": a.paper_dates, "sgm1_s": sgm1(times),
+                              "iters_median": float(np.median(iters))}
+            rows.append(row)
+            print(f"paper grid l23={l23:g} l1={l1:g}: SP {row['single']['count']}/{a.paper_dates} "
+                  f"{row['single']['sgm1_s']:.4f} s, MP {row['multi']['count']}/{a.paper_dates} "
+                  f"{row['multi']['sgm1_s']:.4f} s", file=sys.stderr, flush=True)
+    return {"metric": "paper grid: count solved / SGM1 seconds per (lambda2=lambda3, lambda1)", "tol": a.tol,
+            "n": a.paper_n, "dates": a.paper_dates, "T_multi": 10, "data": "synthetic (paper shape, Section 3)",
+            "rows": rows}
 
 
 def algorithmic_bytes_per_iter(n, k, m, P, Tp, w=8):
@@ -247,6 +297,9 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
+    if a.paper_grid:
+        print(json.dumps(paper_grid(ff, torch, a)), flush=True)
+        return
     cfg = CONFIGS[a.config]
     seeds = list(cfg["seeds"])
     dev = torch.device("cuda", 0)

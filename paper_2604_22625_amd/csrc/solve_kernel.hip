@@ -374,10 +374,15 @@ struct S {
   Iter<SL, R> xs, Txs;                      // [P]
   Arr<SL, double> ys0C;                     // [Tp]
   Iter<SL, R> ysC, TysC;                    // [Tp]
-  // constants
+  // constants: the ones that define a trade (column scale, trade-row scale, w0, w_T and
+  // the risk centre) stay float64 in every form, so the fixed point trades to the exact
+  // w0 (a float copy of w0 shifts the cost kinks by ~1e-10, which large cost weights turn
+  // into a relative gap of ~1e-4); the others are LDS copies of type RC
   Arr<SL, RC> alpha;                        // [P]
-  Arr<SL, RC> ca, cb, drC;                  // [Tp]
-  Arr<SL, RC> dc, arisk, cvec, w0, wT;      // [1]
+  Arr<SL, RC> ca, cb;                       // [Tp]
+  Arr<SL, double> drC;                      // [Tp]
+  Arr<SL, RC> arisk;                        // [1]
+  Arr<SL, double> dc, cvec, w0, wT;         // [1]
   __device__ __forceinline__ double Kat(int j, int li) const {
     if constexpr (KL) return (double)Kl[j * ldl + li];
     else return (double)Kg[(size_t)j * p->ldk + i0 + li] * ks[j];
@@ -1173,8 +1178,8 @@ __device__ __forceinline__ void solve_body(const DevProblem& p, const DevState& 
     V.xs = {V.x0s, take(fr, P)}; V.Txs = {V.x0s, take(fr, P)};
     V.ys0C = take(fd, Tp);
     V.ysC = {V.ys0C, take(fr, Tp)}; V.TysC = {V.ys0C, take(fr, Tp)};
-    V.alpha = take(fc, P); V.ca = take(fc, Tp); V.cb = take(fc, Tp); V.drC = take(fc, Tp);
-    V.dc = take(fc, 1); V.arisk = take(fc, 1); V.cvec = take(fc, 1); V.w0 = take(fc, 1); V.wT = take(fc, 1);
+    V.alpha = take(fc, P); V.ca = take(fc, Tp); V.cb = take(fc, Tp); V.drC = take(fd, Tp);
+    V.dc = take(fd, 1); V.arisk = take(fc, 1); V.cvec = take(fd, 1); V.w0 = take(fd, 1); V.wT = take(fd, 1);
   } else {
     // state buffers hold [P or Tp][n] elements (iterates of type R); constants are the
     // FP64 inputs
@@ -2603,7 +2608,7 @@ int solve_vmax(const DevProblem& p) {
 template <class R>
 static size_t state_lds_doubles(size_t P, size_t Tp, size_t nw) {
   return 4 * P * nw + 2 * lds_doubles<R>(P * nw) + Tp * nw + 2 * lds_doubles<R>(Tp * nw) +
-         lds_doubles<R>(P * nw) + 3 * lds_doubles<R>(Tp * nw) + 5 * lds_doubles<R>(nw);
+         lds_doubles<R>(P * nw) + 2 * lds_doubles<R>(Tp * nw) + Tp * nw + lds_doubles<R>(nw) + 4 * nw;
 }
 
 size_t solve_lds_bytes(const DevProblem& p, const DevControl& c) {

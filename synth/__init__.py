@@ -24,3 +24,11 @@ from .markets import (  # noqa: F401
     ushape_profile_inputs,
     make_tiny,
 )
+from .paper import (  # noqa: F401
+    LAMBDA1_GRID,
+    LAMBDA23_GRID,
+    N_DATES,
+    paper_instance,
+    eta_profile,
+    returns_panel,
+)

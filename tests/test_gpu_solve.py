@@ -250,18 +250,55 @@ def test_fp32_multi_period_small():
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 
 
-@pytest.mark.parametrize("precision", ["fp64", "fp32"])
-def test_full_size_single_period_against_golden(precision):
-    inst = make_config(1, seed=1)
-    g = np.load(os.path.join(GOLDEN, "c1_seed1_oracle.npz"))
+def _golden(name, seed):
+    g = np.load(os.path.join(GOLDEN, f"{name}_seed{seed}_oracle.npz"))
     assert bool(g["polished"]) and abs(float(g["gap"])) <= 1e-10 * abs(float(g["phi"]))
-    W, info, Y = _run(inst, tol=1e-6, precision=precision)
+    return g
+
+
+C1_GOLDEN_SEEDS = sorted(int(f.split("seed")[1].split("_")[0]) for f in os.listdir(GOLDEN)
+                         if f.startswith("c1_seed") and f.endswith("_oracle.npz"))
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("seed", C1_GOLDEN_SEEDS)
+def test_full_size_single_period_against_golden(precision, seed):
+    """n = 5000 markets at the benchmark's relative KKT 1e-6: the KKT-implied bars (2e-5 in
+    W, 2e-6 relative objective; seed 1 measured 9.0e-6 and 4.5e-7), then the stated parity
+    bars (|W - W*|_inf <= 1e-5, relative objective <= 1e-6) at relative KKT 2e-7."""
+    inst = make_config(1, seed=seed)
+    g = _golden("c1", seed)
     pb = _dual_problem(inst)
-    assert info.status == 0 and info.rel_kkt <= 1e-6
-    K = kkt(pb, W, *Y)
-    assert K.rel_kkt <= 2e-6, (K, info)
-    assert np.max(np.abs(W - g["W"])) <= 2e-5
-    assert abs(objective(pb, W) - float(g["phi"])) <= 2e-6 * abs(float(g["phi"]))
+    for tol, w_tol, obj_tol in ((1e-6, 2e-5, 2e-6), (2e-7, 1e-5, 1e-6)):
+        W, info, Y = _run(inst, tol=tol, precision=precision)
+        assert info.status == 0 and info.rel_kkt <= tol
+        K = kkt(pb, W, *Y)
+        assert K.rel_kkt <= 2.0 * tol, (K, info)
+        assert np.max(np.abs(W - g["W"])) <= w_tol, (tol, np.max(np.abs(W - g["W"])))
+        assert abs(objective(pb, W) - float(g["phi"])) <= obj_tol * abs(float(g["phi"]))
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_full_size_T20_against_golden(precision):
+    """T = 20, n = 3000 (19 decision periods) element-wise against the oracle's certified
+    W* (paper Section 2.2, eq. 4-6).  At relative KKT 1e-6 the weights are 2.3e-5 away
+    (bar 3e-5) with the objective within 2.3e-7 (bar 2e-6); at 1e-8 the stated parity bars
+    hold (measured 7.7e-6 in W, 1.5e-8 in the objective)."""
+    inst = make_config(2, seed=20)
+    g = _golden("c2", 20)
+    pb = _dual_problem(inst)
+    for tol, w_tol, obj_tol in ((1e-6, 3e-5, 2e-6), (1e-8, 1e-5, 1e-6)):
+        W, info, Y = _run(inst, tol=tol, precision=precision, max_iter=400000)
+        assert info.status == 0 and info.rel_kkt <= tol
+        K = kkt(pb, W, *Y)
+        assert K.rel_kkt <= 2.0 * tol, (K, info)
+        err = np.max(np.abs(W - g["W"]))
+        assert err <= w_tol, (tol, err)
+        assert abs(objective(pb, W) - float(g["phi"])) <= obj_tol * abs(float(g["phi"]))
+        # feasibility: budgets and exposure bounds of every period
+        assert np.all(np.abs(W).sum(axis=1) <= 1.0 + 1e-9)
+        AW = W @ pb.A.T
+        assert np.all(AW >= pb.L - 1e-5) and np.all(AW <= pb.U + 1e-5)
 
 
 @pytest.mark.parametrize("cfg,seed", [(2, 20), (4, 40)])
@@ -276,6 +313,8 @@ def test_full_size_multi_period_kkt(cfg, seed, precision):
     assert abs(K.primal_obj - info.primal_obj) <= 1e-10 * abs(K.primal_obj)
     # feasibility of the returned weights: budgets and exposure bounds
     assert np.all(np.abs(W).sum(axis=1) <= 1.0 + 1e-5)
+    AW = W @ pb.A.T
+    assert np.all(AW >= pb.L - 1e-4) and np.all(AW <= pb.U + 1e-4)
 
 
 def test_large_single_period_kkt():
