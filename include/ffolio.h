@@ -271,6 +271,31 @@ ffo_status ffo_solve_batched(int64_t B, const int64_t* n_b, int64_t n_max, int64
                              double lambda1, double lambda2, double lambda3, const ffo_options* opt,
                              void* stream, double* w_out, ffo_info* infos);
 
+/*
+ * Risk-model construction (paper Section 3.2): the inputs S = beta Sigma_f beta^T + D of
+ * the solvers from a window of daily returns.
+ *   R      [days][n]  asset returns (device)
+ *   Fr     [days][p]  factor returns (device), 1 <= p <= 8 (the paper: p = 6)
+ *   mask   [days][n]  optional (device, NULL = all observed): nonzero where R holds an
+ *                     observation; unobserved entries are never read (they may be NaN)
+ *   min_obs           assets with fewer observed days get no loadings (the paper: at
+ *                     least two months of history)
+ * Outputs (device, caller-allocated):
+ *   beta   [n][p]     least-squares loadings of r_i ~ Fr beta_i over the asset's observed
+ *                     days (no intercept), 0 for assets without loadings
+ *   Sigma_f [p][p]    (Fr - mean)^T (Fr - mean) / (days - 1) over the whole window
+ *   D      [n]        sample variance (centred, 1/(count - 1)) of the residuals
+ *                     r_ki - beta_i^T f_k over the observed days (of the returns themselves
+ *                     for assets without loadings; 0 with fewer than two observations)
+ *   valid  [n]        1 where loadings were estimated (enough observations and a
+ *                     nonsingular Gram matrix), else 0
+ * These feed ffo_solve as F = beta, Omega = Sigma_f, delta = sqrt(D).  Observed entries
+ * must be finite.  Statuses: FFO_EINVAL (sizes, pointers), FFO_ENOMEM, FFO_EDEVICE.
+ */
+ffo_status ffo_risk_model(int64_t days, int64_t n, int64_t p, const double* R, const double* Fr,
+                          const uint8_t* mask, int64_t min_obs, void* stream, double* beta,
+                          double* Sigma_f, double* D, int32_t* valid);
+
 /* Thread-local description of the last non-OK status ("" if none). */
 const char* ffo_last_error(void);
 

@@ -14,8 +14,8 @@ from dataclasses import dataclass, asdict
 
 import numpy as np
 
-__all__ = ["solve", "solve_instance", "solve_batched", "adjoint", "FolioFn", "Info", "FolioError", "lib",
-           "LIB_PATH", "STATUS"]
+__all__ = ["solve", "solve_instance", "solve_batched", "adjoint", "risk_model", "FolioFn", "Info", "FolioError",
+           "lib", "LIB_PATH", "STATUS"]
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libffolio.so")
 
@@ -94,6 +94,8 @@ def lib() -> ctypes.CDLL:
         L.ffo_solve_warm.restype = ctypes.c_int
         L.ffo_solve_noalloc.argtypes = L.ffo_solve.argtypes
         L.ffo_solve_noalloc.restype = ctypes.c_int
+        L.ffo_risk_model.argtypes = [_I64, _I64, _I64, _P, _P, _P, _I64, _P, _P, _P, _P, _P]
+        L.ffo_risk_model.restype = ctypes.c_int
         L.ffo_solve_batched.argtypes = [_I64, _P, _I64, _I64, _I64, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P,
                                         _D, _D, _D, _D, _D, ctypes.POINTER(_Options), _P, _P, _P]
         L.ffo_solve_batched.restype = ctypes.c_int
@@ -374,6 +376,36 @@ def adjoint(inst: dict, W, Y, grad_w, *, omega: float = 0.0, tol: float = 1e-9, 
     if rc == 1 or (rc in (2, 3)) or (rc != 0 and raise_on_failure):
         raise FolioError(rc, lib().ffo_last_error().decode())
     return g_a, g_s, g_F, inf
+
+
+def risk_model(R, Fr, mask=None, min_obs: int = 42, device=None, stream=None):
+    """Risk model of paper Section 3.2 on the GPU (ffo_risk_model): R [days][n] asset
+    returns, Fr [days][p] factor returns, optional mask [days][n] (nonzero = observed).
+    Returns (beta [n][p], Sigma_f [p][p], D [n], valid [n] int32) as CUDA tensors; the
+    solver takes F = beta, Omega = Sigma_f, delta = sqrt(D)."""
+    torch = _torch()
+    if not torch.cuda.is_available():
+        raise FolioError(3, "no GPU visible to PyTorch: the library has no CPU path")
+    dev = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
+    Rd = _dev_f64(R, dev)
+    days, n = Rd.shape
+    Fd = _dev_f64(Fr, dev).reshape(days, -1)
+    p = Fd.shape[1]
+    Md = None
+    if mask is not None:
+        Md = torch.as_tensor(np.asarray(mask) if not isinstance(mask, torch.Tensor) else mask)
+        Md = Md.to(device=dev, dtype=torch.uint8).reshape(days, n).contiguous()
+    beta = torch.empty((n, p), dtype=torch.float64, device=dev)
+    Sf = torch.empty((p, p), dtype=torch.float64, device=dev)
+    D = torch.empty(n, dtype=torch.float64, device=dev)
+    valid = torch.empty(n, dtype=torch.int32, device=dev)
+    st = torch.cuda.current_stream(dev) if stream is None else stream
+    with torch.cuda.device(dev):
+        rc = lib().ffo_risk_model(days, n, p, _ptr(Rd), _ptr(Fd), _ptr(Md), int(min_obs),
+                                  ctypes.c_void_p(st.cuda_stream), _ptr(beta), _ptr(Sf), _ptr(D), _ptr(valid))
+    if rc != 0:
+        raise FolioError(rc, lib().ffo_last_error().decode())
+    return beta, Sf, D, valid
 
 
 def _folio_fn():

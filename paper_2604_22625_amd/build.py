@@ -13,7 +13,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libffolio.so")
-SOURCES = ["ffolio_host.hip", "solve_kernel.hip", "setup_kernels.hip", "lockstep.hip"]
+SOURCES = ["ffolio_host.hip", "solve_kernel.hip", "setup_kernels.hip", "lockstep.hip", "riskmodel.hip"]
 ARCH = os.environ.get("FFO_OFFLOAD_ARCH", "gfx950")
 
 

@@ -965,6 +965,27 @@ ffo_status ffo_solve_noalloc(int64_t n, int64_t k, int64_t m, int64_t T, const d
                     w_target, nullptr, nullptr, 0.0, opt_in, stream, w_out, y_out, info, &fx);
 }
 
+ffo_status ffo_risk_model(int64_t days, int64_t n, int64_t p, const double* R, const double* Fr, const uint8_t* mask,
+                          int64_t min_obs, void* stream, double* beta, double* Sigma_f, double* D, int32_t* valid) {
+  g_err.clear();
+  if (days < 2 || days > ((int64_t)1 << 20)) return fail(FFO_EINVAL, "days must lie in [2, 2^20]");
+  if (n < 1 || n > ((int64_t)1 << 26)) return fail(FFO_EINVAL, "n must lie in [1, 2^26]");
+  if (days * n > ((int64_t)1 << 34)) return fail(FFO_EINVAL, "days * n too large");
+  if (p < 1 || p > 8) return fail(FFO_EINVAL, "p must lie in [1, 8]");
+  if (min_obs < 0 || min_obs > days) return fail(FFO_EINVAL, "min_obs must lie in [0, days]");
+  if (!R || !Fr || !beta || !Sigma_f || !D || !valid) return fail(FFO_EINVAL, "null array pointer");
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  Workspace* ws = nullptr;
+  if (ffo_status st = get_workspace(dev, stream, ffo::rm_workspace_bytes(days, n, p), 256, &ws, 4)) return st;
+  if (ffo::launch_risk_model((int)days, (int)n, (int)p, R, Fr, mask, (int)min_obs, (double*)ws->base, beta, Sigma_f,
+                             D, valid, stream))
+    return fail(FFO_EDEVICE, "risk-model kernel launch failed");
+  HIPCHK(hipStreamSynchronize((hipStream_t)stream));
+  return FFO_OK;
+}
+
+
 ffo_status ffo_solve_warm(int64_t n, int64_t k, int64_t m, int64_t T, const double* alpha, const double* F,
                           const double* Omega, const double* delta, const double* s, const double* q, double d,
                           const double* A, const double* L, const double* U, const double* w0, double GMV,

@@ -224,4 +224,10 @@ int ls_launch_power(const LsShared& S, int step, void* stream);   // step 0: row
 int ls_launch_transpose(const LsShared& S, double* KDT, void* stream);
 size_t ls_primal_lds(const LsShared& S);
 
+// Risk-model construction (riskmodel.hip): workspace bytes and the launches of the
+// partial sums, the per-asset solves and the factor covariance (1 <= p <= 8).
+size_t rm_workspace_bytes(int64_t days, int64_t n, int64_t p);
+int launch_risk_model(int days, int n, int p, const double* R, const double* Fr, const uint8_t* mask, int min_obs,
+                      double* part, double* beta, double* Sf, double* D, int32_t* valid, void* stream);
+
 }  // namespace ffo

@@ -540,7 +540,10 @@ __global__ __launch_bounds__(128) void k_dual(LsShared S, int mode) {
     double ty;
     if (r < S.m) {
       const double sd = sigma * dr;
-      ty = vs - sd * fmin(fmax(vs / sd, S.L[(size_t)b * S.m + r]), S.U[(size_t)b * S.m + r]);
+      const double Lr = S.L[(size_t)b * S.m + r], Ur = S.U[(size_t)b * S.m + r];
+      ty = vs - sd * fmin(fmax(vs / sd, Lr), Ur);
+      if (isinf(Ur) && ty > 0.0) ty = 0.0;   // an infinite side fixes the dual's sign exactly
+      if (isinf(Lr) && ty < 0.0) ty = 0.0;
     } else {
       ty = 2.0 * S.g1 * vs / (sigma * dr * dr + 2.0 * S.g1);   // G^T c = 0 (single period)
     }

@@ -1651,6 +1651,10 @@ __device__ __forceinline__ void solve_body(const DevProblem& p, const DevState& 
       if (j < p.m) {
         const double sd = sigma * p.dr[j];
         ny = vs - sd * fmin(fmax(vs / sd, p.L[j]), p.U[j]);
+        // an infinite bound side forces the dual's sign exactly (rounding of
+        // vs - sd (vs / sd) must not leave the conjugate's domain)
+        if (isinf(p.U[j]) && ny > 0.0) ny = 0.0;
+        if (isinf(p.L[j]) && ny < 0.0) ny = 0.0;
       } else {
         const double drj = p.dr[j];
         ny = 2.0 * p.g1 * (vs - sigma * drj * p.bF[j - p.m]) / (sigma * drj * drj + 2.0 * p.g1);
