@@ -31,17 +31,22 @@ class OracleResult:
 
 
 def solve(inst, tol: float = 1e-9, max_iter: int = 400000, require_polish: bool = True,
-          verbose: bool = False) -> OracleResult:
+          verbose: bool = False, start=None) -> OracleResult:
     """Optimal W for a single- or multi-period instance (dict of arrays or Problem).
 
     Runs the averaged PDHG to relative KKT ``tol``, polishes on the identified active
     set and certifies by a duality gap at rounding level.  If the polish fails, the
     PDHG is tightened by 100x (twice) and the polish retried; ``require_polish``
-    raises if it never succeeds.
+    raises if it never succeeds.  ``start``: an optional (W, yA, yF, yC) to start the
+    PDHG from (e.g. the solution of a nearby instance).
     """
     t0 = time.perf_counter()
     pb = inst if isinstance(inst, Problem) else normalize(inst)
-    r = pdhg(pb, tol=tol, max_iter=max_iter, verbose=verbose)
+    if start is None:
+        r = pdhg(pb, tol=tol, max_iter=max_iter, verbose=verbose)
+    else:
+        W0, yA0, yF0, yC0 = start
+        r = pdhg(pb, tol=tol, max_iter=max_iter, verbose=verbose, W0=W0, Y0=(yA0, yF0, yC0))
     iters = r.iters
     pol = polish(pb, r.W, r.yA, r.yF, r.yC)
     cur_tol = tol

@@ -301,6 +301,23 @@ def test_full_size_T20_against_golden(precision):
         assert np.all(AW >= pb.L - 1e-5) and np.all(AW <= pb.U + 1e-5)
 
 
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_full_size_T10_against_golden(precision):
+    """The differentiation workload (T = 10, n = 2000, k = 40, m = 5 + 35) element-wise
+    against the oracle's certified W*: KKT-implied bars at relative KKT 1e-6, the stated
+    parity bars at 1e-8."""
+    inst = make_config(4, seed=40)
+    g = _golden("c4", 40)
+    pb = _dual_problem(inst)
+    for tol, w_tol, obj_tol in ((1e-6, 3e-5, 2e-6), (1e-8, 1e-5, 1e-6)):
+        W, info, Y = _run(inst, tol=tol, precision=precision, max_iter=400000)
+        assert info.status == 0 and info.rel_kkt <= tol
+        err = np.max(np.abs(W - g["W"]))
+        print(f"  tol {tol:g}: |W - W*| {err:.2e}", flush=True)
+        assert err <= w_tol, (tol, err)
+        assert abs(objective(pb, W) - float(g["phi"])) <= obj_tol * abs(float(g["phi"]))
+
+
 @pytest.mark.parametrize("cfg,seed", [(2, 20), (4, 40)])
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
 def test_full_size_multi_period_kkt(cfg, seed, precision):
