@@ -199,11 +199,11 @@ def _timed(torch, fn, reps):
 
 def comparisons(ff, torch, dev, dev_insts, tol, plain_value):
     """The other legs of the metric, each timed after one warm-up: the T=20 multi-period
-    solve (n=3000), the FP32 form on the same n=5000 markets, the 256-instance batched
-    form (FP64, FP32, FP32 with bfloat16 rows; the reduced forms with their weight error
-    against the FP64 batch) against sequential plain solves of the same instances (a sample
-    of 32, scaled),
-    and the adjoint of the T=10 workload (FP32 forward + FP64 backward)."""
+    solve (n=3000), the FP32 form on the same n=5000 markets, the 256-instance batch in
+    the lockstep form (FP64) and the team form (FP64, FP32, FP32 with bfloat16 rows; each
+    with its weight error against the FP64 lockstep batch) against the 256 instances
+    solved one after another with the plain solver, the risk-model construction, and the
+    adjoint of the T=10 workload (FP32 forward + FP64 backward)."""
     from synth import make_config, batch_instance
     out = {}
     # T = 20 multi-period, FP64 and FP32
@@ -222,25 +222,36 @@ def comparisons(ff, torch, dev, dev_insts, tol, plain_value):
     out["single_period_n5000_fp32"] = {"solves_per_s": len(dev_insts) / dt, "vs_fp64": (len(dev_insts) / dt) / plain_value,
                                        "iters_mean": float(np.mean([i.iters for i in infos])),
                                        "all_ok": all(i.status == 0 for i in infos)}
-    # batched form
+    # batched form: the lockstep form (FP64, matrix-core products over the shared rows) and
+    # the team form (FP64, FP32, FP32 with bfloat16 rows)
     batch = make_config(3)
     offs = np.asarray(batch["offs"])
+    nb_arr = np.asarray(batch["n_b"])
     W64 = None
-    for prec in ("fp64", "fp32", "fp32_bf16k"):
-        ff.solve_batched(batch, tol=tol, precision=prec)
-        dt, (W, binfos) = _timed(torch, lambda: ff.solve_batched(batch, tol=tol, precision=prec), 2)
-        leg = {"solves_per_s": len(binfos) / dt, "batch_ms": dt * 1e3,
-               "iters_max": int(max(i.iters for i in binfos)), "all_ok": all(i.status == 0 for i in binfos)}
+    for prec, form in (("fp64", "lockstep"), ("fp64", "teams"), ("fp32", "teams"), ("fp32_bf16k", "teams")):
+        ff.solve_batched(batch, tol=tol, precision=prec, form=form)
+        dt, (W, binfos) = _timed(torch, lambda: ff.solve_batched(batch, tol=tol, precision=prec, form=form), 2)
+        iters = np.array([i.iters for i in binfos], dtype=np.float64)
+        leg = {"form": form, "solves_per_s": len(binfos) / dt, "batch_ms": dt * 1e3,
+               "iters_max": int(iters.max()), "iters_mean": float(iters.mean()),
+               "all_ok": all(i.status == 0 for i in binfos)}
+        if form == "lockstep":
+            # the two shared-row products of an iteration, 2 * n_b * (m + k) flops each per
+            # instance, summed over the iterations each instance ran, per second of batch
+            nr = int(batch["m"]) + int(batch["k"])
+            flops = float(np.sum(4.0 * nb_arr * nr * iters))
+            leg["mfma_fp64_tflops"] = flops / dt / 1e12
+            leg["mfma_fp64_frac_of_peak"] = flops / dt / 78.6e12
         Wn = W.cpu().numpy()
         if W64 is None:
             W64 = Wn
         else:
-            # error against the FP64 batch, per instance relative to max |w|
+            # error against the first (FP64 lockstep) batch, per instance relative to max |w|
             rel = [float(np.max(np.abs(Wn[a:b] - W64[a:b])) / max(1e-300, np.max(np.abs(W64[a:b]))))
                    for a, b in zip(offs[:-1], offs[1:])]
-            leg["w_rel_err_vs_fp64_max"] = max(rel)
-            leg["w_rel_err_vs_fp64_median"] = float(np.median(rel))
-        out[f"batched_256_{prec}"] = leg
+            leg["w_rel_err_vs_fp64_lockstep_max"] = max(rel)
+            leg["w_rel_err_vs_fp64_lockstep_median"] = float(np.median(rel))
+        out[f"batched_256_{prec}_{form}"] = leg
     nb = np.asarray(batch["n_b"])
     seq = [batch_instance(batch, int(b)) for b in range(len(nb))]
     seq_dev = []
@@ -254,7 +265,8 @@ def comparisons(ff, torch, dev, dev_insts, tol, plain_value):
     seq_ms = dt * 1e3
     out["sequential_plain_256_fp64"] = {"batch_ms": seq_ms, "solves_per_s": len(seq_dev) / dt,
                                        "note": "all 256 instances solved one after another with ffo_solve",
-                                       "batched_fp64_speedup": seq_ms / out["batched_256_fp64"]["batch_ms"]}
+                                       "lockstep_fp64_speedup": seq_ms / out["batched_256_fp64_lockstep"]["batch_ms"],
+                                       "teams_fp64_speedup": seq_ms / out["batched_256_fp64_teams"]["batch_ms"]}
     # adjoint of the T = 10 workload: forward + backward
     c4 = make_config(4)
     P, n = c4["alpha"].shape
@@ -272,6 +284,33 @@ def comparisons(ff, torch, dev, dev_insts, tol, plain_value):
     fwd_bwd("fp32")
     dt, (finfo, ainfo, ga32) = _timed(torch, lambda: fwd_bwd("fp32"), 1)
     rel = float(torch.linalg.norm(ga32 - ga64) / torch.linalg.norm(ga64))
+    # risk-model construction (paper Section 3.2): 504 days x 5000 assets, six factors,
+    # 15% of the assets with a shorter history; one streaming pass over the returns
+    from synth import returns_panel
+    panel = returns_panel(n=5000, days=504, seed=5)
+    rng = np.random.default_rng(6)
+    mask = np.ones((504, 5000), dtype=np.uint8)
+    late = np.nonzero(rng.random(5000) < 0.15)[0]
+    for i in late:
+        mask[:rng.integers(0, 400), i] = 0
+    Rd = torch.as_tensor(panel["R"], device=dev)
+    Fd = torch.as_tensor(panel["Fr"], device=dev)
+    Md = torch.as_tensor(mask, device=dev)
+    ff.risk_model(Rd, Fd, mask=Md)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    reps = 20
+    e0.record()
+    for _ in range(reps):
+        ff.risk_model(Rd, Fd, mask=Md)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    rm_bytes = 504 * 5000 * (8 + 1) + 5000 * (6 + 1) * 8 + 5000 * 4
+    out["risk_model_days504_n5000_p6"] = {"ms": ms, "algorithmic_bytes": rm_bytes,
+                                          "achieved_gb_s": rm_bytes / (ms * 1e-3) / 1e9,
+                                          "frac_of_hbm_peak": rm_bytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                                          "note": "ffo_risk_model call (partial sums, per-asset solves, factor "
+                                                  "covariance) timed with events on the current stream"}
     out["adjoint_T10_n2000"] = {"forward_precision": "fp32", "forward_plus_backward_ms": dt * 1e3,
                                 "forward_kernel_ms": finfo.ms_iter, "forward_iters": finfo.iters,
                                 "adjoint_kernel_ms": ainfo.ms_iter, "adjoint_iters": ainfo.iters,
