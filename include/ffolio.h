@@ -81,7 +81,8 @@ typedef struct {
   double restart_art;      /* ... or the epoch is >= art * total iterations (0.36)    */
   double reflection;       /* rho of the reflected Halpern step, in [0, 1] (1.0)      */
   int32_t workgroups;      /* workgroups of the persistent solve kernel, 0 = auto     */
-  int32_t verbose;         /* 1: one summary line per solve to stderr; 2: also per-check progress (device printf) */
+  int32_t verbose;         /* 1: one summary line per solve to stderr; 2: also per-check progress (device
+                              printf) and, in the batched team form, one line per instance */
   int32_t deterministic;   /* 1: partial sums exchanged through per-workgroup slots and
                               added in a fixed order, so repeated solves are bitwise
                               identical (slower); 0 (default): device-scope atomic adds,

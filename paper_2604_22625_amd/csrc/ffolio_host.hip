@@ -276,6 +276,20 @@ __global__ void k_fill(uint32_t* p, int64_t words, uint32_t value) {
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < words; e += stride) p[e] = value;
 }
 
+// Copies of the atomic exchange slot for a grid of nwg workgroups (see the kernel's
+// exchange): one per group of workgroups, so that fewer read-modify-writes meet on each
+// word.  Below 32 workgroups the extra reads of the copies cost more than they save.
+int xgroups_for(int nwg) { return nwg >= 32 ? ffo::XG_MAX : 1; }
+
+// Default workgroup count of the plain and adjoint kernels: every phase of an iteration
+// is a latency chain, and with the grouped exchange its cost grows slowly with the grid,
+// so from n = 2000 on each workgroup takes 16 assets (up to one per compute unit);
+// smaller problems keep 64 per workgroup.
+int default_workgroups(int64_t n, int cus) {
+  const int64_t per = n >= 2000 ? 16 : 64;
+  return (int)std::max<int64_t>(1, std::min<int64_t>(cus, (n + per - 1) / per));
+}
+
 hipError_t fill(void* p, size_t bytes, uint32_t value, hipStream_t hs) {
   const int64_t words = (int64_t)(bytes / 4);
   if (words == 0) return hipSuccess;
@@ -341,7 +355,7 @@ ffo_status solve_impl(int64_t n, int64_t k, int64_t m, int64_t T, const double* 
   p.n = (int)n; p.k = (int)k; p.m = (int)m; p.P = (int)P; p.Tp = (int)Tp; p.nr = nr;
   p.multi = T > 0 ? 1 : 0; p.ldk = ldk; p.kscaled = 1;
   const int cus = std::max(1, prop.multiProcessorCount);
-  int nwg = opt.workgroups > 0 ? opt.workgroups : (int)std::min<int64_t>(cus, (n + 63) / 64);
+  int nwg = opt.workgroups > 0 ? opt.workgroups : default_workgroups(n, cus);
   nwg = std::max(1, std::min<int>(nwg, (int)n));
   nwg = std::min(nwg, cus);  // one workgroup per compute unit keeps the cooperative grid resident
   int nw = (int)((n + nwg - 1) / nwg);
@@ -354,6 +368,7 @@ ffo_status solve_impl(int64_t n, int64_t k, int64_t m, int64_t T, const double* 
   c.verbose = opt.verbose; c.nw = nw; c.spin_limit = 1u << 26; c.wall_hz = (double)wall_khz * 1e3;
   c.prec = opt.precision == FFO_FP32 ? ffo::PREC_FP32 : ffo::PREC_FP64;
   c.xmode = opt.deterministic ? ffo::XM_GATHER : ffo::XM_ATOMIC;
+  c.xgroups = xgroups_for(nwg);
   c.vmax = ffo::solve_vmax(p);
   c.spec = opt.speculative < 0 ? (P == 1 ? 1 : 0) : (opt.speculative ? 1 : 0);
   c.lists = opt.breakpoint_lists ? 1 : 0;
@@ -401,8 +416,8 @@ ffo_status solve_impl(int64_t n, int64_t k, int64_t m, int64_t T, const double* 
   for (auto& o : ost) o = carve(Pn, 8);
   size_t osc[3];
   for (auto& o : osc) o = carve(Tpn, 8);
-  const size_t nxbuf = (size_t)std::max(2 * nwg, 3) * c.vmax;
-  const size_t oxb = carve(nxbuf, 8), obar = carve(1, 8);
+  const size_t nxbuf = (size_t)std::max(2 * nwg, 3 * ffo::XG_MAX) * c.vmax;
+  const size_t oxb = carve(nxbuf, 8), obar = carve(ffo::BAR_WORDS, 8);
   const size_t oblist = carve(c.lists ? (size_t)2 * nwg * P * ffo::LIST_W : 1, 8);
   const size_t oinfo = carve(ffo::INFO_LEN, 8), ostat = carve(1, 4), oflag = carve(1, 4);
   const size_t total = off;
@@ -482,7 +497,7 @@ ffo_status solve_impl(int64_t n, int64_t k, int64_t m, int64_t T, const double* 
   sv.info = D(oinfo); sv.status = (int32_t*)(B + ostat); sv.w_out = w_out; sv.y_out = y_out;
   sv.w_init = w_init; sv.y_init = y_init;
   HIPCHK(fill(B + oxb, nxbuf * 8, 0u, hs));
-  HIPCHK(fill(B + obar, 8, 0u, hs));
+  HIPCHK(fill(B + obar, 8 * ffo::BAR_WORDS, 0u, hs));
   HIPCHK(fill(B + oinfo, ffo::INFO_LEN * 8, 0u, hs));
   HIPCHK(fill(B + ostat, 4, 0xffffffffu, hs));
   if (ev) HIPCHK(hipEventRecord(ev[1], hs));
@@ -1035,7 +1050,7 @@ ffo_status ffo_adjoint(int64_t n, int64_t k, int64_t m, int64_t T, const double*
   p.n = (int)n; p.k = (int)k; p.m = (int)m; p.P = (int)P; p.Tp = (int)Tp; p.nr = nr;
   p.multi = T > 0 ? 1 : 0; p.ldk = ldk; p.kscaled = 1;
   const int cus = std::max(1, prop.multiProcessorCount);
-  int nwg = opt.workgroups > 0 ? opt.workgroups : (int)std::min<int64_t>(cus, (n + 63) / 64);
+  int nwg = opt.workgroups > 0 ? opt.workgroups : default_workgroups(n, cus);
   nwg = std::max(1, std::min<int>(nwg, (int)n));
   nwg = std::min(nwg, cus);
   const int nw = (int)((n + nwg - 1) / nwg);
@@ -1045,6 +1060,7 @@ ffo_status ffo_adjoint(int64_t n, int64_t k, int64_t m, int64_t T, const double*
   c.r_suff = opt.restart_suff; c.r_nec = opt.restart_nec; c.r_art = opt.restart_art;
   c.rho = opt.reflection; c.eta_safety = 0.95; c.max_iter = opt.max_iter;
   c.check_every = opt.check_every; c.xmode = ffo::XM_ATOMIC; c.nwg = nwg; c.npow = 40;
+  c.xgroups = xgroups_for(nwg);
   c.verbose = opt.verbose; c.nw = nw; c.spin_limit = 1u << 26; c.wall_hz = (double)wall_khz * 1e3;
   c.prec = ffo::PREC_FP64; c.spec = 0; c.lds_state = 0;
   c.vmax = ffo::adjoint_vmax(p);
@@ -1068,7 +1084,7 @@ ffo_status ffo_adjoint(int64_t n, int64_t k, int64_t m, int64_t T, const double*
   size_t osc[8];
   for (auto& o : osc) o = carve(Tpn, 8);
   const size_t ogG = carve((size_t)n * std::max<int64_t>(k, 1), 8);
-  const size_t oxb = carve((size_t)3 * c.vmax, 8), obar = carve(1, 8);
+  const size_t oxb = carve((size_t)3 * ffo::XG_MAX * c.vmax, 8), obar = carve(ffo::BAR_WORDS, 8);
   const size_t oinfo = carve(ffo::INFO_LEN, 8), ostat = carve(1, 4), oflag = carve(1, 4);
   const size_t total = off;
   const size_t hk = align_up((size_t)std::max<int64_t>(k * k, 1) * 8);
@@ -1123,9 +1139,9 @@ ffo_status ffo_adjoint(int64_t n, int64_t k, int64_t m, int64_t T, const double*
   for (int attempt = 0; attempt < 2; ++attempt) {
     ffo::DevControl ca = c;
     ca.max_iter = attempt == 0 ? first_cap : std::max<int64_t>(1, opt.max_iter - used);
-    HIPCHK(hipMemsetAsync(B + oxb, 0, (size_t)3 * c.vmax * 8, hs));
-    HIPCHK(hipMemsetAsync(B + obar, 0, 8, hs));
-    HIPCHK(hipMemsetAsync(B + oinfo, 0, ffo::INFO_LEN * 8, hs));
+    HIPCHK(fill(B + oxb, (size_t)3 * ffo::XG_MAX * c.vmax * 8, 0u, hs));
+    HIPCHK(fill(B + obar, 8 * ffo::BAR_WORDS, 0u, hs));
+    HIPCHK(fill(B + oinfo, ffo::INFO_LEN * 8, 0u, hs));
     HIPCHK(hipMemsetAsync(B + ostat, 0xff, 4, hs));
     if (int e = ffo::launch_adjoint(p, a, ca, weights[attempt], stream, lds))
       return fail(FFO_EDEVICE, std::string("cooperative launch of the adjoint kernel failed: ") +
@@ -1454,7 +1470,7 @@ ffo_status ffo_solve_batched(int64_t B, const int64_t* n_b, int64_t n_max, int64
                    h[ffo::IX_T_B1S] * 1e3, h[ffo::IX_T_B2] * 1e3, h[ffo::IX_T_B3] * 1e3);
     };
     show("slowest", slow);
-    if (std::getenv("FFO_BATCH_ALL"))
+    if (opt.verbose >= 2)
       for (int64_t b = 0; b < B; ++b) show("every", b);
   }
   if (worst == FFO_NOT_CONVERGED) g_err = "iteration limit reached for at least one instance";

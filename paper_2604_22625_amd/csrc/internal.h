@@ -9,6 +9,11 @@ namespace ffo {
 // Exchange modes: device-scope atomic adds, per-workgroup slots summed in a fixed order,
 // or (a single-workgroup team) LDS only.
 enum XMode : int32_t { XM_ATOMIC = 0, XM_GATHER = 1, XM_LOCAL = 2 };
+// Atomic exchange over several copies of the slot: at most XG_MAX copies; barrier
+// counters XGSTRIDE words apart (bar[0] and bar[XGSTRIDE * (1 + g)], one cache line each).
+constexpr int XG_MAX = 8;
+constexpr int XGSTRIDE = 32;
+constexpr int BAR_WORDS = XGSTRIDE * (1 + XG_MAX);
 
 // Status codes written by the device (mirror ffo_status).
 enum DevStatus : int32_t {
@@ -76,6 +81,7 @@ struct DevControl {
   int32_t lists;        // 1: publish breakpoint lists with the statistics (blist non-null)
   int32_t infeas;       // 1: test the exposure-dual displacement for an infeasibility certificate
   double omega0;        // starting primal weight (> 0)
+  int32_t xgroups;      // atomic exchange: copies of the slot (workgroup w adds into copy w % xgroups)
 };
 
 // Breakpoint lists: per workgroup and period, a count and LIST_CAP entries

@@ -186,50 +186,70 @@ __global__ __launch_bounds__(256) void k_rm_solve(int n, int nchunk, int min_obs
   valid[i] = ok ? 1 : 0;
 }
 
-// Sigma_f = (Fr - mean)^T (Fr - mean) / (days - 1), one workgroup, fixed-order sums.
+// Sigma_f = (Fr - mean)^T (Fr - mean) / (days - 1), one workgroup: each thread sums its
+// days for all P means (pass 1) and all P(P+1)/2 centred products (pass 2); one
+// fixed-order workgroup reduction per pass.
+template <int NV>
+__device__ __forceinline__ void block_sum(double (&v)[NV], double* red) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+  for (int q = 0; q < NV; ++q) {
+    double x = v[q];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
+    if (lane == 0) red[w * NV + q] = x;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < NV; ++q) v[q] = red[q] + red[NV + q] + red[2 * NV + q] + red[3 * NV + q];
+  __syncthreads();
+}
+
 template <int P>
 __global__ __launch_bounds__(256) void k_rm_cov(int days, const double* __restrict__ Fr, double* __restrict__ Sf) {
-  __shared__ double mean[P];
-  __shared__ double red[256];
-  const int t = threadIdx.x;
-  for (int a = 0; a < P; ++a) {
-    double v = 0.0;
-    for (int k = t; k < days; k += 256) v += Fr[(size_t)k * P + a];
-    red[t] = v;
-    __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
-      if (t < w) red[t] += red[t + w];
-      __syncthreads();
-    }
-    if (t == 0) mean[a] = red[0] / (double)days;
-    __syncthreads();
+  constexpr int G = P * (P + 1) / 2;
+  __shared__ double red[4 * G];
+  double mu[P];
+#pragma unroll
+  for (int a = 0; a < P; ++a) mu[a] = 0.0;
+  for (int k = threadIdx.x; k < days; k += 256)
+#pragma unroll
+    for (int a = 0; a < P; ++a) mu[a] += Fr[(size_t)k * P + a];
+  block_sum<P>(mu, red);
+#pragma unroll
+  for (int a = 0; a < P; ++a) mu[a] /= (double)days;
+  double c[G];
+#pragma unroll
+  for (int g = 0; g < G; ++g) c[g] = 0.0;
+  for (int k = threadIdx.x; k < days; k += 256) {
+    double f[P];
+#pragma unroll
+    for (int a = 0; a < P; ++a) f[a] = Fr[(size_t)k * P + a] - mu[a];
+    int g = 0;
+#pragma unroll
+    for (int a = 0; a < P; ++a)
+#pragma unroll
+      for (int b = a; b < P; ++b) { c[g] = fma(f[a], f[b], c[g]); ++g; }
   }
-  for (int a = 0; a < P; ++a)
-    for (int b = a; b < P; ++b) {
-      double v = 0.0;
-      for (int k = t; k < days; k += 256) v = fma(Fr[(size_t)k * P + a] - mean[a], Fr[(size_t)k * P + b] - mean[b], v);
-      red[t] = v;
-      __syncthreads();
-      for (int w = 128; w > 0; w >>= 1) {
-        if (t < w) red[t] += red[t + w];
-        __syncthreads();
+  block_sum<G>(c, red);
+  if (threadIdx.x == 0) {
+    int g = 0;
+    for (int a = 0; a < P; ++a)
+      for (int b = a; b < P; ++b) {
+        const double v = c[g++] / (double)(days - 1);
+        Sf[a * P + b] = v;
+        Sf[b * P + a] = v;
       }
-      if (t == 0) {
-        const double c = red[0] / (double)(days - 1);
-        Sf[a * P + b] = c;
-        Sf[b * P + a] = c;
-      }
-      __syncthreads();
-    }
+  }
 }
 
 template <int P>
 int launch_rm(int days, int n, const double* R, const double* Fr, const uint8_t* mask, int min_obs, double* part,
               double* beta, double* Sf, double* D, int32_t* valid, hipStream_t st) {
   const int nchunk = (days + RM_CHUNK - 1) / RM_CHUNK;
+  hipLaunchKernelGGL(k_rm_cov<P>, dim3(1), dim3(256), 0, st, days, Fr, Sf);
   hipLaunchKernelGGL(k_rm_partial<P>, dim3((n + 63) / 64, nchunk), dim3(256), 0, st, days, n, R, Fr, mask, part);
   hipLaunchKernelGGL(k_rm_solve<P>, dim3((n + 255) / 256), dim3(256), 0, st, n, nchunk, min_obs, part, beta, D, valid);
-  hipLaunchKernelGGL(k_rm_cov<P>, dim3(1), dim3(256), 0, st, days, Fr, Sf);
   return (int)hipGetLastError();
 }
 

@@ -141,8 +141,9 @@ struct Ctx {
   int i0, nwa;            // owned assets [i0, i0 + nwa)
   unsigned long long epoch;
   double* xbuf;
-  unsigned long long* bar;
+  unsigned long long* bar;  // [0]: arrivals of groups; [XGSTRIDE * (1 + g)]: arrivals in group g
   int vmax, xmode, P;
+  int ng, grp, gsize;     // atomic mode: copies of the exchange slot, this workgroup's copy, its users
   int mx_lo, mx_hi;       // exchange indices lo + STW*t + 1 in [mx_lo, mx_hi) combine by max
   uint32_t spin_limit;
   ldbl* tot;              // LDS [vmax]
@@ -164,7 +165,7 @@ __device__ __forceinline__ void put(const Ctx& c, int j, double v) {
   } else if (c.xmode == XM_GATHER) {
     std_(&c.xbuf[((size_t)(c.epoch & 1) * c.nwg + c.wg) * c.vmax + j], v);
   } else if (v != 0.0) {
-    addd(&c.xbuf[(size_t)(c.epoch % 3) * c.vmax + j], v);
+    addd(&c.xbuf[((size_t)(c.epoch % 3) * c.ng + c.grp) * c.vmax + j], v);
   }
 }
 
@@ -182,7 +183,7 @@ __device__ __forceinline__ void put_max(const Ctx& c, int j, double v) {
   } else if (c.xmode == XM_GATHER) {
     std_(&c.xbuf[((size_t)(c.epoch & 1) * c.nwg + c.wg) * c.vmax + j], v);
   } else if (v > 0.0) {
-    unsigned long long* a = (unsigned long long*)&c.xbuf[(size_t)(c.epoch % 3) * c.vmax + j];
+    unsigned long long* a = (unsigned long long*)&c.xbuf[((size_t)(c.epoch % 3) * c.ng + c.grp) * c.vmax + j];
     __hip_atomic_fetch_max(a, (unsigned long long)__double_as_longlong(v), __ATOMIC_RELAXED,
                            __HIP_MEMORY_SCOPE_AGENT);
   }
@@ -201,7 +202,7 @@ __device__ __forceinline__ PutTo put_to(const Ctx& c) {
   q.mode = c.xmode;
   q.l = c.lslot ? c.lslot + (size_t)(c.epoch % 3) * c.vmax : nullptr;
   q.g = c.xmode == XM_GATHER ? c.xbuf + ((size_t)(c.epoch & 1) * c.nwg + c.wg) * c.vmax
-                             : c.xbuf + (size_t)(c.epoch % 3) * c.vmax;
+                             : c.xbuf + ((size_t)(c.epoch % 3) * c.ng + c.grp) * c.vmax;
   return q;
 }
 
@@ -238,8 +239,19 @@ __device__ __forceinline__ bool xsync(Ctx& c, int V) {
   if (c.tid == 0) {
     const long long t0 = wall_clock64();
     c.t_pre += t0 - tp0;
-    const unsigned long long target = (c.epoch + 1) * (unsigned long long)c.nwg;
-    __hip_atomic_fetch_add(c.bar, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    unsigned long long target;
+    if (c.ng > 1) {
+      // two-level arrival: the last workgroup of each group arrives for the group, so
+      // at most max(group size, groups) read-modify-writes meet on one counter
+      target = (c.epoch + 1) * (unsigned long long)c.ng;
+      const unsigned long long gt = (c.epoch + 1) * (unsigned long long)c.gsize;
+      if (__hip_atomic_fetch_add(c.bar + XGSTRIDE * (1 + c.grp), 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) +
+              1 == gt)
+        __hip_atomic_fetch_add(c.bar, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    } else {
+      target = (c.epoch + 1) * (unsigned long long)c.nwg;
+      __hip_atomic_fetch_add(c.bar, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
     uint32_t spins = 0;
     int ok = 1;
     while (__hip_atomic_load(c.bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
@@ -263,12 +275,47 @@ __device__ __forceinline__ bool xsync(Ctx& c, int V) {
       c.tot[j] = s;
     }
   } else {
-    const double* base = c.xbuf + (size_t)(c.epoch % 3) * c.vmax;
-    for (int j = c.tid; j < V; j += TB) c.tot[j] = ldd(&base[j]);
+    const double* base = c.xbuf + (size_t)(c.epoch % 3) * c.ng * c.vmax;
+    if (c.ng == 1) {
+      // four loads in flight per thread
+      for (int j = c.tid; j < V; j += 4 * TB) {
+        double u[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) u[r] = j + r * TB < V ? ldd(&base[j + r * TB]) : 0.0;
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+          if (j + r * TB < V) c.tot[j + r * TB] = u[r];
+      }
+    } else {
+      // the copies combine in a fixed order (sum, or max for the max-combined entries);
+      // two totals per thread and step, every copy's load issued before the first use
+      for (int j = c.tid; j < V; j += 2 * TB) {
+        double u[2][XG_MAX];
+#pragma unroll
+        for (int r = 0; r < 2; ++r)
+#pragma unroll
+          for (int g = 0; g < XG_MAX; ++g)
+            u[r][g] = (g < c.ng && j + r * TB < V) ? ldd(&base[(size_t)g * c.vmax + j + r * TB]) : 0.0;
+#pragma unroll
+        for (int r = 0; r < 2; ++r) {
+          const int jj = j + r * TB;
+          double t = u[r][0];
+          if (jj >= c.mx_lo && jj < c.mx_hi && (jj - c.mx_lo) % STW == 1) {
+#pragma unroll
+            for (int g = 1; g < XG_MAX; ++g) t = fmax(t, u[r][g]);
+          } else {
+#pragma unroll
+            for (int g = 1; g < XG_MAX; ++g) t += u[r][g];
+          }
+          if (jj < V) c.tot[jj] = t;
+        }
+      }
+    }
     // clear the slot used two exchanges from now (its last readers passed this barrier)
-    double* z = c.xbuf + (size_t)((c.epoch + 2) % 3) * c.vmax;
-    const int per = (c.vmax + c.nwg - 1) / c.nwg;
-    const int j0 = c.wg * per, j1 = min(c.vmax, j0 + per);
+    double* z = c.xbuf + (size_t)((c.epoch + 2) % 3) * c.ng * c.vmax;
+    const int zl = c.ng * c.vmax;
+    const int per = (zl + c.nwg - 1) / c.nwg;
+    const int j0 = c.wg * per, j1 = min(zl, j0 + per);
     for (int j = j0 + c.tid; j < j1; j += TB) std_(&z[j], 0.0);
   }
   __syncthreads();
@@ -1115,6 +1162,9 @@ __device__ __forceinline__ void solve_body(const DevProblem& p, const DevState& 
   c.bar = s.bar;
   c.vmax = ctl.vmax;
   c.xmode = ctl.xmode;
+  c.ng = ctl.xmode == XM_ATOMIC ? max(1, min(ctl.xgroups, min(XG_MAX, nwg))) : 1;
+  c.grp = wg % c.ng;
+  c.gsize = (nwg - c.grp + c.ng - 1) / c.ng;
   c.P = P;
   c.spin_limit = ctl.spin_limit;
   c.mx_lo = c.mx_hi = 0;
@@ -2101,6 +2151,9 @@ __global__ __launch_bounds__(TB) void k_adjoint(DevProblem p, AdjState a, DevCon
   c.bar = a.bar;
   c.vmax = ctl.vmax;
   c.xmode = ctl.xmode;
+  c.ng = ctl.xmode == XM_ATOMIC ? max(1, min(ctl.xgroups, min(XG_MAX, (int)gridDim.x))) : 1;
+  c.grp = c.wg % c.ng;
+  c.gsize = (c.nwg - c.grp + c.ng - 1) / c.ng;
   c.P = P;
   c.spin_limit = ctl.spin_limit;
   c.mx_lo = c.mx_hi = 0;
