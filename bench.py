@@ -33,7 +33,7 @@ if ROOT not in sys.path:
 METRIC = "solves/s to 1e-6 rel KKT (n=5000; T=20); batched/FP32 vs plain; HBM % peak"
 HBM_PEAK_GBS = 8000.0
 COUNTERS = os.path.join(ROOT, "profiles", "k_solve_n5000_fp64.md")
-KERNEL_SOURCES = ["solve_kernel.hip", "setup_kernels.hip", "ffolio_host.hip", "internal.h"]
+KERNEL_SOURCES = ["solve_kernel.hip", "setup_kernels.hip", "ffolio_host.hip", "internal.h", "cost_math.h"]
 
 
 def kernel_source_hash():
@@ -68,7 +68,10 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--config", type=int, default=1)
+    ap.add_argument("--config", type=int, default=1,
+                    help="1: the headline workload (n=5000 single-period, seeds 1-10); 2: T=20 n=3000 multi-period "
+                         "(one JSON line, no comparison legs); 3: only the 256-instance batch in the lockstep form "
+                         "(for profiling)")
     ap.add_argument("--tol", type=float, default=1e-6)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-max-iter", type=int, default=40000)
@@ -319,6 +322,29 @@ def comparisons(ff, torch, dev, dev_insts, tol, plain_value):
     return out
 
 
+def batched_only(ff, torch, a):
+    """The 256-instance batch (uneven n on one shared universe) in the lockstep form: W
+    warm-up batches, then S timed ones; batch time, iterations and the matrix-core rate of
+    the two shared-row products."""
+    from synth import make_config
+    batch = make_config(3)
+    nb = np.asarray(batch["n_b"], dtype=np.float64)
+    for _ in range(a.warmup):
+        ff.solve_batched(batch, tol=a.tol, form="lockstep")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(a.steps):
+        _, infos = ff.solve_batched(batch, tol=a.tol, form="lockstep")
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / max(1, a.steps)
+    iters = np.array([i.iters for i in infos], dtype=np.float64)
+    flops = float(np.sum(4.0 * nb * (int(batch["m"]) + int(batch["k"])) * iters))
+    return {"workload": "256 single-period instances, n log-uniform in [500, 8000], k=40, m=30, lockstep form, FP64",
+            "batch_ms": dt * 1e3, "solves_per_s": len(infos) / dt, "iters_max": int(iters.max()),
+            "iters_mean": float(iters.mean()), "all_ok": all(i.status == 0 for i in infos),
+            "mfma_fp64_tflops": flops / dt / 1e12}
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -338,6 +364,9 @@ def main():
         sys.exit(1)
     if a.paper_grid:
         print(json.dumps(paper_grid(ff, torch, a)), flush=True)
+        return
+    if a.config == 3:
+        print(json.dumps(batched_only(ff, torch, a)), flush=True)
         return
     cfg = CONFIGS[a.config]
     seeds = list(cfg["seeds"])
@@ -395,7 +424,8 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": f"single-period portfolio solve, n={n} k={k} m={m} (sector + factor rows), d=1.5, "
+        "config": {"workload": (f"single-period portfolio solve" if T == 0 else f"multi-period portfolio solve, T={T}")
+                               + f", n={n} k={k} m={m} (sector + factor rows), d=1.5, "
                                f"seeds {seeds[0]}-{seeds[-1]}, plain FP64, to rel KKT {a.tol:g}",
                    "n": n, "k": k, "m": m, "T": T, "instances_per_step": len(insts), "tol": a.tol},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
