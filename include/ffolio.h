@@ -257,10 +257,19 @@ ffo_status ffo_adjoint(int64_t n, int64_t k, int64_t m, int64_t T,
  * infos [B] (one record per instance).  d, GMV, lambda1..3 as in ffo_solve (shared).
  * Output (device): w_out [N], packed like alpha.
  * Every instance runs the same restarted Halpern PDHG as ffo_solve, to its own relative
- * KKT tolerance, on a team of workgroups sized to its asset count; all teams of a launch
- * are resident at once and never wait for each other (batches larger than the resident
- * grid run in several launches, largest instances first).  opt->precision: FFO_FP64,
- * FFO_FP32 or FFO_FP32_BF16K; opt->workgroups is ignored; statuses as in ffo_solve.
+ * KKT tolerance, in one of two forms (opt->batched_form):
+ *   lockstep: every unconverged instance advances one iteration per step; a step is a
+ *     few kernels replayed from a captured graph: the products over the shared rows as
+ *     float64 matrix-core GEMMs with ragged columns, then per-instance passes (budget
+ *     multiplier, dual prox, Halpern step); converged instances are compacted out at
+ *     every check; tile sizes come from the library's autotuner (opt->autotune).  The
+ *     default for FFO_FP64 with m + k <= 128, B <= 65536, n_max <= 2^22.
+ *   teams: each instance runs the solve kernel's loop on a team of workgroups sized to
+ *     its asset count; all teams of a launch are resident at once and never wait for each
+ *     other (batches larger than the resident grid run in several launches, largest
+ *     instances first).  Every precision.
+ * opt->precision: FFO_FP64, FFO_FP32 or FFO_FP32_BF16K (the last two: team form);
+ * opt->workgroups is ignored; statuses as in ffo_solve.
  * Returns FFO_OK if every instance converged, else the most severe instance status
  * (FFO_EDEVICE > FFO_NUMERIC > FFO_TIMEOUT > FFO_NOT_CONVERGED); infos[b].status holds
  * each instance's own status.  FFO_EINVAL is returned before any device work.
