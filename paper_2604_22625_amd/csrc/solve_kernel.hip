@@ -523,7 +523,9 @@ __device__ __forceinline__ void kty_all(const Ctx& c, const SV& v, const ldbl* y
   }
   const int ne = P * c.nwa;
   if (ne == 0) { __syncthreads(); return; }
-  const int G = ne <= TB / 4 ? 4 : (ne <= TB / 2 ? 2 : 1);
+  // as many thread groups over the rows as the workgroup holds copies of the slice's
+  // (t, li) pairs: short slices keep every thread busy on a shorter chain
+  const int G = ne <= TB / 16 ? 16 : (ne <= TB / 8 ? 8 : (ne <= TB / 4 ? 4 : (ne <= TB / 2 ? 2 : 1)));
   if (G > 1) {
     const int per = TB / G, g = c.tid / per, e = c.tid - g * per;
     double r = 0.0;
@@ -630,12 +632,12 @@ __device__ __forceinline__ void rows_dev(const KG* K, int ldk, int i0, const ldb
 // Row products over the owned assets with four lanes per row: for every e = t*nr + j,
 // emit(e, a) with a[q] = sum_li K~[j][li] xq[t*nw + li] (x1, and x2 when NX = 2; LDS).
 // All threads call (the lane shuffles need full waves).
-template <int NX, class SV, class F>
-__device__ __forceinline__ void rows_prod_lds(const Ctx& c, const SV& v, const ldbl* x1, const ldbl* x2, int nw, int P, int nr,
-                              F emit) {
-  const int q = c.tid & 3, ntot = P * nr;
-  for (int base = 0; base < ntot; base += TB / 4) {
-    const int e = base + (c.tid >> 2);
+template <int NX, int LPR, class SV, class F>
+__device__ __forceinline__ void rows_prod_lds_l(const Ctx& c, const SV& v, const ldbl* x1, const ldbl* x2, int nw, int P,
+                                                int nr, F emit) {
+  const int q = c.tid & (LPR - 1), ntot = P * nr;
+  for (int base = 0; base < ntot; base += TB / LPR) {
+    const int e = base + c.tid / LPR;
     double a[NX];
 #pragma unroll
     for (int u = 0; u < NX; ++u) a[u] = 0.0;
@@ -644,16 +646,27 @@ __device__ __forceinline__ void rows_prod_lds(const Ctx& c, const SV& v, const l
       const ldbl* xa = x1 + t * nw;
       const ldbl* xb = (NX > 1 ? x2 : x1) + t * nw;
 #pragma unroll 4
-      for (int li = q; li < c.nwa; li += 4) {
+      for (int li = q; li < c.nwa; li += LPR) {
         const double kv = v.Kat(j, li);
         a[0] = fma(kv, xa[li], a[0]);
         if (NX > 1) a[NX - 1] = fma(kv, xb[li], a[NX - 1]);
       }
     }
+    if constexpr (LPR == 4) {
 #pragma unroll
-    for (int u = 0; u < NX; ++u) a[u] = sum4(a[u]);
+      for (int u = 0; u < NX; ++u) a[u] = sum4(a[u]);
+    }
     if (q == 0 && e < ntot) emit(e, a);
   }
+}
+
+// Lanes per row: one for slices of up to 32 assets (every lane owns a row, so a pass
+// covers 256 rows with no lane reduction), else four with a DPP quad sum.
+template <int NX, class SV, class F>
+__device__ __forceinline__ void rows_prod_lds(const Ctx& c, const SV& v, const ldbl* x1, const ldbl* x2, int nw, int P, int nr,
+                              F emit) {
+  if (c.nwa <= 32) rows_prod_lds_l<NX, 1>(c, v, x1, x2, nw, P, nr, emit);
+  else rows_prod_lds_l<NX, 4>(c, v, x1, x2, nw, P, nr, emit);
 }
 
 // Short slices (the usual case, rows in LDS or not): four lanes per row.  Long slices
