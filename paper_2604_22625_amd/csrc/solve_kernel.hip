@@ -961,22 +961,37 @@ __device__ __forceinline__ double* list_at(const double* blist, int par, int nwg
 // appends, so all workgroups agree.  Whole workgroup; ptot is zero on entry and returned
 // holding the entry counts.
 __device__ __noinline__ void gather_pool(const double* blist, int par, int nwg, int P, lint* gneed, lint* ptot,
-                                            lint* poff, lint* pfill, ldbl* pool) {
+                                            lint* poff, lint* pfill, lint* nidx, ldbl* pool) {
   constexpr int U = 8;   // pairs per thread with loads in flight together
-  const int npair = P * nwg, tid = threadIdx.x;
+  const int tid = threadIdx.x;
+  // the periods that want their lists, in increasing order, in nidx[0, nidx[P]) (wave 0):
+  // the (period, workgroup) pairs below run over those periods only
+  if (tid < 64) {
+    int carry = 0;
+    for (int t0 = 0; t0 < P; t0 += 64) {
+      const int t = t0 + tid;
+      const bool nd = t < P && gneed[t] > 0;
+      const unsigned long long bal = __ballot(nd);
+      if (nd) nidx[carry + __popcll(bal & ((1ull << tid) - 1ull))] = t;
+      carry += __popcll(bal);
+    }
+    if (tid == 0) nidx[P] = carry;
+  }
+  __syncthreads();
+  const int npair = nidx[P] * nwg;
   const bool held = npair <= TB * U;   // one pass covers every pair: the counts stay in registers
   double cn[U];
   // pass 1: per-period entry counts
   for (int base = tid; base < npair; base += TB * U) {
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      const int idx = base + u * TB, t = idx / nwg, w = idx - t * nwg;
-      cn[u] = (idx < npair && gneed[t] > 0) ? ldd(list_at(blist, par, nwg, P, w, t)) : 0.0;
+      const int idx = base + u * TB, r = idx / nwg, w = idx - r * nwg;
+      cn[u] = idx < npair ? ldd(list_at(blist, par, nwg, P, w, nidx[r])) : 0.0;
     }
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       if (!(cn[u] > 0.0)) continue;
-      const int t = (base + u * TB) / nwg, cnt = (int)cn[u];
+      const int t = nidx[(base + u * TB) / nwg], cnt = (int)cn[u];
       if (cnt > LIST_CAP) gneed[t] = -1;
       __hip_atomic_fetch_add(&ptot[t], min(cnt, LIST_CAP), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
     }
@@ -1012,13 +1027,15 @@ __device__ __noinline__ void gather_pool(const double* blist, int par, int nwg, 
     if (!held) {
 #pragma unroll
       for (int u = 0; u < U; ++u) {
-        const int idx = base + u * TB, t = idx / nwg, w = idx - t * nwg;
-        cn[u] = (idx < npair && gneed[t] > 0) ? ldd(list_at(blist, par, nwg, P, w, t)) : 0.0;
+        const int idx = base + u * TB, r = idx / nwg, w = idx - r * nwg;
+        cn[u] = (idx < npair && gneed[nidx[r]] > 0) ? ldd(list_at(blist, par, nwg, P, w, nidx[r])) : 0.0;
       }
     }
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      const int idx = base + u * TB, t = idx / nwg, w = idx - t * nwg;
+      const int idx = base + u * TB, r = idx / nwg, w = idx - r * nwg;
+      if (idx >= npair) continue;
+      const int t = nidx[r];
       if (!(cn[u] > 0.0) || gneed[t] <= 0) continue;
       const int kmax = min((int)cn[u], LIST_CAP);
       const int pos = poff[t] + __hip_atomic_fetch_add(&pfill[t], kmax, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
@@ -1284,6 +1301,7 @@ __device__ __forceinline__ void solve_body(const DevProblem& p, const DevState& 
   lint* ptot = lcnt + P;                    // per period: gathered entries, their first pool
   lint* poff = ptot + P;                    // entry, and the fill counter
   lint* pfill = poff + P;
+  lint* nidx = pfill + P;                   // [P + 1]: periods gathering lists, their count
   c.tot = tot;
   c.red = red;
   c.flag = iflag;
@@ -1534,7 +1552,7 @@ __device__ __forceinline__ void solve_body(const DevProblem& p, const DevState& 
           int anyg = 0;
           for (int t = 0; t < P; ++t) anyg |= gneed[t];
           if (anyg) {
-            gather_pool(s.blist, lpar, nwg, P, gneed, ptot, poff, pfill, pool);
+            gather_pool(s.blist, lpar, nwg, P, gneed, ptot, poff, pfill, nidx, pool);
             __syncthreads();
           }
         }
@@ -2690,7 +2708,7 @@ size_t solve_lds_bytes(const DevProblem& p, const DevControl& c) {
   if (c.xmode == XM_LOCAL) d += 3 * (size_t)c.vmax;
   if (c.lds_state) d += f32 ? state_lds_doubles<float>(P, Tp, nw) : state_lds_doubles<double>(P, Tp, nw);
   if (c.lists) d += NPOOL * 4;
-  d += (sizeof(Scal) + 7) / 8 + 2 + 5 * P + 1;   // flags and nine per-period integer arrays
+  d += (sizeof(Scal) + 7) / 8 + 2 + 5 * P + 1;   // flags, nine per-period integer arrays and nidx[P + 1]
   return d * sizeof(double);
 }
 
