@@ -10,10 +10,11 @@ namespace ffo {
 // or (a single-workgroup team) LDS only.
 enum XMode : int32_t { XM_ATOMIC = 0, XM_GATHER = 1, XM_LOCAL = 2 };
 // Atomic exchange over several copies of the slot: at most XG_MAX copies; barrier
-// counters XGSTRIDE words apart (bar[0] and bar[XGSTRIDE * (1 + g)], one cache line each).
+// words XGSTRIDE apart, one cache line each: bar[0], the group counters
+// bar[XGSTRIDE * (1 + g)] and the group release flags bar[XGSTRIDE * (1 + XG_MAX + g)].
 constexpr int XG_MAX = 8;
 constexpr int XGSTRIDE = 32;
-constexpr int BAR_WORDS = XGSTRIDE * (1 + XG_MAX);
+constexpr int BAR_WORDS = XGSTRIDE * (1 + 2 * XG_MAX);
 
 // Status codes written by the device (mirror ffo_status).
 enum DevStatus : int32_t {

@@ -141,7 +141,8 @@ struct Ctx {
   int i0, nwa;            // owned assets [i0, i0 + nwa)
   unsigned long long epoch;
   double* xbuf;
-  unsigned long long* bar;  // [0]: arrivals of groups; [XGSTRIDE * (1 + g)]: arrivals in group g
+  unsigned long long* bar;  // [0]: arrivals of groups; [XGSTRIDE * (1 + g)]: arrivals in group g;
+                            // [XGSTRIDE * (1 + XG_MAX + g)]: release of group g (last epoch)
   int vmax, xmode, P;
   int ng, grp, gsize;     // atomic mode: copies of the exchange slot, this workgroup's copy, its users
   int mx_lo, mx_hi;       // exchange indices lo + STW*t + 1 in [mx_lo, mx_hi) combine by max
@@ -240,21 +241,30 @@ __device__ __forceinline__ bool xsync(Ctx& c, int V) {
     const long long t0 = wall_clock64();
     c.t_pre += t0 - tp0;
     unsigned long long target;
+    const unsigned long long* poll = c.bar;
     if (c.ng > 1) {
       // two-level arrival: the last workgroup of each group arrives for the group, so
-      // at most max(group size, groups) read-modify-writes meet on one counter
-      target = (c.epoch + 1) * (unsigned long long)c.ng;
+      // at most max(group size, groups) read-modify-writes meet on one counter; the
+      // last group's arrival releases every group through its own flag, so each flag
+      // is polled by one group only
+      target = c.epoch + 1;
       const unsigned long long gt = (c.epoch + 1) * (unsigned long long)c.gsize;
       if (__hip_atomic_fetch_add(c.bar + XGSTRIDE * (1 + c.grp), 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) +
-              1 == gt)
-        __hip_atomic_fetch_add(c.bar, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+              1 == gt) {
+        if (__hip_atomic_fetch_add(c.bar, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) + 1 ==
+            (c.epoch + 1) * (unsigned long long)c.ng)
+          for (int g = 0; g < c.ng; ++g)
+            __hip_atomic_store(c.bar + XGSTRIDE * (1 + XG_MAX + g), c.epoch + 1, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+      }
+      poll = c.bar + XGSTRIDE * (1 + XG_MAX + c.grp);
     } else {
       target = (c.epoch + 1) * (unsigned long long)c.nwg;
       __hip_atomic_fetch_add(c.bar, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
     uint32_t spins = 0;
     int ok = 1;
-    while (__hip_atomic_load(c.bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+    while (__hip_atomic_load(poll, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
       __builtin_amdgcn_s_sleep(1);
       if (++spins > c.spin_limit) { ok = 0; break; }
     }
