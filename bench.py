@@ -84,6 +84,10 @@ def parse():
                          "of the paper's Table 1 (one JSON line)")
     ap.add_argument("--paper-n", type=int, default=1000, help="assets per paper-shaped instance")
     ap.add_argument("--paper-dates", type=int, default=21, help="dates per grid point (the paper: 21)")
+    ap.add_argument("--stress-n", type=int, default=0, metavar="N",
+                    help="only time single-period FP64 solves at n=N (k=60, m=80, rows beyond LDS, read from "
+                         "device memory every iteration) and print one JSON line (for profiling the "
+                         "bandwidth-bound form)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only copy a float64 buffer of MIB MiB three times on the GPU (one read and one write "
                          "of MIB MiB each) and exit: the known-size reference that scales rocprofv3's "
@@ -287,6 +291,9 @@ def comparisons(ff, torch, dev, dev_insts, tol, plain_value):
     fwd_bwd("fp32")
     dt, (finfo, ainfo, ga32) = _timed(torch, lambda: fwd_bwd("fp32"), 1)
     rel = float(torch.linalg.norm(ga32 - ga64) / torch.linalg.norm(ga64))
+    # the bandwidth-bound form: n = 400,000, constraint rows (448 MB) beyond LDS and the
+    # 256 MB last-level cache, streamed from HBM twice per iteration
+    out["single_period_n400000_fp64_device_rows"] = stress_leg(ff, torch, 400000)
     # risk-model construction (paper Section 3.2): 504 days x 5000 assets, six factors,
     # 15% of the assets with a shorter history; one streaming pass over the returns
     from synth import returns_panel
@@ -320,6 +327,33 @@ def comparisons(ff, torch, dev, dev_insts, tol, plain_value):
                                 "adjoint_rel_residual": ainfo.rel_kkt,
                                 "grad_alpha_rel_diff_vs_fp64_forward": rel}
     return out
+
+
+def stress_leg(ff, torch, n, steps=1, warmup=1, tol=1e-6):
+    """Single-period FP64 solves at n assets (k=60, m=80, seed 5): the constraint rows
+    (140 x n doubles) stay in device memory and are streamed twice per iteration, so
+    this is the form whose roofline is HBM bandwidth.  Algorithmic bytes per iteration
+    as for the headline workload."""
+    from synth import make_single
+    inst = make_single(n, 60, 80, seed=5)
+    dev = torch.device("cuda", 0)
+    d = dict(inst)
+    for kk in ("alpha", "F", "Omega", "delta", "s", "q", "A", "L", "U", "w0"):
+        d[kk] = torch.as_tensor(d[kk], dtype=torch.float64, device=dev).contiguous()
+    W = torch.empty((1, n), dtype=torch.float64, device=dev)
+    for _ in range(warmup):
+        ff.solve_instance(d, tol=tol, out=W, time_limit_s=300)
+    torch.cuda.synchronize()
+    infos = [ff.solve_instance(d, tol=tol, out=W, time_limit_s=300)[1] for _ in range(steps)]
+    torch.cuda.synchronize()
+    bpi = algorithmic_bytes_per_iter(n, 60, 80, 1, 1)
+    iters = float(np.mean([i.iters for i in infos]))
+    kms = float(np.mean([i.ms_iter for i in infos]))
+    return {"n": n, "k": 60, "m": 80, "iters": iters, "kernel_ms": kms, "us_per_iter": kms * 1e3 / iters,
+            "bytes_per_iter": bpi, "achieved_gb_s": bpi * iters / (kms * 1e-3) / 1e9,
+            "frac_of_hbm_peak": bpi * iters / (kms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+            "rows_bytes": 140 * n * 8, "status_all_ok": all(i.status == 0 for i in infos),
+            "rel_kkt_max": max(i.rel_kkt for i in infos)}
 
 
 def batched_only(ff, torch, a):
@@ -367,6 +401,10 @@ def main():
         return
     if a.config == 3:
         print(json.dumps(batched_only(ff, torch, a)), flush=True)
+        return
+    if a.stress_n:
+        print(json.dumps(stress_leg(ff, torch, a.stress_n, steps=max(1, a.steps), warmup=a.warmup, tol=a.tol)),
+              flush=True)
         return
     cfg = CONFIGS[a.config]
     seeds = list(cfg["seeds"])

@@ -465,7 +465,7 @@ __device__ __forceinline__ double kcol_dot(const SV& v, const ldbl* y, int li, i
 // (LDS).  Small slices split the rows over 2 or 4 thread groups with partials in
 // red[0, TB).  All threads call; synchronised on return.
 // The same with the rows in device memory (K~[j][li] = K[j*ldk + i0 + li] ks[j]).
-template <class KG>
+template <int AW, class KG>
 __device__ __forceinline__ void kty_dev(const KG* K, int ldk, int i0, const ldbl* ks, const ldbl* y, int P, int nr,
                                      int nw, int nwa, ldbl* red, ldbl* out) {
   const int tid = threadIdx.x, ne = P * nwa;
@@ -516,6 +516,47 @@ __device__ __forceinline__ void kty_dev(const KG* K, int ldk, int i0, const ldbl
       for (int gg = 0; gg < G; ++gg) a += red[gg * per + tid];
       out[t * nw + li] = a;
     }
+  } else if (AW > 1 && nr >= 8) {
+    // AW assets per thread and step: 8 AW row loads in flight per lane (the plain
+    // kernel's long slices; the batched kernel's register budget keeps one asset)
+    int e = tid;
+    for (; e + (AW - 1) * TB < ne; e += AW * TB) {
+      const gmem_t<KG>* col[AW];
+      const ldbl* yy[AW];
+      double acc[AW][2];
+#pragma unroll
+      for (int a = 0; a < AW; ++a) {
+        const int f = e + a * TB, t = f / nwa, l = f - t * nwa;
+        col[a] = (const gmem_t<KG>*)(K + i0 + l);
+        yy[a] = y + t * nr;
+        acc[a][0] = acc[a][1] = 0.0;
+      }
+      int j = 0;
+      for (; j + 8 <= nr; j += 8) {
+        KG kr[AW][8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+#pragma unroll
+          for (int a = 0; a < AW; ++a) kr[a][u] = gload(col[a] + (size_t)(j + u) * ldk);
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+#pragma unroll
+          for (int a = 0; a < AW; ++a) acc[a][u & 1] = fma((double)kr[a][u] * ks[j + u], yy[a][j + u], acc[a][u & 1]);
+      }
+      for (; j < nr; ++j)
+#pragma unroll
+        for (int a = 0; a < AW; ++a) acc[a][0] = fma((double)gload(col[a] + (size_t)j * ldk) * ks[j], yy[a][j], acc[a][0]);
+#pragma unroll
+      for (int a = 0; a < AW; ++a) {
+        const int f = e + a * TB, t = f / nwa, l = f - t * nwa;
+        out[t * nw + l] = acc[a][0] + acc[a][1];
+      }
+    }
+    for (; e < ne; e += TB) {
+      const int t = e / nwa, li = e - t * nwa;
+      out[t * nw + li] = dot(y + t * nr, li, 0, nr);
+    }
   } else {
     for (int e = tid; e < ne; e += TB) {
       const int t = e / nwa, li = e - t * nwa;
@@ -525,10 +566,10 @@ __device__ __forceinline__ void kty_dev(const KG* K, int ldk, int i0, const ldbl
   __syncthreads();
 }
 
-template <class SV>
+template <int AW = 1, class SV>
 __device__ __forceinline__ void kty_all(const Ctx& c, const SV& v, const ldbl* y, int P, int nr, int nw, ldbl* out) {
   if constexpr (!SV::KLDS) {
-    kty_dev(v.Kg, v.p->ldk, v.i0, v.ks, y, P, nr, nw, c.nwa, c.red, out);
+    kty_dev<AW>(v.Kg, v.p->ldk, v.i0, v.ks, y, P, nr, nw, c.nwa, c.red, out);
     return;
   }
   const int ne = P * c.nwa;
@@ -1449,7 +1490,7 @@ __device__ __forceinline__ void solve_body(const DevProblem& p, const DevState& 
 
     const long long ta0 = wall_clock64();
     // Phase A: prox inputs (signed b and 1/a) for owned (t, li).
-    kty_all(c, V, ys, P, nr, nw, xv1);
+    kty_all<LS ? 2 : 1>(c, V, ys, P, nr, nw, xv1);
     for (int e = c.tid; e < P * c.nwa; e += TB) {
       const int t = e / c.nwa, li = e % c.nwa;
       const double Ry = xv1[t * nw + li] + kty_trade(V, V.ysC, t, li);
