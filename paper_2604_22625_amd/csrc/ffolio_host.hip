@@ -531,15 +531,15 @@ ffo_status solve_impl(int64_t n, int64_t k, int64_t m, int64_t T, const double* 
                  "[ffo] status %d iters %.0f restarts %.0f spec_miss %.0f ms_rounds %.0f exchanges %.0f checks %.0f "
                  "normK %.4f nwg %d nw %d lds_k %d lds_state %d spec %d | t_power %.3f ms t_iter %.3f ms "
                  "t_check %.3f ms t_wait(wg0) %.3f ms | A %.3f B %.3f C %.3f D %.3f pre %.3f read %.3f ms "
-                 "| B1 %.3f (stats %.3f) B2 %.3f B3 %.3f ms | multisect in %.0f out %.0f\n",
+                 "| B1 %.3f (stats %.3f) B2 %.3f (gather %.3f in %.0f iterations) B3 %.3f ms | multisect in %.0f out %.0f\n",
                  (int)st, hinfo[ffo::IX_ITERS], hinfo[ffo::IX_RESTARTS], hinfo[ffo::IX_SPEC_MISS],
                  hinfo[ffo::IX_MS_ROUNDS], hinfo[ffo::IX_EXCHANGES], hinfo[ffo::IX_CHECKS], hinfo[ffo::IX_NORMK], nwg,
                  nw, c.lds_k, c.lds_state, c.spec, hinfo[ffo::IX_T_POWER] * 1e3, hinfo[ffo::IX_T_ITER] * 1e3,
                  hinfo[ffo::IX_T_CHECK] * 1e3, hinfo[ffo::IX_T_WAIT] * 1e3, hinfo[ffo::IX_T_PHA] * 1e3,
                  hinfo[ffo::IX_T_PHB] * 1e3, hinfo[ffo::IX_T_PHC] * 1e3, hinfo[ffo::IX_T_PHD] * 1e3,
                  hinfo[ffo::IX_T_PRE] * 1e3, hinfo[ffo::IX_T_READ] * 1e3, hinfo[ffo::IX_T_B1] * 1e3,
-                 hinfo[ffo::IX_T_B1S] * 1e3, hinfo[ffo::IX_T_B2] * 1e3, hinfo[ffo::IX_T_B3] * 1e3,
-                 hinfo[ffo::IX_MISS_IN], hinfo[ffo::IX_MISS_OUT]);
+                 hinfo[ffo::IX_T_B1S] * 1e3, hinfo[ffo::IX_T_B2] * 1e3, hinfo[ffo::IX_T_GATHER] * 1e3,
+                 hinfo[ffo::IX_GATHERS], hinfo[ffo::IX_T_B3] * 1e3, hinfo[ffo::IX_MISS_IN], hinfo[ffo::IX_MISS_OUT]);
   return st;
 }
 

@@ -122,7 +122,8 @@ enum InfoIdx {
   IX_ITERS = 0, IX_RESTARTS, IX_RELKKT, IX_RELPRI, IX_RELDUAL, IX_RELGAP, IX_FPR, IX_POBJ,
   IX_DOBJ, IX_OMEGA, IX_ETA, IX_NORMK, IX_SPEC_MISS, IX_EXCHANGES, IX_CHECKS, IX_T_WAIT,
   IX_T_ITER, IX_T_CHECK, IX_T_POWER, IX_MS_ROUNDS, IX_T_PHA, IX_T_PHB, IX_T_PHC, IX_T_PHD,
-  IX_T_PRE, IX_T_READ, IX_T_B1, IX_T_B2, IX_T_B3, IX_T_B1S, IX_MISS_IN, IX_MISS_OUT, INFO_LEN = 32
+  IX_T_PRE, IX_T_READ, IX_T_B1, IX_T_B2, IX_T_B3, IX_T_B1S, IX_MISS_IN, IX_MISS_OUT, IX_T_GATHER, IX_GATHERS,
+  INFO_LEN = 34
 };
 
 // Launch the persistent solve kernel (defined in solve_kernel.hip).

@@ -1012,7 +1012,8 @@ __device__ __forceinline__ double* list_at(const double* blist, int par, int nwg
 // appends, so all workgroups agree.  Whole workgroup; ptot is zero on entry and returned
 // holding the entry counts.
 __device__ __noinline__ void gather_pool(const double* blist, int par, int nwg, int P, lint* gneed, lint* ptot,
-                                            lint* poff, lint* pfill, lint* nidx, ldbl* pool) {
+                                            lint* poff, lint* pfill, lint* nidx, ldbl* pool, lint* psrc,
+                                            lint* pper) {
   constexpr int U = 8;   // pairs per thread with loads in flight together
   const int tid = threadIdx.x;
   // the periods that want their lists, in increasing order, in nidx[0, nidx[P]) (wave 0):
@@ -1073,7 +1074,8 @@ __device__ __noinline__ void gather_pool(const double* blist, int par, int nwg, 
     }
   }
   __syncthreads();
-  // pass 2: the entries
+  // pass 2: every listed entry gets its pool position and source (list slot, entry) in
+  // LDS, then one thread per entry loads it: one round trip for the whole pool
   for (int base = tid; base < npair; base += TB * U) {
     if (!held) {
 #pragma unroll
@@ -1090,41 +1092,51 @@ __device__ __noinline__ void gather_pool(const double* blist, int par, int nwg, 
       if (!(cn[u] > 0.0) || gneed[t] <= 0) continue;
       const int kmax = min((int)cn[u], LIST_CAP);
       const int pos = poff[t] + __hip_atomic_fetch_add(&pfill[t], kmax, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-      const double* L = list_at(blist, par, nwg, P, w, t) + 1;
-      for (int k0 = 0; k0 < kmax; k0 += 4) {   // four entries' loads in flight together
-        double e[16];
-#pragma unroll
-        for (int k = 0; k < 4; ++k)
-#pragma unroll
-          for (int f = 0; f < 4; ++f) e[4 * k + f] = k0 + k < kmax ? ldd(L + 4 * (k0 + k) + f) : 0.0;
-#pragma unroll
-        for (int k = 0; k < 4; ++k)
-          if (k0 + k < kmax)
-#pragma unroll
-            for (int f = 0; f < 4; ++f) pool[4 * (pos + k0 + k) + f] = e[4 * k + f];
+      for (int k = 0; k < kmax; ++k) {
+        psrc[pos + k] = (w * LIST_CAP + k);
+        pper[pos + k] = t;
       }
     }
   }
   __syncthreads();
-  // sort each period's entries in place by (|b|, asset): entry i takes its rank.  The
-  // offsets grow with the period, so entry i belongs to the last period starting at or
-  // before it.
+  // the pool's extent: the last needing period's offset plus its entries
+  int total = 0;
+  for (int r = 0; r < nidx[P]; ++r) {
+    const int t = nidx[r];
+    if (gneed[t] > 0) total = max(total, (int)poff[t] + (int)ptot[t]);
+  }
   double e0 = 0.0, e1 = 0.0, e2 = 0.0, e3 = 0.0;
+  const int i = tid;   // NPOOL == TB: one entry per thread
+  int t = -1;
+  if (i < total) {
+    t = pper[i];
+    const int src = psrc[i], w = src / LIST_CAP, k = src - w * LIST_CAP;
+    const double* L = list_at(blist, par, nwg, P, w, t) + 1 + 4 * k;
+    e0 = ldd(L); e1 = ldd(L + 1); e2 = ldd(L + 2); e3 = ldd(L + 3);
+    ldbl* q = pool + 4 * i;
+    q[0] = e0; q[1] = e1; q[2] = e2; q[3] = e3;
+  }
+  __syncthreads();
+  // sort each period's entries in place by (|b|, asset): entry i takes its rank among its
+  // period's entries (four comparisons per step)
   int dst = -1;
-  {
-    const int i = tid;   // NPOOL == TB: one entry per thread
-    int t = -1;
-    for (int u = 0; u < P; ++u)
-      if (poff[u] <= i) t = u;
-    if (t >= 0 && i < poff[t] + ptot[t]) {
-      e0 = pool[4 * i]; e1 = pool[4 * i + 1]; e2 = pool[4 * i + 2]; e3 = pool[4 * i + 3];
-      int r = 0;
-      for (int j = poff[t]; j < poff[t] + ptot[t]; ++j) {
-        const double vj = pool[4 * j], gj = pool[4 * j + 2];
-        r += (vj < e0 || (vj == e0 && gj < e2)) ? 1 : 0;
-      }
-      dst = poff[t] + r;
+  if (t >= 0) {
+    const int j0 = poff[t], j1 = j0 + ptot[t];
+    int r0 = 0, r1 = 0, r2 = 0, r3 = 0;
+    int j = j0;
+    for (; j + 4 <= j1; j += 4) {
+      const double v0 = pool[4 * j], v1 = pool[4 * j + 4], v2 = pool[4 * j + 8], v3 = pool[4 * j + 12];
+      const double g0 = pool[4 * j + 2], g1 = pool[4 * j + 6], g2 = pool[4 * j + 10], g3 = pool[4 * j + 14];
+      r0 += (v0 < e0 || (v0 == e0 && g0 < e2)) ? 1 : 0;
+      r1 += (v1 < e0 || (v1 == e0 && g1 < e2)) ? 1 : 0;
+      r2 += (v2 < e0 || (v2 == e0 && g2 < e2)) ? 1 : 0;
+      r3 += (v3 < e0 || (v3 == e0 && g3 < e2)) ? 1 : 0;
     }
+    for (; j < j1; ++j) {
+      const double vj = pool[4 * j], gj = pool[4 * j + 2];
+      r0 += (vj < e0 || (vj == e0 && gj < e2)) ? 1 : 0;
+    }
+    dst = j0 + (r0 + r1) + (r2 + r3);
   }
   __syncthreads();
   if (dst >= 0) {
@@ -1252,7 +1264,8 @@ __device__ __forceinline__ void solve_body(const DevProblem& p, const DevState& 
   c.t_wait = 0;
   c.t_pre = 0;
   c.t_read = 0;
-  long long t_phA = 0, t_phB = 0, t_phC = 0, t_phD = 0, t_b1 = 0, t_b2 = 0, t_b3 = 0, t_b1s = 0;
+  long long t_phA = 0, t_phB = 0, t_phC = 0, t_phD = 0, t_b1 = 0, t_b2 = 0, t_b3 = 0, t_b1s = 0, t_gather = 0;
+  long long n_gather = 0;
 
   // LDS layout (doubles); must match solve_lds_bytes
   ldbl* ptr = lds;
@@ -1288,7 +1301,13 @@ __device__ __forceinline__ void solve_body(const DevProblem& p, const DevState& 
   ldbl* dwd = ptr;  ptr += P;
   const bool lists = LS && ctl.lists;       // breakpoint lists (single-team launches only)
   ldbl* pool = nullptr;                     // gathered breakpoint lists (sorted)
-  if (lists) { pool = ptr; ptr += NPOOL * 4; }
+  lint* psrc = nullptr;                     // per pool entry: its list slot and entry, its period
+  lint* pper = nullptr;
+  if (lists) {
+    pool = ptr; ptr += NPOOL * 4;
+    psrc = (lint*)ptr; ptr += NPOOL / 2;
+    pper = (lint*)ptr; ptr += NPOOL / 2;
+  }
   using SV = S<KL, SL, R, KGT>;
   SV V;
   V.p = &p;
@@ -1603,8 +1622,11 @@ __device__ __forceinline__ void solve_body(const DevProblem& p, const DevState& 
           int anyg = 0;
           for (int t = 0; t < P; ++t) anyg |= gneed[t];
           if (anyg) {
-            gather_pool(s.blist, lpar, nwg, P, gneed, ptot, poff, pfill, nidx, pool);
+            const long long tg0 = wall_clock64();
+            gather_pool(s.blist, lpar, nwg, P, gneed, ptot, poff, pfill, nidx, pool, psrc, pper);
             __syncthreads();
+            t_gather += wall_clock64() - tg0;
+            ++n_gather;
           }
         }
         {
@@ -2167,6 +2189,8 @@ __device__ __forceinline__ void solve_body(const DevProblem& p, const DevState& 
     s.info[IX_T_B1S] = (double)t_b1s / ctl.wall_hz;
     s.info[IX_MISS_IN] = (double)sc->miss_in;
     s.info[IX_MISS_OUT] = (double)sc->miss_out;
+    s.info[IX_T_GATHER] = (double)t_gather / ctl.wall_hz;
+    s.info[IX_GATHERS] = (double)n_gather;
     s.status[0] = sc->status;
   }
   return;
@@ -2758,7 +2782,7 @@ size_t solve_lds_bytes(const DevProblem& p, const DevControl& c) {
   d += 4 * P * nr + 4 * P * nw + (size_t)c.vmax + RED_LEN + 14 * P + nr;
   if (c.xmode == XM_LOCAL) d += 3 * (size_t)c.vmax;
   if (c.lds_state) d += f32 ? state_lds_doubles<float>(P, Tp, nw) : state_lds_doubles<double>(P, Tp, nw);
-  if (c.lists) d += NPOOL * 4;
+  if (c.lists) d += NPOOL * 4 + NPOOL;   // pool, and two ints per pool entry
   d += (sizeof(Scal) + 7) / 8 + 2 + 5 * P + 1;   // flags, nine per-period integer arrays and nidx[P + 1]
   return d * sizeof(double);
 }
