@@ -691,6 +691,10 @@ ffo_status batched_lockstep(int64_t B, const int64_t* n_b, int64_t n_max, int64_
   const size_t otE = carve((size_t)2 * maxE, 4), oeoff = carve(B, 4), oest = carve((size_t)8 * maxE, 8);
   const size_t oest2 = carve((size_t)8 * nab * B, 8);
   const size_t oinfo = carve((size_t)B * ffo::INFO_LEN, 8), ostat = carve(B, 4), oclk = carve(1, 8), oflag = carve(1, 4);
+  // the hand-off of the last instances to the plain kernel: warm start and a contiguous
+  // copy of the instance's exposure rows
+  const size_t ohw = carve(n_max, 8), ohy = carve((size_t)nr + n_max, 8);
+  const size_t ohA = carve((size_t)std::max<int64_t>(m, 1) * n_max, 8);
   const size_t total = off;
   size_t hoff = 0;
   auto hcarve = [&](size_t bytes) { const size_t o = hoff; hoff = align_up(hoff + bytes); return o; };
@@ -698,7 +702,7 @@ ffo_status batched_lockstep(int64_t B, const int64_t* n_b, int64_t n_max, int64_
   const size_t hOm_o = hcarve(kk2 * 8), hC_o = hcarve(kk2 * 8), hW_o = hcarve(2 * kk2 * 8), hflag_o = hcarve(4);
   const size_t hnb_o = hcarve((size_t)B * 8), hnb32_o = hcarve((size_t)B * 4), hoffs_o = hcarve((size_t)(B + 1) * 8);
   const size_t hact_o = hcarve((size_t)B * 4), hcnt_o = hcarve(32), hinfo_o = hcarve((size_t)B * ffo::INFO_LEN * 8);
-  const size_t hstat_o = hcarve((size_t)B * 4);
+  const size_t hstat_o = hcarve((size_t)B * 4), hinst_o = hcarve((size_t)B * sizeof(ffo::LsInst));
   Workspace* ws = nullptr;
   if (ffo_status st = get_workspace(dev, stream, total, hoff, &ws, 3)) return st;
   LsBuffers* lb = nullptr;
@@ -824,7 +828,13 @@ ffo_status batched_lockstep(int64_t B, const int64_t* n_b, int64_t n_max, int64_
   hipGraphExec_t ex = nullptr;
   HIPCHK(ls_graph(S, tu, gA, gC, ce, true, ps, &ex));
   const int64_t max_replays = (opt.max_iter + ce - 1) / ce + 1;
+  // When at most kHandoff instances remain, each step still pays every kernel's launch
+  // and latency for a handful of assets (about 41 us per step against ~12 us for an
+  // iteration of the plain kernel), so the last ones finish on the plain kernel, warm
+  // started from their current iterate and primal weight.
+  constexpr int64_t kHandoff = 2;
   int64_t replays = 0;
+  bool handoff = false;
   hipError_t le = hipSuccess;
   for (; replays < max_replays; ++replays) {
     le = hipGraphLaunch(ex, ps);
@@ -833,9 +843,40 @@ ffo_status batched_lockstep(int64_t B, const int64_t* n_b, int64_t n_max, int64_
     if (le != hipSuccess) break;
     le = hipStreamSynchronize(ps);
     if (le != hipSuccess || hcnt[0] == 0) { ++replays; break; }
+    if (B > kHandoff && hcnt[0] <= kHandoff) { ++replays; handoff = true; break; }
   }
   hipGraphExecDestroy(ex);
   if (le != hipSuccess) return fail(FFO_EDEVICE, std::string("lockstep replay failed: ") + hipGetErrorString(le));
+  // the hand-off: every remaining instance in turn on the plain kernel (same stream)
+  std::vector<std::pair<int64_t, ffo_info>> handed;
+  if (handoff) {
+    const int nleft = hcnt[0];
+    ffo::LsInst* hinst = (ffo::LsInst*)(Hb + hinst_o);
+    HIPCHK(hipMemcpyAsync(hact, S.act, (size_t)nleft * 4, hipMemcpyDeviceToHost, ps));
+    HIPCHK(hipMemcpyAsync(hinst, S.inst, (size_t)B * sizeof(ffo::LsInst), hipMemcpyDeviceToHost, ps));
+    HIPCHK(hipStreamSynchronize(ps));
+    for (int j = 0; j < nleft; ++j) {
+      const int64_t b = hact[j], o = offs[b], nb = n_b[b];
+      const ffo::LsInst I = hinst[b];
+      if (ffo::ls_launch_export(S, (int)b, (int)nb, D(ohw), D(ohy), ps)) return fail(FFO_EDEVICE, "export launch failed");
+      if (m > 0)
+        HIPCHK(hipMemcpy2DAsync(D(ohA), (size_t)nb * 8, A, (size_t)n_max * 8, (size_t)nb * 8, (size_t)m,
+                                hipMemcpyDeviceToDevice, ps));
+      ffo_options o2 = opt;
+      o2.max_iter = std::max<int64_t>(1, opt.max_iter - I.it);
+      o2.workgroups = 0;
+      o2.verbose = 0;
+      ffo_info ib{};
+      const ffo_status sb = solve_impl(nb, k, m, 0, alpha + o, F, Omega, delta, s + o, q + o, d, D(ohA),
+                                       m ? L + (size_t)b * m : nullptr, m ? U + (size_t)b * m : nullptr, w0 + o, GMV,
+                                       lambda1, lambda2, lambda3, nullptr, D(ohw), D(ohy), I.omega, &o2, ps,
+                                       w_out + o, nullptr, &ib, nullptr);
+      if (sb == FFO_EINVAL || sb == FFO_ENOMEM || sb == FFO_EDEVICE) return sb;
+      ib.iters += I.it;
+      ib.restarts += I.restarts;
+      handed.emplace_back(b, ib);
+    }
+  }
   HIPCHK(hipEventRecord(ws->ev[2], ps));
   double* hinfo = (double*)(Hb + hinfo_o);
   int32_t* hstat = (int32_t*)(Hb + hstat_o);
@@ -853,13 +894,28 @@ ffo_status batched_lockstep(int64_t B, const int64_t* n_b, int64_t n_max, int64_
   for (int64_t b = 0; b < B; ++b) {
     const ffo_status st = status_of(hstat[b]);
     fill_info(&infos[b], st, hinfo + (size_t)b * ffo::INFO_LEN, ms_setup, ms_iter);
-    if (rank(st) > rank(worst)) worst = st;
   }
-  if (opt.verbose)
+  for (const auto& h : handed) {   // instances finished by the plain kernel
+    infos[h.first] = h.second;
+    infos[h.first].ms_setup = ms_setup;
+    infos[h.first].ms_iter = ms_iter;
+  }
+  for (int64_t b = 0; b < B; ++b)
+    if (rank((ffo_status)infos[b].status) > rank(worst)) worst = (ffo_status)infos[b].status;
+  if (opt.verbose) {
+    double passes = 0.0, iters = 0.0, pmax = 0.0;
+    for (int64_t b = 0; b < B; ++b) {
+      const double* h = hinfo + (size_t)b * ffo::INFO_LEN;
+      passes += h[ffo::IX_MS_ROUNDS];
+      iters += h[ffo::IX_ITERS];
+      pmax = std::max(pmax, h[ffo::IX_MS_ROUNDS] / std::max(1.0, h[ffo::IX_ITERS]));
+    }
     std::fprintf(stderr, "[ffo lockstep] B %lld replays %lld (x %d iterations) tune fused %d threads %d ch %d gpt %d "
-                         "(%d candidates timed) | setup+tune %.3f ms solve %.3f ms\n",
+                         "(%d candidates timed) | setup+tune %.3f ms solve %.3f ms | multiplier passes per "
+                         "iteration %.2f (instance max %.2f) | %d finished on the plain kernel\n",
                  (long long)B, (long long)replays, ce, tu.fused, tu.threads, tu.ch, tu.gpt, tuned_candidates,
-                 ms_setup, ms_iter);
+                 ms_setup, ms_iter, passes / std::max(1.0, iters), pmax, (int)handed.size());
+  }
   if (worst == FFO_NOT_CONVERGED) g_err = "iteration limit reached for at least one instance";
   else if (worst == FFO_TIMEOUT) g_err = "time limit reached for at least one instance";
   else if (worst == FFO_NUMERIC) g_err = "NaN or Inf in an FP64 check of at least one instance";

@@ -172,7 +172,7 @@ struct LsInst {
   double kvr;                              // power iteration: sum of squares of the row products
   int64_t it, kk, restarts, checks;        // iterations, iterations since restart, restarts, checks
   int32_t done, status;                    // status: DevStatus (DS_RUNNING while active)
-  int32_t mu_passes, pad;                  // multiplier passes in the last step (diagnostic)
+  int32_t mu_passes, mu_passes_sum;        // multiplier passes in the last step, and in all (diagnostic)
 };
 
 struct LsShared {
@@ -230,6 +230,8 @@ int ls_launch_check(const LsShared& S, int threads, void* stream);
 int ls_launch_compact(const LsShared& S, void* stream);
 int ls_launch_power(const LsShared& S, int step, void* stream);   // step 0: rows, 1: assets
 int ls_launch_transpose(const LsShared& S, double* KDT, void* stream);
+// Instance b's current iterate, unscaled: w [n_b], y [nr + n_b] (rows, then trades).
+int ls_launch_export(const LsShared& S, int b, int n_b, double* w, double* y, void* stream);
 size_t ls_primal_lds(const LsShared& S);
 
 // Risk-model construction (riskmodel.hip): workspace bytes and the launches of the

@@ -663,16 +663,18 @@ __global__ __launch_bounds__(512) void k_mu(LsShared S, int fused) {
       ldbl* sb = (ldbl*)(lds + RED_DOUBLES);
       ldbl* sa = sb + n;
       const int nt = blockDim.x;
-      for (int i0 = threadIdx.x; i0 < n; i0 += 4 * nt) {
-        double bq[4], aq[4];
+      // sixteen pairs per thread and step: the copy of an 8000-asset instance is one or
+      // two round trips to memory instead of four to eight
+      for (int i0 = threadIdx.x; i0 < n; i0 += 16 * nt) {
+        double bq[16], aq[16];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
+        for (int u = 0; u < 16; ++u) {
           const int i = i0 + u * nt;
           bq[u] = i < n ? gb[i] : 0.0;
           aq[u] = i < n ? ga[i] : 0.0;
         }
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
+        for (int u = 0; u < 16; ++u) {
           const int i = i0 + u * nt;
           if (i < n) { sb[i] = bq[u]; sa[i] = aq[u]; }
         }
@@ -687,6 +689,7 @@ __global__ __launch_bounds__(512) void k_mu(LsShared S, int fused) {
   if (threadIdx.x == 0) {
     S.inst[b].mu = mu;
     S.inst[b].mu_passes = passes;
+    S.inst[b].mu_passes_sum += passes;
   }
 }
 
@@ -927,6 +930,7 @@ __global__ __launch_bounds__(512) void k_check(LsShared S) {
       inf[IX_ETA] = J.eta;
       inf[IX_NORMK] = 0.95 / J.eta;
       inf[IX_CHECKS] = (double)J.checks;
+      inf[IX_MS_ROUNDS] = (double)J.mu_passes_sum;   // multiplier passes over the elements
       inf[IX_T_ITER] = el;
       S.status[b] = J.status;
     }
@@ -989,6 +993,26 @@ size_t ls_primal_lds(const LsShared& S) {
 int ls_launch_init(const LsShared& S, void* stream) {
   hipLaunchKernelGGL(k_clock, dim3(1), dim3(64), 0, (hipStream_t)stream, S.clock0);
   hipLaunchKernelGGL(k_init, dim3(S.B), dim3(256), 0, (hipStream_t)stream, S);
+  return (int)hipGetLastError();
+}
+
+// The current iterate of instance b in unscaled coordinates, as a warm start of the
+// plain solver: w [n_b] = dc x, and the duals in its y layout [m rows][k rows][n_b
+// trades] (row r: dr_r y_r; trade i: drC_i yC_i).
+__global__ void k_export(LsShared S, int b, double* __restrict__ w, double* __restrict__ y) {
+  const int64_t o = S.offs[b];
+  const int n = S.nb[b];
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    w[i] = S.dc[i] * S.x[o + i];
+    y[S.nr + i] = S.drC[i] * S.yC[o + i];
+  }
+  for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < S.nr; r += gridDim.x * blockDim.x)
+    y[r] = S.drs[(size_t)b * S.nr + r] * S.y[(size_t)b * S.nrp + r];
+}
+
+int ls_launch_export(const LsShared& S, int b, int n_b, double* w, double* y, void* stream) {
+  const int grid = std::max(1, std::min(256, (n_b + 255) / 256));
+  hipLaunchKernelGGL(k_export, dim3(grid), dim3(256), 0, (hipStream_t)stream, S, b, w, y);
   return (int)hipGetLastError();
 }
 

@@ -135,7 +135,10 @@ def test_full_batch_256(precision, form):
     order = np.argsort(nb)
     for b in order[:3]:
         _check_against_oracle(batch, W, infos, int(b), 1e-6, w_tol=2e-5, obj_tol=2e-6)
-    for b in order[-3:]:
+    # the three largest, and the two that ran longest (in the lockstep form these are the
+    # last instances, which finish on the plain kernel from their lockstep iterate)
+    slowest = np.argsort([i.iters for i in infos])[-2:]
+    for b in list(order[-3:]) + [b for b in slowest if b not in order[-3:]]:
         inst = batch_instance(batch, int(b))
         Wp, ip = ff.solve_instance(inst, tol=1e-6)
         lo, hi = int(batch["offs"][b]), int(batch["offs"][b + 1])
@@ -178,13 +181,15 @@ def test_lockstep_is_bitwise_repeatable():
 @pytest.mark.parametrize("autotune", [0, -1])
 def test_lockstep_instances_beyond_the_lds_pairs(autotune):
     """n_b above the LDS capacity for the (b, 1/a) pairs (about 10,000 assets): those
-    instances keep them in device memory; against the plain solver."""
+    instances keep them in device memory; against the plain solver, both at relative KKT
+    1e-10 (at 1e-8 two solutions of these four-factor instances differ by up to ~1.2e-5;
+    here the last two instances also finish on the plain kernel after the hand-off)."""
     ff = _gpu()
     batch = make_batch(3, 4, 6, seed=19, n_lo=10500, n_hi=12000, n_max=12000)
-    W, infos = _solve_batched(batch, tol=1e-8, form="lockstep", autotune=autotune)
+    W, infos = _solve_batched(batch, tol=1e-10, form="lockstep", autotune=autotune)
     for b in range(3):
         inst = batch_instance(batch, b)
-        Wp, ip = ff.solve_instance(inst, tol=1e-8)
+        Wp, ip = ff.solve_instance(inst, tol=1e-10)
         lo, hi = int(batch["offs"][b]), int(batch["offs"][b + 1])
         assert infos[b].status == 0 and ip.status == 0
         assert np.max(np.abs(W[lo:hi] - Wp.cpu().numpy()[0])) <= 1e-5
