@@ -302,7 +302,12 @@ def comparisons(ff, torch, dev, dev_insts, tol, plain_value):
     rel = float(torch.linalg.norm(ga32 - ga64) / torch.linalg.norm(ga64))
     # the bandwidth-bound form: n = 400,000, constraint rows (448 MB) beyond LDS and the
     # 256 MB last-level cache, streamed from HBM twice per iteration
-    out["single_period_n400000_fp64_device_rows"] = stress_leg(ff, torch, 400000)
+    leg64, W64s = stress_leg(ff, torch, 400000)
+    leg32, _ = stress_leg(ff, torch, 400000, precision="fp32", ref=W64s)
+    leg32["vs_fp64"] = leg64["kernel_ms"] / leg32["kernel_ms"]
+    out["single_period_n400000_fp64_device_rows"] = leg64
+    out["single_period_n400000_fp32_device_rows"] = leg32
+    del W64s
     # risk-model construction (paper Section 3.2): 504 days x 5000 assets, six factors,
     # 15% of the assets with a shorter history; one streaming pass over the returns
     from synth import returns_panel
@@ -338,11 +343,13 @@ def comparisons(ff, torch, dev, dev_insts, tol, plain_value):
     return out
 
 
-def stress_leg(ff, torch, n, steps=1, warmup=1, tol=1e-6):
-    """Single-period FP64 solves at n assets (k=60, m=80, seed 5): the constraint rows
-    (140 x n doubles) stay in device memory and are streamed twice per iteration, so
-    this is the form whose roofline is HBM bandwidth.  Algorithmic bytes per iteration
-    as for the headline workload."""
+def stress_leg(ff, torch, n, steps=1, warmup=1, tol=1e-6, precision="fp64", ref=None):
+    """Single-period solves at n assets (k=60, m=80, seed 5): the constraint rows (140 x n)
+    stay in device memory and are streamed twice per iteration, so this is the form whose
+    roofline is HBM bandwidth.  Algorithmic bytes per iteration as for the headline
+    workload, in the form's element size (the FP32 form reads float rows and float
+    iterate offsets).  Returns (record, W); with ``ref`` (an FP64 solution) the record
+    states the largest weight difference against it."""
     from synth import make_single
     inst = make_single(n, 60, 80, seed=5)
     dev = torch.device("cuda", 0)
@@ -351,18 +358,23 @@ def stress_leg(ff, torch, n, steps=1, warmup=1, tol=1e-6):
         d[kk] = torch.as_tensor(d[kk], dtype=torch.float64, device=dev).contiguous()
     W = torch.empty((1, n), dtype=torch.float64, device=dev)
     for _ in range(warmup):
-        ff.solve_instance(d, tol=tol, out=W, time_limit_s=300)
+        ff.solve_instance(d, tol=tol, out=W, time_limit_s=300, precision=precision)
     torch.cuda.synchronize()
-    infos = [ff.solve_instance(d, tol=tol, out=W, time_limit_s=300)[1] for _ in range(steps)]
+    infos = [ff.solve_instance(d, tol=tol, out=W, time_limit_s=300, precision=precision)[1] for _ in range(steps)]
     torch.cuda.synchronize()
-    bpi = algorithmic_bytes_per_iter(n, 60, 80, 1, 1)
+    w = 8 if precision == "fp64" else 4
+    bpi = algorithmic_bytes_per_iter(n, 60, 80, 1, 1, w=w)
     iters = float(np.mean([i.iters for i in infos]))
     kms = float(np.mean([i.ms_iter for i in infos]))
-    return {"n": n, "k": 60, "m": 80, "iters": iters, "kernel_ms": kms, "us_per_iter": kms * 1e3 / iters,
-            "bytes_per_iter": bpi, "achieved_gb_s": bpi * iters / (kms * 1e-3) / 1e9,
-            "frac_of_hbm_peak": bpi * iters / (kms * 1e-3) / 1e9 / HBM_PEAK_GBS,
-            "rows_bytes": 140 * n * 8, "status_all_ok": all(i.status == 0 for i in infos),
-            "rel_kkt_max": max(i.rel_kkt for i in infos)}
+    out = {"n": n, "k": 60, "m": 80, "precision": precision, "iters": iters, "kernel_ms": kms,
+           "us_per_iter": kms * 1e3 / iters, "bytes_per_iter": bpi,
+           "achieved_gb_s": bpi * iters / (kms * 1e-3) / 1e9,
+           "frac_of_hbm_peak": bpi * iters / (kms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+           "rows_bytes": 140 * n * w, "status_all_ok": all(i.status == 0 for i in infos),
+           "rel_kkt_max": max(i.rel_kkt for i in infos)}
+    if ref is not None:
+        out["w_max_abs_diff_vs_fp64"] = float(torch.max(torch.abs(W - ref)))
+    return out, W
 
 
 def batched_only(ff, torch, a):
@@ -412,7 +424,7 @@ def main():
         print(json.dumps(batched_only(ff, torch, a)), flush=True)
         return
     if a.stress_n:
-        print(json.dumps(stress_leg(ff, torch, a.stress_n, steps=max(1, a.steps), warmup=a.warmup, tol=a.tol)),
+        print(json.dumps(stress_leg(ff, torch, a.stress_n, steps=max(1, a.steps), warmup=a.warmup, tol=a.tol)[0]),
               flush=True)
         return
     cfg = CONFIGS[a.config]
