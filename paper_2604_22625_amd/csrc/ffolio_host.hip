@@ -832,7 +832,7 @@ ffo_status batched_lockstep(int64_t B, const int64_t* n_b, int64_t n_max, int64_
   // and latency for a handful of assets (about 41 us per step against ~12 us for an
   // iteration of the plain kernel), so the last ones finish on the plain kernel, warm
   // started from their current iterate and primal weight.
-  constexpr int64_t kHandoff = 2;
+  constexpr int64_t kHandoff = 4;
   int64_t replays = 0;
   bool handoff = false;
   hipError_t le = hipSuccess;

@@ -135,9 +135,9 @@ def test_full_batch_256(precision, form):
     order = np.argsort(nb)
     for b in order[:3]:
         _check_against_oracle(batch, W, infos, int(b), 1e-6, w_tol=2e-5, obj_tol=2e-6)
-    # the three largest, and the two that ran longest (in the lockstep form these are the
+    # the three largest, and the four that ran longest (in the lockstep form these are the
     # last instances, which finish on the plain kernel from their lockstep iterate)
-    slowest = np.argsort([i.iters for i in infos])[-2:]
+    slowest = np.argsort([i.iters for i in infos])[-4:]
     for b in list(order[-3:]) + [b for b in slowest if b not in order[-3:]]:
         inst = batch_instance(batch, int(b))
         Wp, ip = ff.solve_instance(inst, tol=1e-6)
@@ -154,7 +154,11 @@ def test_lockstep_many_groups_with_compaction(autotune):
     """40 instances (three slot groups) of uneven sizes: instances converge at different
     checks and leave the slot list while the others continue; each against the oracle
     (every fifth) and all against the team form.  autotune 0 / -1: the fused and the
-    separate element passes with fixed tiles; 1: the tuned choice."""
+    separate element passes with fixed tiles; 1: the tuned choice.  The team form runs
+    the same iteration from the same start, so most instances agree to rounding; the last
+    four finish on the plain kernel from their lockstep iterate (a different path), and
+    two solutions to relative KKT 1e-10 of these four-factor instances differ by up to a
+    few 1e-6 (the strong-convexity bound allows ~3e-5), hence the 1e-5 bar."""
     batch = make_batch(40, 4, 6, seed=13, n_lo=30, n_hi=1500, n_max=1500)
     W, infos = _solve_batched(batch, tol=1e-10, form="lockstep", autotune=autotune)
     Wt, it = _solve_batched(batch, tol=1e-10, form="teams")
@@ -163,7 +167,7 @@ def test_lockstep_many_groups_with_compaction(autotune):
     offs = np.asarray(batch["offs"])
     for b in range(40):
         assert infos[b].status == 0 and infos[b].rel_kkt <= 1e-10, (b, infos[b])
-        assert np.max(np.abs(W[offs[b]:offs[b + 1]] - Wt[offs[b]:offs[b + 1]])) <= 1e-6
+        assert np.max(np.abs(W[offs[b]:offs[b + 1]] - Wt[offs[b]:offs[b + 1]])) <= 1e-5
     for b in range(0, 40, 5):
         _check_against_oracle(batch, W, infos, b, 1e-10, w_tol=1e-5, obj_tol=1e-6)
 
@@ -182,8 +186,7 @@ def test_lockstep_is_bitwise_repeatable():
 def test_lockstep_instances_beyond_the_lds_pairs(autotune):
     """n_b above the LDS capacity for the (b, 1/a) pairs (about 10,000 assets): those
     instances keep them in device memory; against the plain solver, both at relative KKT
-    1e-10 (at 1e-8 two solutions of these four-factor instances differ by up to ~1.2e-5;
-    here the last two instances also finish on the plain kernel after the hand-off)."""
+    1e-10 (at 1e-8 two solutions of these four-factor instances differ by up to ~1.2e-5)."""
     ff = _gpu()
     batch = make_batch(3, 4, 6, seed=19, n_lo=10500, n_hi=12000, n_max=12000)
     W, infos = _solve_batched(batch, tol=1e-10, form="lockstep", autotune=autotune)
