@@ -794,7 +794,9 @@ __device__ __forceinline__ void period_stats(Ctx& c, const ldbl* absb, const ldb
                              const ldbl* hw, int off0) {
   const int lane = c.tid & 63, wave = c.tid >> 6, g = lane >> 3, sub = lane & 7;
   // waves per period: all of them share one period's assets when there are few periods
-  const int WP = c.P >= NWAVE ? 1 : (c.P >= NWAVE / 2 ? 2 : NWAVE);
+  // and many assets; one period of at most 64 assets stays in wave 0 (a few elements per
+  // lane, and no combine through LDS with its two barriers)
+  const int WP = (c.P >= NWAVE || (c.P == 1 && c.nwa <= 64)) ? 1 : (c.P >= NWAVE / 2 ? 2 : NWAVE);
   const int pw = wave % WP, tw = wave / WP, groups = NWAVE / WP;
   static_assert(NWAVE * 32 <= RED_OUT, "reduction scratch");
   for (int t0 = 0; t0 < c.P; t0 += groups) {
