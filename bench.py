@@ -283,6 +283,32 @@ def comparisons(ff, torch, dev, dev_insts, tol, plain_value):
                                        "note": "all 256 instances solved one after another with ffo_solve",
                                        "lockstep_fp64_speedup": seq_ms / out["batched_256_fp64_lockstep"]["batch_ms"],
                                        "teams_fp64_speedup": seq_ms / out["batched_256_fp64_teams"]["batch_ms"]}
+    # the benchmark's shape as a batch: ten n = 5000 instances (k = 60, m = 80) on one
+    # shared universe, in one launch of the team form, against the plain kernel solving
+    # the same ten one after another (the lockstep form takes at most 128 rows)
+    from synth.markets import make_batch
+    b10 = make_batch(10, 60, 80, seed=11, n_lo=5000, n_hi=5000, n_max=5000)
+    offs10 = np.asarray(b10["offs"])
+    b10_dev = []
+    for bi in range(10):
+        d = dict(batch_instance(b10, bi))
+        for key in ("alpha", "F", "Omega", "delta", "s", "q", "A", "L", "U", "w0"):
+            d[key] = torch.as_tensor(d[key], dtype=torch.float64, device=dev).contiguous()
+        b10_dev.append(d)
+    plain10 = lambda: [ff.solve_instance(d, tol=tol) for d in b10_dev]
+    plain10()
+    dtp, res = _timed(torch, plain10, 1)
+    Wp10 = np.concatenate([r[0].cpu().numpy().reshape(-1) for r in res])
+    ff.solve_batched(b10, tol=tol, form="teams")
+    dtt, (W10, i10) = _timed(torch, lambda: ff.solve_batched(b10, tol=tol, form="teams"), 2)
+    Wt10 = W10.cpu().numpy()
+    out["batched_10_n5000_fp64_teams"] = {
+        "form": "teams", "solves_per_s": 10 / dtt, "batch_ms": dtt * 1e3,
+        "plain_ms": dtp * 1e3, "plain_solves_per_s": 10 / dtp, "speedup_vs_plain": dtp / dtt,
+        "iters_max": int(max(i.iters for i in i10)), "all_ok": all(i.status == 0 for i in i10),
+        "w_max_abs_diff_vs_plain": float(max(np.max(np.abs(Wt10[lo:hi] - Wp10[lo:hi]))
+                                             for lo, hi in zip(offs10[:-1], offs10[1:]))),
+        "note": "ten n=5000 k=60 m=80 instances on one shared universe (seed 11), same tolerance"}
     # adjoint of the T = 10 workload: forward + backward
     c4 = make_config(4)
     P, n = c4["alpha"].shape

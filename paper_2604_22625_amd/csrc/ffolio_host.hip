@@ -1308,7 +1308,9 @@ ffo_status ffo_solve_batched(int64_t B, const int64_t* n_b, int64_t n_max, int64
   c0.prec = prec; c0.spec = 1; c0.lds_k = 0; c0.lds_state = 0; c0.infeas = opt.infeasibility_check ? 1 : 0;
   c0.vmax = ffo::solve_vmax(p0);
   const int NW_MAX = 2048;   // assets per workgroup at most (bounds the LDS staging)
-  const int NW_MIN = 256;    // extra workgroups only while a team keeps at least this many assets each
+  // extra workgroups only while a team keeps at least this many assets each (ten n = 5000
+  // instances: 25 workgroups per team at 128, 0.28 s per batch, against 19 and 0.34 s at 256)
+  const int NW_MIN = 128;
   size_t lds_cap = 0;
   {
     ffo::DevProblem pp = p0;

@@ -71,7 +71,8 @@ def test_small_batch_matches_oracle(precision, form):
 
 @pytest.mark.parametrize("precision,form", FORMS)
 def test_multi_workgroup_teams_match_oracle(precision, form):
-    # team form: n_b >= 512 is split over several workgroups when spare ones exist;
+    # team form: n_b >= 256 is split over several workgroups (at least 128 assets each)
+    # when spare ones exist;
     # lockstep form: several K~ x chunks per instance
     tol, w_tol = BARS[precision]
     batch = make_batch(3, 4, 6, seed=5, n_lo=900, n_hi=2600, n_max=2600)
@@ -109,6 +110,24 @@ def test_batched_agrees_with_plain_solver(form):
         lo, hi = int(batch["offs"][b]), int(batch["offs"][b + 1])
         assert infos[b].status == 0 and ip.status == 0
         assert np.max(np.abs(W[lo:hi] - Wp.cpu().numpy()[0])) <= 1e-5
+
+
+def test_headline_shape_teams_agree_with_plain_solver():
+    """Four n = 5000 instances with k = 60 and m = 80 (20 sector and 60 factor rows) on one
+    shared universe: one team of several dozen workgroups per instance (at least 128 assets
+    each), against the plain kernel on each instance (250 workgroups of 20 assets), both to
+    relative KKT 1e-8.  The lockstep form takes at
+    most 128 rows, so it rejects this shape."""
+    ff = _gpu()
+    batch = make_batch(4, 60, 80, seed=11, n_lo=5000, n_hi=5000, n_max=5000)
+    W, infos = _solve_batched(batch, tol=1e-8, form="teams")
+    for b in range(4):
+        Wp, ip = ff.solve_instance(batch_instance(batch, b), tol=1e-8)
+        lo, hi = int(batch["offs"][b]), int(batch["offs"][b + 1])
+        assert infos[b].status == 0 and ip.status == 0 and infos[b].rel_kkt <= 1e-8
+        assert np.max(np.abs(W[lo:hi] - Wp.cpu().numpy()[0])) <= 1e-5
+    with pytest.raises(ff.FolioError):
+        ff.solve_batched(batch, tol=1e-8, form="lockstep")
 
 
 @pytest.mark.parametrize("form", ["lockstep", "teams"])
