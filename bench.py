@@ -299,16 +299,17 @@ def comparisons(ff, torch, dev, dev_insts, tol, plain_value):
     plain10()
     dtp, res = _timed(torch, plain10, 1)
     Wp10 = np.concatenate([r[0].cpu().numpy().reshape(-1) for r in res])
-    ff.solve_batched(b10, tol=tol, form="teams")
-    dtt, (W10, i10) = _timed(torch, lambda: ff.solve_batched(b10, tol=tol, form="teams"), 2)
-    Wt10 = W10.cpu().numpy()
-    out["batched_10_n5000_fp64_teams"] = {
-        "form": "teams", "solves_per_s": 10 / dtt, "batch_ms": dtt * 1e3,
-        "plain_ms": dtp * 1e3, "plain_solves_per_s": 10 / dtp, "speedup_vs_plain": dtp / dtt,
-        "iters_max": int(max(i.iters for i in i10)), "all_ok": all(i.status == 0 for i in i10),
-        "w_max_abs_diff_vs_plain": float(max(np.max(np.abs(Wt10[lo:hi] - Wp10[lo:hi]))
-                                             for lo, hi in zip(offs10[:-1], offs10[1:]))),
-        "note": "ten n=5000 k=60 m=80 instances on one shared universe (seed 11), same tolerance"}
+    for prec in ("fp64", "fp32"):
+        ff.solve_batched(b10, tol=tol, form="teams", precision=prec)
+        dtt, (W10, i10) = _timed(torch, lambda: ff.solve_batched(b10, tol=tol, form="teams", precision=prec), 2)
+        Wt10 = W10.cpu().numpy()
+        out[f"batched_10_n5000_{prec}_teams"] = {
+            "form": "teams", "solves_per_s": 10 / dtt, "batch_ms": dtt * 1e3,
+            "plain_fp64_ms": dtp * 1e3, "plain_fp64_solves_per_s": 10 / dtp, "speedup_vs_plain_fp64": dtp / dtt,
+            "iters_max": int(max(i.iters for i in i10)), "all_ok": all(i.status == 0 for i in i10),
+            "w_max_abs_diff_vs_plain_fp64": float(max(np.max(np.abs(Wt10[lo:hi] - Wp10[lo:hi]))
+                                                      for lo, hi in zip(offs10[:-1], offs10[1:]))),
+            "note": "ten n=5000 k=60 m=80 instances on one shared universe (seed 11), same tolerance"}
     # adjoint of the T = 10 workload: forward + backward
     c4 = make_config(4)
     P, n = c4["alpha"].shape

@@ -266,7 +266,8 @@ ffo_status ffo_adjoint(int64_t n, int64_t k, int64_t m, int64_t T,
  *     default for FFO_FP64 with m + k <= 128, B <= 65536, n_max <= 2^22.
  *   teams: each instance runs the solve kernel's loop on a team of workgroups sized to
  *     its asset count (spare resident workgroups go to the teams with the most assets per
- *     workgroup, down to 128 assets each); all teams of a launch are resident at once and
+ *     workgroup, down to 128 assets each; constraint slice and per-asset state in LDS when
+ *     every team of the launch fits); all teams of a launch are resident at once and
  *     never wait for each
  *     other (batches larger than the resident grid run in several launches, largest
  *     instances first).  Every precision.

@@ -1465,6 +1465,38 @@ ffo_status ffo_solve_batched(int64_t B, const int64_t* n_b, int64_t n_max, int64
     c.xmode = g[b] == 1 ? ffo::XM_LOCAL : ffo::XM_ATOMIC;
     hCt[b] = c;
   }
+  // LDS placement per launch, as in ffo_solve: the constraint slice, then the per-asset
+  // state, when every team of the launch fits and the launch stays resident (bfloat16
+  // rows are always read from device memory)
+  std::vector<int> ckl(chunks.size(), 0), csl(chunks.size(), 0);
+  std::vector<size_t> clds(chunks.size(), 0);
+  const size_t lds_lim = std::min<size_t>(prop.sharedMemPerBlock, 160 * 1024);
+  for (size_t ci = 0; ci < chunks.size(); ++ci) {
+    int nb = 0;
+    for (int64_t r = chunks[ci].first; r < chunks[ci].second; ++r) nb += g[order[r]];
+    const int order2[4][2] = {{1, 1}, {1, 0}, {0, 1}, {0, 0}};
+    for (const auto& o : order2) {
+      if (o[0] && bf16rows) continue;
+      size_t need = 0;
+      for (int64_t r = chunks[ci].first; r < chunks[ci].second; ++r) {
+        ffo::DevControl t = hCt[order[r]];
+        t.lds_k = o[0];
+        t.lds_state = o[1];
+        need = std::max(need, ffo::solve_lds_bytes(hP[order[r]], t));
+      }
+      const bool last = o[0] == 0 && o[1] == 0;
+      if (last || (need <= lds_lim && ffo::solve_batch_occupancy(o[0], o[1], prec, need) * cus >= nb)) {
+        ckl[ci] = o[0];
+        csl[ci] = o[1];
+        clds[ci] = need;
+        break;
+      }
+    }
+    for (int64_t r = chunks[ci].first; r < chunks[ci].second; ++r) {
+      hCt[order[r]].lds_k = ckl[ci];
+      hCt[order[r]].lds_state = csl[ci];
+    }
+  }
   HIPCHK(hipMemcpyAsync(Bd + oP, hP, (size_t)B * sizeof(ffo::DevProblem), hipMemcpyHostToDevice, hs));
   HIPCHK(hipMemcpyAsync(Bd + oS, hS, (size_t)B * sizeof(ffo::DevState), hipMemcpyHostToDevice, hs));
   HIPCHK(hipMemcpyAsync(Bd + oCt, hCt, (size_t)B * sizeof(ffo::DevControl), hipMemcpyHostToDevice, hs));
@@ -1475,18 +1507,17 @@ ffo_status ffo_solve_batched(int64_t B, const int64_t* n_b, int64_t n_max, int64
     int* ht = (int*)(Hb + hteam_o) + ci * W;
     int* hr = (int*)(Hb + hrank_o) + ci * W;
     int nb = 0;
-    size_t lds = 0;
+    const size_t lds = clds[ci];
     for (int64_t r = chunks[ci].first; r < chunks[ci].second; ++r) {
       const int64_t b = order[r];
       for (int w = 0; w < g[b]; ++w) { ht[nb] = (int)b; hr[nb] = w; ++nb; }
-      lds = std::max(lds, ffo::solve_lds_bytes(hP[b], hCt[b]));
     }
     // the device team tables are rewritten in stream order, after the previous launch
     HIPCHK(hipMemcpyAsync(Bd + oteam, ht, (size_t)nb * 4, hipMemcpyHostToDevice, hs));
     HIPCHK(hipMemcpyAsync(Bd + orank, hr, (size_t)nb * 4, hipMemcpyHostToDevice, hs));
     if (int e = ffo::launch_solve_batch((const ffo::DevProblem*)(Bd + oP), (const ffo::DevState*)(Bd + oS),
                                         (const ffo::DevControl*)(Bd + oCt), (const int*)(Bd + oteam),
-                                        (const int*)(Bd + orank), nb, 0, 0, prec, stream, lds))
+                                        (const int*)(Bd + orank), nb, ckl[ci], csl[ci], prec, stream, lds))
       return fail(FFO_EDEVICE, std::string("cooperative launch of the batched solve kernel failed: ") +
                                    hipGetErrorString((hipError_t)e));
   }
@@ -1510,8 +1541,10 @@ ffo_status ffo_solve_batched(int64_t B, const int64_t* n_b, int64_t n_max, int64
     if (rank(st) > rank(worst)) worst = st;
   }
   if (opt.verbose) {
-    std::fprintf(stderr, "[ffo batch] B %lld launches %zu resident %d (occupancy %d) lds %zu | setup %.3f ms solve %.3f ms\n",
-                 (long long)B, chunks.size(), W, occ, lds_cap, ms_setup, ms_iter);
+    std::fprintf(stderr,
+                 "[ffo batch] B %lld launches %zu resident %d (occupancy %d) lds %zu | first launch: slice in LDS %d, "
+                 "state in LDS %d, %zu bytes | setup %.3f ms solve %.3f ms\n",
+                 (long long)B, chunks.size(), W, occ, lds_cap, ckl[0], csl[0], clds[0], ms_setup, ms_iter);
     int64_t slow = 0;
     for (int64_t b = 1; b < B; ++b)
       if (hinfo[(size_t)b * ffo::INFO_LEN + ffo::IX_T_ITER] > hinfo[(size_t)slow * ffo::INFO_LEN + ffo::IX_T_ITER]) slow = b;

@@ -112,22 +112,26 @@ def test_batched_agrees_with_plain_solver(form):
         assert np.max(np.abs(W[lo:hi] - Wp.cpu().numpy()[0])) <= 1e-5
 
 
-def test_headline_shape_teams_agree_with_plain_solver():
-    """Four n = 5000 instances with k = 60 and m = 80 (20 sector and 60 factor rows) on one
-    shared universe: one team of several dozen workgroups per instance (at least 128 assets
-    each), against the plain kernel on each instance (250 workgroups of 20 assets), both to
-    relative KKT 1e-8.  The lockstep form takes at
-    most 128 rows, so it rejects this shape."""
+@pytest.mark.parametrize("B,precision", [(4, "fp64"), (10, "fp32")])
+def test_headline_shape_teams_agree_with_plain_solver(B, precision):
+    """n = 5000 instances with k = 60 and m = 80 (20 sector and 60 factor rows) on one
+    shared universe: one team of workgroups per instance (at least 128 assets each; at
+    B = 10, 25 workgroups of 200 assets, whose FP32 slice and state sit in LDS), against
+    the plain FP64 kernel on each instance (250 workgroups of 20 assets), both to relative
+    KKT 1e-8 (FP64) or 1e-7 (FP32, bar 2e-5 as for the other FP32 batches).  The lockstep
+    form takes at most 128 rows, so it rejects this shape."""
     ff = _gpu()
-    batch = make_batch(4, 60, 80, seed=11, n_lo=5000, n_hi=5000, n_max=5000)
-    W, infos = _solve_batched(batch, tol=1e-8, form="teams")
-    for b in range(4):
-        Wp, ip = ff.solve_instance(batch_instance(batch, b), tol=1e-8)
+    tol, w_tol = (1e-8, 1e-5) if precision == "fp64" else BARS["fp32"]
+    batch = make_batch(B, 60, 80, seed=11, n_lo=5000, n_hi=5000, n_max=5000)
+    W, infos = _solve_batched(batch, tol=tol, form="teams", precision=precision)
+    for b in range(B):
+        Wp, ip = ff.solve_instance(batch_instance(batch, b), tol=tol)
         lo, hi = int(batch["offs"][b]), int(batch["offs"][b + 1])
-        assert infos[b].status == 0 and ip.status == 0 and infos[b].rel_kkt <= 1e-8
-        assert np.max(np.abs(W[lo:hi] - Wp.cpu().numpy()[0])) <= 1e-5
-    with pytest.raises(ff.FolioError):
-        ff.solve_batched(batch, tol=1e-8, form="lockstep")
+        assert infos[b].status == 0 and ip.status == 0 and infos[b].rel_kkt <= tol
+        assert np.max(np.abs(W[lo:hi] - Wp.cpu().numpy()[0])) <= w_tol
+    if precision == "fp64":
+        with pytest.raises(ff.FolioError):
+            ff.solve_batched(batch, tol=tol, form="lockstep")
 
 
 @pytest.mark.parametrize("form", ["lockstep", "teams"])
