@@ -88,6 +88,10 @@ def parse():
                     help="only time single-period FP64 solves at n=N (k=60, m=80, rows beyond LDS, read from "
                          "device memory every iteration) and print one JSON line (for profiling the "
                          "bandwidth-bound form)")
+    ap.add_argument("--batch10", action="store_true",
+                    help="only the ten-instance batch of the headline shape (n=5000, k=60, m=80, one shared "
+                         "universe): team form FP64 and FP32 against the plain FP64 kernel, one JSON line (for "
+                         "profiling); --steps timed repetitions, a warm-up unless --warmup 0")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only copy a float64 buffer of MIB MiB three times on the GPU (one read and one write "
                          "of MIB MiB each) and exit: the known-size reference that scales rocprofv3's "
@@ -213,6 +217,43 @@ def _timed(torch, fn, reps):
     return (time.perf_counter() - t0) / reps, res
 
 
+def batch10_legs(ff, torch, dev, tol, plain_reps, batch_reps, warm=True):
+    """The benchmark's shape as a batch: ten n = 5000 instances (k = 60, m = 80) on one
+    shared universe (seed 11), in one launch of the team form (FP64 and FP32), against the
+    plain FP64 kernel solving the same ten one after another (the lockstep form takes at
+    most 128 rows).  Returns the two legs."""
+    from synth import batch_instance
+    from synth.markets import make_batch
+    out = {}
+    b10 = make_batch(10, 60, 80, seed=11, n_lo=5000, n_hi=5000, n_max=5000)
+    offs10 = np.asarray(b10["offs"])
+    b10_dev = []
+    for bi in range(10):
+        d = dict(batch_instance(b10, bi))
+        for key in ("alpha", "F", "Omega", "delta", "s", "q", "A", "L", "U", "w0"):
+            d[key] = torch.as_tensor(d[key], dtype=torch.float64, device=dev).contiguous()
+        b10_dev.append(d)
+    plain10 = lambda: [ff.solve_instance(d, tol=tol) for d in b10_dev]
+    if warm:
+        plain10()
+    dtp, res = _timed(torch, plain10, plain_reps)
+    Wp10 = np.concatenate([r[0].cpu().numpy().reshape(-1) for r in res])
+    for prec in ("fp64", "fp32"):
+        if warm:
+            ff.solve_batched(b10, tol=tol, form="teams", precision=prec)
+        dtt, (W10, i10) = _timed(torch, lambda: ff.solve_batched(b10, tol=tol, form="teams", precision=prec),
+                                 batch_reps)
+        Wt10 = W10.cpu().numpy()
+        out[f"batched_10_n5000_{prec}_teams"] = {
+            "form": "teams", "solves_per_s": 10 / dtt, "batch_ms": dtt * 1e3,
+            "plain_fp64_ms": dtp * 1e3, "plain_fp64_solves_per_s": 10 / dtp, "speedup_vs_plain_fp64": dtp / dtt,
+            "iters_max": int(max(i.iters for i in i10)), "all_ok": all(i.status == 0 for i in i10),
+            "w_max_abs_diff_vs_plain_fp64": float(max(np.max(np.abs(Wt10[lo:hi] - Wp10[lo:hi]))
+                                                      for lo, hi in zip(offs10[:-1], offs10[1:]))),
+            "note": "ten n=5000 k=60 m=80 instances on one shared universe (seed 11), same tolerance"}
+    return out
+
+
 def comparisons(ff, torch, dev, dev_insts, tol, plain_value):
     """The other legs of the metric, each timed after one warm-up: the T=20 multi-period
     solve (n=3000), the FP32 form on the same n=5000 markets, the 256-instance batch in
@@ -283,33 +324,7 @@ def comparisons(ff, torch, dev, dev_insts, tol, plain_value):
                                        "note": "all 256 instances solved one after another with ffo_solve",
                                        "lockstep_fp64_speedup": seq_ms / out["batched_256_fp64_lockstep"]["batch_ms"],
                                        "teams_fp64_speedup": seq_ms / out["batched_256_fp64_teams"]["batch_ms"]}
-    # the benchmark's shape as a batch: ten n = 5000 instances (k = 60, m = 80) on one
-    # shared universe, in one launch of the team form, against the plain kernel solving
-    # the same ten one after another (the lockstep form takes at most 128 rows)
-    from synth.markets import make_batch
-    b10 = make_batch(10, 60, 80, seed=11, n_lo=5000, n_hi=5000, n_max=5000)
-    offs10 = np.asarray(b10["offs"])
-    b10_dev = []
-    for bi in range(10):
-        d = dict(batch_instance(b10, bi))
-        for key in ("alpha", "F", "Omega", "delta", "s", "q", "A", "L", "U", "w0"):
-            d[key] = torch.as_tensor(d[key], dtype=torch.float64, device=dev).contiguous()
-        b10_dev.append(d)
-    plain10 = lambda: [ff.solve_instance(d, tol=tol) for d in b10_dev]
-    plain10()
-    dtp, res = _timed(torch, plain10, 1)
-    Wp10 = np.concatenate([r[0].cpu().numpy().reshape(-1) for r in res])
-    for prec in ("fp64", "fp32"):
-        ff.solve_batched(b10, tol=tol, form="teams", precision=prec)
-        dtt, (W10, i10) = _timed(torch, lambda: ff.solve_batched(b10, tol=tol, form="teams", precision=prec), 2)
-        Wt10 = W10.cpu().numpy()
-        out[f"batched_10_n5000_{prec}_teams"] = {
-            "form": "teams", "solves_per_s": 10 / dtt, "batch_ms": dtt * 1e3,
-            "plain_fp64_ms": dtp * 1e3, "plain_fp64_solves_per_s": 10 / dtp, "speedup_vs_plain_fp64": dtp / dtt,
-            "iters_max": int(max(i.iters for i in i10)), "all_ok": all(i.status == 0 for i in i10),
-            "w_max_abs_diff_vs_plain_fp64": float(max(np.max(np.abs(Wt10[lo:hi] - Wp10[lo:hi]))
-                                                      for lo, hi in zip(offs10[:-1], offs10[1:]))),
-            "note": "ten n=5000 k=60 m=80 instances on one shared universe (seed 11), same tolerance"}
+    out.update(batch10_legs(ff, torch, dev, tol, 1, 2))
     # adjoint of the T = 10 workload: forward + backward
     c4 = make_config(4)
     P, n = c4["alpha"].shape
@@ -449,6 +464,12 @@ def main():
         return
     if a.config == 3:
         print(json.dumps(batched_only(ff, torch, a)), flush=True)
+        return
+    if a.batch10:
+        dev = torch.device("cuda", 0)
+        legs = batch10_legs(ff, torch, dev, a.tol, max(1, a.steps), max(1, a.steps), warm=a.warmup > 0)
+        print(json.dumps({"workload": "ten n=5000 k=60 m=80 single-period instances on one shared universe: "
+                                      "team form (FP64, FP32) against the plain FP64 kernel", **legs}), flush=True)
         return
     if a.stress_n:
         print(json.dumps(stress_leg(ff, torch, a.stress_n, steps=max(1, a.steps), warmup=a.warmup, tol=a.tol)[0]),
