@@ -90,7 +90,8 @@ def parse():
                          "bandwidth-bound form)")
     ap.add_argument("--batch10", action="store_true",
                     help="only the ten-instance batch of the headline shape (n=5000, k=60, m=80, one shared "
-                         "universe): team form FP64 and FP32 against the plain FP64 kernel, one JSON line (for "
+                         "universe): lockstep FP64 and team form FP64 and FP32 against the plain FP64 kernel, one "
+                         "JSON line (for "
                          "profiling); --steps timed repetitions, a warm-up unless --warmup 0")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only copy a float64 buffer of MIB MiB three times on the GPU (one read and one write "
@@ -219,9 +220,9 @@ def _timed(torch, fn, reps):
 
 def batch10_legs(ff, torch, dev, tol, plain_reps, batch_reps, warm=True):
     """The benchmark's shape as a batch: ten n = 5000 instances (k = 60, m = 80) on one
-    shared universe (seed 11), in one launch of the team form (FP64 and FP32), against the
-    plain FP64 kernel solving the same ten one after another (the lockstep form takes at
-    most 128 rows).  Returns the two legs."""
+    shared universe (seed 11), in the lockstep form (FP64) and in one launch of the team
+    form (FP64 and FP32), against the plain FP64 kernel solving the same ten one after
+    another.  Returns the three legs."""
     from synth import batch_instance
     from synth.markets import make_batch
     out = {}
@@ -238,14 +239,14 @@ def batch10_legs(ff, torch, dev, tol, plain_reps, batch_reps, warm=True):
         plain10()
     dtp, res = _timed(torch, plain10, plain_reps)
     Wp10 = np.concatenate([r[0].cpu().numpy().reshape(-1) for r in res])
-    for prec in ("fp64", "fp32"):
+    for prec, form in (("fp64", "lockstep"), ("fp64", "teams"), ("fp32", "teams")):
         if warm:
-            ff.solve_batched(b10, tol=tol, form="teams", precision=prec)
-        dtt, (W10, i10) = _timed(torch, lambda: ff.solve_batched(b10, tol=tol, form="teams", precision=prec),
+            ff.solve_batched(b10, tol=tol, form=form, precision=prec)
+        dtt, (W10, i10) = _timed(torch, lambda: ff.solve_batched(b10, tol=tol, form=form, precision=prec),
                                  batch_reps)
         Wt10 = W10.cpu().numpy()
-        out[f"batched_10_n5000_{prec}_teams"] = {
-            "form": "teams", "solves_per_s": 10 / dtt, "batch_ms": dtt * 1e3,
+        out[f"batched_10_n5000_{prec}_{form}"] = {
+            "form": form, "solves_per_s": 10 / dtt, "batch_ms": dtt * 1e3,
             "plain_fp64_ms": dtp * 1e3, "plain_fp64_solves_per_s": 10 / dtp, "speedup_vs_plain_fp64": dtp / dtt,
             "iters_max": int(max(i.iters for i in i10)), "all_ok": all(i.status == 0 for i in i10),
             "w_max_abs_diff_vs_plain_fp64": float(max(np.max(np.abs(Wt10[lo:hi] - Wp10[lo:hi]))
@@ -469,7 +470,8 @@ def main():
         dev = torch.device("cuda", 0)
         legs = batch10_legs(ff, torch, dev, a.tol, max(1, a.steps), max(1, a.steps), warm=a.warmup > 0)
         print(json.dumps({"workload": "ten n=5000 k=60 m=80 single-period instances on one shared universe: "
-                                      "team form (FP64, FP32) against the plain FP64 kernel", **legs}), flush=True)
+                                      "lockstep (FP64) and team form (FP64, FP32) against the plain FP64 kernel",
+                          **legs}), flush=True)
         return
     if a.stress_n:
         print(json.dumps(stress_leg(ff, torch, a.stress_n, steps=max(1, a.steps), warmup=a.warmup, tol=a.tol)[0]),

@@ -101,7 +101,7 @@ typedef struct {
                               2: the lockstep form (every unconverged instance advances one
                               iteration per step, the products over the shared rows run as
                               float64 matrix-core GEMMs; FFO_FP64 only); 0 (default): the
-                              lockstep form when it applies (FFO_FP64, m + k <= 128),
+                              lockstep form when it applies (FFO_FP64, m + k <= 160),
                               else the team form                                      */
   int32_t autotune;        /* lockstep form only.  1 (default): on the first solve of a shape
                               the library times a few tile sizes and kernel arrangements and
@@ -263,7 +263,7 @@ ffo_status ffo_adjoint(int64_t n, int64_t k, int64_t m, int64_t T,
  *     float64 matrix-core GEMMs with ragged columns, then per-instance passes (budget
  *     multiplier, dual prox, Halpern step); converged instances are compacted out at
  *     every check; tile sizes come from the library's autotuner (opt->autotune).  The
- *     default for FFO_FP64 with m + k <= 128, B <= 65536, n_max <= 2^22.
+ *     default for FFO_FP64 with m + k <= 160, B <= 65536, n_max <= 2^22.
  *   teams: each instance runs the solve kernel's loop on a team of workgroups sized to
  *     its asset count (spare resident workgroups go to the teams with the most assets per
  *     workgroup, down to 128 assets each; constraint slice and per-asset state in LDS when

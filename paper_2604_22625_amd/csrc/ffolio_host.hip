@@ -1275,9 +1275,9 @@ ffo_status ffo_solve_batched(int64_t B, const int64_t* n_b, int64_t n_max, int64
   if (opt.batched_form < 0 || opt.batched_form > 2) return fail(FFO_EINVAL, "batched_form must be 0, 1 or 2");
   if (opt.autotune < -1 || opt.autotune > 1) return fail(FFO_EINVAL, "autotune must be -1, 0 or 1");
   {
-    const bool ls_ok = opt.precision == FFO_FP64 && m + k >= 1 && m + k <= 128 && B <= 65536 && n_max <= (1 << 22);
+    const bool ls_ok = opt.precision == FFO_FP64 && m + k >= 1 && m + k <= 160 && B <= 65536 && n_max <= (1 << 22);
     if (opt.batched_form == 2 && !ls_ok)
-      return fail(FFO_EINVAL, "the lockstep batched form needs FFO_FP64, 1 <= m + k <= 128, B <= 65536 and "
+      return fail(FFO_EINVAL, "the lockstep batched form needs FFO_FP64, 1 <= m + k <= 160, B <= 65536 and "
                               "n_max <= 2^22");
     if (opt.batched_form == 2 || (opt.batched_form == 0 && ls_ok))
       return batched_lockstep(B, n_b, n_max, k, m, F, Omega, delta, A, offs, alpha, s, q, w0, L, U, d, GMV, lambda1,

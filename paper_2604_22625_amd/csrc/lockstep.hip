@@ -387,7 +387,9 @@ __global__ __launch_bounds__(256) void k_kty(LsShared S, const double* __restric
 // POST: the staged inputs are formed here from the prox inputs (as k_post does): T(x),
 // xbar = 2 T(x) - x (the A operand), the trade duals and the Halpern step, or (check)
 // T(x), T(y_C) kept.
-template <int NRB, int CH, bool POST>
+// XB (more than NRB row blocks): wave rb takes blocks rb, rb + NRB, ..., loading each
+// block's rows over the chunk per group instead of keeping one block in registers.
+template <int NRB, int CH, bool POST, bool XB = false>
 __global__ __launch_bounds__(64 * NRB) void k_kx(LsShared S, const double* __restrict__ xin, int check) {
   __shared__ double xs[16 * (CH + 1)];   // the group's inputs over the chunk, row stride CH + 1
   __shared__ int64_t s_off[16];
@@ -400,15 +402,18 @@ __global__ __launch_bounds__(64 * NRB) void k_kx(LsShared S, const double* __res
   const int r = rb * 16 + cl;   // B-operand column: row of KD
   const int nt = blockDim.x;
   const double rho = S.rho;
+  const int nrb_all = S.nrp / 16;
   for (int tile = blockIdx.x; tile < ntile; tile += gridDim.x) {
     const int c = S.tileC[3 * tile], g0 = S.tileC[3 * tile + 1], g1 = S.tileC[3 * tile + 2];
     const int i0 = c * CH;
     // this wave's block of 16 rows over the chunk, kept in registers for all groups
-    double bk[CH / 4];
+    double bk[XB ? 1 : CH / 4];
+    if constexpr (!XB) {
 #pragma unroll
-    for (int q = 0; q < CH / 4; ++q) {
-      const int ii = i0 + 4 * q + rq;
-      bk[q] = ii < S.n_max ? S.KDT[(size_t)ii * S.nrp + r] : 0.0;
+      for (int q = 0; q < CH / 4; ++q) {
+        const int ii = i0 + 4 * q + rq;
+        bk[q] = ii < S.n_max ? S.KDT[(size_t)ii * S.nrp + r] : 0.0;
+      }
     }
     for (int g = g0; g < g1; ++g) {
       if (threadIdx.x < 16) {
@@ -484,13 +489,39 @@ __global__ __launch_bounds__(64 * NRB) void k_kx(LsShared S, const double* __res
         }
       }
       __syncthreads();
-      d4 acc = {0.0, 0.0, 0.0, 0.0};
+      if constexpr (!XB) {
+        d4 acc = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-      for (int q = 0; q < CH / 4; ++q) acc = mfma(xs[cl * ld + 4 * q + rq], bk[q], acc);   // A[slot cl][asset]
+        for (int q = 0; q < CH / 4; ++q) acc = mfma(xs[cl * ld + 4 * q + rq], bk[q], acc);   // A[slot cl][asset]
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const int s = 16 * g + 4 * j + rq;
-        if (s < nact) S.part[((size_t)c * S.B + s) * S.nrp + r] = acc[j];
+        for (int j = 0; j < 4; ++j) {
+          const int s = 16 * g + 4 * j + rq;
+          if (s < nact) S.part[((size_t)c * S.B + s) * S.nrp + r] = acc[j];
+        }
+      }
+      if constexpr (XB) {
+#pragma unroll 1
+        for (int rb2 = rb; rb2 < nrb_all; rb2 += NRB) {
+          const int r2 = rb2 * 16 + cl;
+          d4 acc2 = {0.0, 0.0, 0.0, 0.0};
+          // sixteen steps' rows at a time (a whole block's would not fit the registers)
+#pragma unroll 1
+          for (int q0 = 0; q0 < CH / 4; q0 += 16) {
+            double bk2[16];
+#pragma unroll
+            for (int q = 0; q < 16; ++q) {
+              const int ii = i0 + 4 * (q0 + q) + rq;
+              bk2[q] = ii < S.n_max ? S.KDT[(size_t)ii * S.nrp + r2] : 0.0;
+            }
+#pragma unroll
+            for (int q = 0; q < 16; ++q) acc2 = mfma(xs[cl * ld + 4 * (q0 + q) + rq], bk2[q], acc2);
+          }
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            const int s = 16 * g + 4 * j + rq;
+            if (s < nact) S.part[((size_t)c * S.B + s) * S.nrp + r2] = acc2[j];
+          }
+        }
       }
       __syncthreads();
     }
@@ -1029,6 +1060,7 @@ static int launch_kty_t(const LsShared& S, const double* yin, double* Rout, int 
   else if (S.nr4 <= 16) hipLaunchKernelGGL((k_kty<16, PRE>), dim3(grid), dim3(256), lds, st, S, yin, Rout);
   else if (S.nr4 <= 24) hipLaunchKernelGGL((k_kty<24, PRE>), dim3(grid), dim3(256), lds, st, S, yin, Rout);
   else if (S.nr4 <= 32) hipLaunchKernelGGL((k_kty<32, PRE>), dim3(grid), dim3(256), lds, st, S, yin, Rout);
+  else if (S.nr4 <= 40) hipLaunchKernelGGL((k_kty<40, PRE>), dim3(grid), dim3(256), lds, st, S, yin, Rout);
   else return (int)hipErrorInvalidValue;
   return (int)hipGetLastError();
 }
@@ -1039,22 +1071,26 @@ int ls_launch_kty(const LsShared& S, const double* yin, double* Rout, int grid, 
 
 template <bool POST>
 static int launch_kx_t(const LsShared& S, const double* xin, int check, int grid, hipStream_t st) {
-  const int nrb = S.nrp / 16;   // one wave per block of 16 rows
-  const dim3 blk(64 * nrb);
+  const int nrb = S.nrp / 16;   // one wave per block of 16 rows, at most 8 waves (the
+                                // waves of k_kx<8, ...> loop over further blocks)
+  const dim3 blk(64 * std::min(nrb, 8));
   if (POST && S.ch != 128) return (int)hipErrorInvalidValue;   // the fused form runs 128-asset chunks
   if (POST) {
     if (nrb <= 2) hipLaunchKernelGGL((k_kx<2, 128, true>), dim3(grid), blk, 0, st, S, xin, check);
     else if (nrb <= 5) hipLaunchKernelGGL((k_kx<5, 128, true>), dim3(grid), blk, 0, st, S, xin, check);
     else if (nrb <= 8) hipLaunchKernelGGL((k_kx<8, 128, true>), dim3(grid), blk, 0, st, S, xin, check);
+    else if (nrb <= 10) hipLaunchKernelGGL((k_kx<8, 128, true, true>), dim3(grid), blk, 0, st, S, xin, check);
     else return (int)hipErrorInvalidValue;
     return (int)hipGetLastError();
   }
   if (S.ch == 256 && nrb <= 2) hipLaunchKernelGGL((k_kx<2, 256, POST>), dim3(grid), blk, 0, st, S, xin, check);
   else if (S.ch == 256 && nrb <= 5) hipLaunchKernelGGL((k_kx<5, 256, POST>), dim3(grid), blk, 0, st, S, xin, check);
   else if (S.ch == 256 && nrb <= 8) hipLaunchKernelGGL((k_kx<8, 256, POST>), dim3(grid), blk, 0, st, S, xin, check);
+  else if (S.ch == 256 && nrb <= 10) hipLaunchKernelGGL((k_kx<8, 256, POST, true>), dim3(grid), blk, 0, st, S, xin, check);
   else if (S.ch == 128 && nrb <= 2) hipLaunchKernelGGL((k_kx<2, 128, POST>), dim3(grid), blk, 0, st, S, xin, check);
   else if (S.ch == 128 && nrb <= 5) hipLaunchKernelGGL((k_kx<5, 128, POST>), dim3(grid), blk, 0, st, S, xin, check);
   else if (S.ch == 128 && nrb <= 8) hipLaunchKernelGGL((k_kx<8, 128, POST>), dim3(grid), blk, 0, st, S, xin, check);
+  else if (S.ch == 128 && nrb <= 10) hipLaunchKernelGGL((k_kx<8, 128, POST, true>), dim3(grid), blk, 0, st, S, xin, check);
   else return (int)hipErrorInvalidValue;
   return (int)hipGetLastError();
 }
