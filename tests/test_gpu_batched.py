@@ -234,3 +234,19 @@ def test_lockstep_many_rows(autotune):
     W, infos = _solve_batched(batch, tol=1e-9, form="lockstep", autotune=autotune)
     for b in range(6):
         _check_against_oracle(batch, W, infos, b, 1e-9, w_tol=1e-5, obj_tol=1e-6)
+
+
+@pytest.mark.parametrize("autotune", [0, -1])
+def test_lockstep_at_its_row_limit(autotune):
+    """m + k = 160 rows, the lockstep form's limit: ten row blocks of 16 for eight K~ x
+    waves (two of them take a second block) and 40 MFMA steps per K~^T y tile, against the
+    oracle, in the fused (autotune 0) and the separate-pass (autotune -1) forms; one more
+    row is refused before any device work."""
+    ff = _gpu()
+    batch = make_batch(5, 60, 100, seed=29, n_lo=200, n_hi=700, n_max=700)
+    W, infos = _solve_batched(batch, tol=1e-9, form="lockstep", autotune=autotune)
+    for b in range(5):
+        _check_against_oracle(batch, W, infos, b, 1e-9, w_tol=1e-5, obj_tol=1e-6)
+    over = make_batch(2, 61, 100, seed=29, n_lo=200, n_hi=300, n_max=300)
+    with pytest.raises(ff.FolioError):
+        ff.solve_batched(over, tol=1e-6, form="lockstep")
