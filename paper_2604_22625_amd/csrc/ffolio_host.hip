@@ -923,6 +923,166 @@ ffo_status batched_lockstep(int64_t B, const int64_t* n_b, int64_t n_max, int64_
   return worst;
 }
 
+// ---- the team form: sizing, LDS placement, launches, results (ffo_solve_batched and
+// ffo_solve_many) ----
+
+// Instances in decreasing size, cut into launches whose minimal teams (ceil(n / nw_max)
+// workgroups) fit the resident grid of W workgroups; a launch's spare workgroups go to
+// the team with the most assets per workgroup while each keeps at least nw_min.
+struct TeamPlan {
+  std::vector<int64_t> order;                        // instances by decreasing n
+  std::vector<int> g;                                // team size per instance
+  std::vector<std::pair<int64_t, int64_t>> chunks;   // launches: [first, last) into order
+};
+
+TeamPlan plan_teams(int64_t B, const int64_t* n_b, int W, int nw_max, int nw_min) {
+  TeamPlan tp;
+  tp.order.resize(B);
+  for (int64_t b = 0; b < B; ++b) tp.order[b] = b;
+  std::stable_sort(tp.order.begin(), tp.order.end(), [&](int64_t a, int64_t b) { return n_b[a] > n_b[b]; });
+  tp.g.assign(B, 1);
+  {
+    int64_t first = 0, used = 0;
+    for (int64_t r = 0; r < B; ++r) {
+      const int64_t need = (n_b[tp.order[r]] + nw_max - 1) / nw_max;
+      if (used + need > W && r > first) {
+        tp.chunks.push_back({first, r});
+        first = r;
+        used = 0;
+      }
+      used += need;
+    }
+    tp.chunks.push_back({first, B});
+  }
+  for (const auto& ch : tp.chunks) {
+    int64_t used = 0;
+    for (int64_t r = ch.first; r < ch.second; ++r) {
+      tp.g[tp.order[r]] = (int)((n_b[tp.order[r]] + nw_max - 1) / nw_max);
+      used += tp.g[tp.order[r]];
+    }
+    while (used < W) {
+      int64_t best = -1;
+      double bv = 0.0;
+      for (int64_t r = ch.first; r < ch.second; ++r) {
+        const int64_t b = tp.order[r];
+        const double per = (double)n_b[b] / tp.g[b];
+        if ((double)n_b[b] / (tp.g[b] + 1) >= nw_min && per > bv) { bv = per; best = b; }
+      }
+      if (best < 0) break;
+      tp.g[best]++;
+      used++;
+    }
+  }
+  return tp;
+}
+
+// LDS placement per launch, in ffo_solve's order (constraint slice and per-asset state,
+// slice only, state only, neither): the first that fits every team of the launch and
+// keeps the launch resident; bfloat16 rows always stay in device memory.  Sets the
+// teams' lds_k / lds_state and returns each launch's placement and LDS bytes.
+void place_teams(const TeamPlan& tp, const ffo::DevProblem* hP, ffo::DevControl* hCt, int prec, size_t lds_lim,
+                 int cus, std::vector<int>& ckl, std::vector<int>& csl, std::vector<size_t>& clds) {
+  const size_t nc = tp.chunks.size();
+  ckl.assign(nc, 0);
+  csl.assign(nc, 0);
+  clds.assign(nc, 0);
+  for (size_t ci = 0; ci < nc; ++ci) {
+    const auto& ch = tp.chunks[ci];
+    int nb = 0;
+    for (int64_t r = ch.first; r < ch.second; ++r) nb += tp.g[tp.order[r]];
+    const int cand[4][2] = {{1, 1}, {1, 0}, {0, 1}, {0, 0}};
+    for (const auto& o : cand) {
+      if (o[0] && prec == ffo::PREC_BF16K) continue;
+      size_t need = 0;
+      for (int64_t r = ch.first; r < ch.second; ++r) {
+        ffo::DevControl t = hCt[tp.order[r]];
+        t.lds_k = o[0];
+        t.lds_state = o[1];
+        need = std::max(need, ffo::solve_lds_bytes(hP[tp.order[r]], t));
+      }
+      const bool last = o[0] == 0 && o[1] == 0;
+      if (last || (need <= lds_lim && ffo::solve_batch_occupancy(o[0], o[1], prec, need) * cus >= nb)) {
+        ckl[ci] = o[0];
+        csl[ci] = o[1];
+        clds[ci] = need;
+        break;
+      }
+    }
+    for (int64_t r = ch.first; r < ch.second; ++r) {
+      hCt[tp.order[r]].lds_k = ckl[ci];
+      hCt[tp.order[r]].lds_state = csl[ci];
+    }
+  }
+}
+
+// One cooperative launch of the team kernel per launch of the plan, in stream order.
+// ht_all / hr_all: host staging of W team and rank entries per launch; dteam / drank:
+// the device tables (W entries), rewritten before each launch.
+ffo_status launch_teams(const TeamPlan& tp, int W, const std::vector<int>& ckl, const std::vector<int>& csl,
+                        const std::vector<size_t>& clds, int prec, const ffo::DevProblem* dP,
+                        const ffo::DevState* dS, const ffo::DevControl* dCt, int* dteam, int* drank, int* ht_all,
+                        int* hr_all, void* stream) {
+  hipStream_t hs = (hipStream_t)stream;
+  for (size_t ci = 0; ci < tp.chunks.size(); ++ci) {
+    int* ht = ht_all + ci * W;
+    int* hr = hr_all + ci * W;
+    int nb = 0;
+    for (int64_t r = tp.chunks[ci].first; r < tp.chunks[ci].second; ++r) {
+      const int64_t b = tp.order[r];
+      for (int w = 0; w < tp.g[b]; ++w) { ht[nb] = (int)b; hr[nb] = w; ++nb; }
+    }
+    HIPCHK(hipMemcpyAsync(dteam, ht, (size_t)nb * 4, hipMemcpyHostToDevice, hs));
+    HIPCHK(hipMemcpyAsync(drank, hr, (size_t)nb * 4, hipMemcpyHostToDevice, hs));
+    if (int e = ffo::launch_solve_batch(dP, dS, dCt, dteam, drank, nb, ckl[ci], csl[ci], prec, stream, clds[ci]))
+      return fail(FFO_EDEVICE, std::string("cooperative launch of the batched solve kernel failed: ") +
+                                   hipGetErrorString((hipError_t)e));
+  }
+  return FFO_OK;
+}
+
+// Statuses and infos of every instance after the team launches; returns the most severe
+// status (FFO_EDEVICE > FFO_NUMERIC > FFO_INFEASIBLE > FFO_TIMEOUT > FFO_NOT_CONVERGED).
+// verbose: the slowest instance's phase times on stderr (verbose >= 2: every instance's).
+ffo_status collect_teams(int64_t B, const int64_t* n_b, const double* hinfo, const int32_t* hstat, float ms_setup,
+                         float ms_iter, const ffo::DevControl* hCt, int verbose, ffo_info* infos) {
+  ffo_status worst = FFO_OK;
+  auto rank = [](ffo_status x) {
+    return x == FFO_EDEVICE ? 5 : x == FFO_NUMERIC ? 4 : x == FFO_INFEASIBLE ? 3 : x == FFO_TIMEOUT ? 2
+           : x == FFO_NOT_CONVERGED ? 1 : 0;
+  };
+  for (int64_t b = 0; b < B; ++b) {
+    const ffo_status st = status_of(hstat[b]);
+    fill_info(&infos[b], st, hinfo + (size_t)b * ffo::INFO_LEN, ms_setup, ms_iter);
+    if (rank(st) > rank(worst)) worst = st;
+  }
+  if (verbose) {
+    int64_t slow = 0;
+    for (int64_t b = 1; b < B; ++b)
+      if (hinfo[(size_t)b * ffo::INFO_LEN + ffo::IX_T_ITER] > hinfo[(size_t)slow * ffo::INFO_LEN + ffo::IX_T_ITER]) slow = b;
+    auto show = [&](const char* what, int64_t b) {
+      const double* h = hinfo + (size_t)b * ffo::INFO_LEN;
+      std::fprintf(stderr,
+                   "[ffo batch] %s instance %lld: n %lld team %d xmode %d iters %.0f spec_miss %.0f exchanges %.0f "
+                   "| t_iter %.3f ms t_check %.3f ms t_wait %.3f ms | A %.3f B %.3f C %.3f D %.3f pre %.3f read %.3f "
+                   "| B1 %.3f (stats %.3f) B2 %.3f B3 %.3f ms\n",
+                   what, (long long)b, (long long)n_b[b], hCt[b].nwg, hCt[b].xmode, h[ffo::IX_ITERS],
+                   h[ffo::IX_SPEC_MISS], h[ffo::IX_EXCHANGES], h[ffo::IX_T_ITER] * 1e3, h[ffo::IX_T_CHECK] * 1e3,
+                   h[ffo::IX_T_WAIT] * 1e3, h[ffo::IX_T_PHA] * 1e3, h[ffo::IX_T_PHB] * 1e3, h[ffo::IX_T_PHC] * 1e3,
+                   h[ffo::IX_T_PHD] * 1e3, h[ffo::IX_T_PRE] * 1e3, h[ffo::IX_T_READ] * 1e3, h[ffo::IX_T_B1] * 1e3,
+                   h[ffo::IX_T_B1S] * 1e3, h[ffo::IX_T_B2] * 1e3, h[ffo::IX_T_B3] * 1e3);
+    };
+    show("slowest", slow);
+    if (verbose >= 2)
+      for (int64_t b = 0; b < B; ++b) show("every", b);
+  }
+  if (worst == FFO_NOT_CONVERGED) g_err = "iteration limit reached for at least one instance";
+  else if (worst == FFO_TIMEOUT) g_err = "time limit reached for at least one instance";
+  else if (worst == FFO_NUMERIC) g_err = "NaN or Inf in an FP64 check of at least one instance";
+  else if (worst == FFO_INFEASIBLE) g_err = "at least one instance is infeasible";
+  else if (worst == FFO_EDEVICE) g_err = "a team ended without a result (bounded wait expired)";
+  return worst;
+}
+
 // ---- memory of the allocation-free entry point (ffo_solve_noalloc) ----
 // One static device array per GPU (each device holds its own copy of `scratch` for the
 // life of the process).  Host code never passes `scratch` itself to a kernel or a copy:
@@ -1324,44 +1484,9 @@ ffo_status ffo_solve_batched(int64_t B, const int64_t* n_b, int64_t n_max, int64
   if (occ < 1) return fail(FFO_EDEVICE, "the batched solve kernel cannot be resident");
   const int W = occ * cus;
   // instances in decreasing size, cut into launches whose minimal teams fit the resident grid
-  std::vector<int64_t> order(B);
-  for (int64_t b = 0; b < B; ++b) order[b] = b;
-  std::stable_sort(order.begin(), order.end(), [&](int64_t a, int64_t b) { return n_b[a] > n_b[b]; });
-  std::vector<int> g(B, 1);
-  std::vector<std::pair<int64_t, int64_t>> chunks;   // [first, last) into order
-  {
-    int64_t first = 0, used = 0;
-    for (int64_t r = 0; r < B; ++r) {
-      const int64_t need = (n_b[order[r]] + NW_MAX - 1) / NW_MAX;
-      if (used + need > W && r > first) {
-        chunks.push_back({first, r});
-        first = r;
-        used = 0;
-      }
-      used += need;
-    }
-    chunks.push_back({first, B});
-  }
-  for (const auto& ch : chunks) {
-    int64_t used = 0;
-    for (int64_t r = ch.first; r < ch.second; ++r) {
-      g[order[r]] = (int)((n_b[order[r]] + NW_MAX - 1) / NW_MAX);
-      used += g[order[r]];
-    }
-    // spare workgroups go to the team with the most assets per workgroup
-    while (used < W) {
-      int64_t best = -1;
-      double bv = 0.0;
-      for (int64_t r = ch.first; r < ch.second; ++r) {
-        const int64_t b = order[r];
-        const double per = (double)n_b[b] / g[b];
-        if ((double)n_b[b] / (g[b] + 1) >= NW_MIN && per > bv) { bv = per; best = b; }
-      }
-      if (best < 0) break;
-      g[best]++;
-      used++;
-    }
-  }
+  const TeamPlan tp = plan_teams(B, n_b, W, NW_MAX, NW_MIN);
+  const std::vector<int>& g = tp.g;
+  const auto& chunks = tp.chunks;
 
   // ---- workspace layout ----
   size_t off = 0;
@@ -1465,62 +1590,18 @@ ffo_status ffo_solve_batched(int64_t B, const int64_t* n_b, int64_t n_max, int64
     c.xmode = g[b] == 1 ? ffo::XM_LOCAL : ffo::XM_ATOMIC;
     hCt[b] = c;
   }
-  // LDS placement per launch, as in ffo_solve: the constraint slice, then the per-asset
-  // state, when every team of the launch fits and the launch stays resident (bfloat16
-  // rows are always read from device memory)
-  std::vector<int> ckl(chunks.size(), 0), csl(chunks.size(), 0);
-  std::vector<size_t> clds(chunks.size(), 0);
-  const size_t lds_lim = std::min<size_t>(prop.sharedMemPerBlock, 160 * 1024);
-  for (size_t ci = 0; ci < chunks.size(); ++ci) {
-    int nb = 0;
-    for (int64_t r = chunks[ci].first; r < chunks[ci].second; ++r) nb += g[order[r]];
-    const int order2[4][2] = {{1, 1}, {1, 0}, {0, 1}, {0, 0}};
-    for (const auto& o : order2) {
-      if (o[0] && bf16rows) continue;
-      size_t need = 0;
-      for (int64_t r = chunks[ci].first; r < chunks[ci].second; ++r) {
-        ffo::DevControl t = hCt[order[r]];
-        t.lds_k = o[0];
-        t.lds_state = o[1];
-        need = std::max(need, ffo::solve_lds_bytes(hP[order[r]], t));
-      }
-      const bool last = o[0] == 0 && o[1] == 0;
-      if (last || (need <= lds_lim && ffo::solve_batch_occupancy(o[0], o[1], prec, need) * cus >= nb)) {
-        ckl[ci] = o[0];
-        csl[ci] = o[1];
-        clds[ci] = need;
-        break;
-      }
-    }
-    for (int64_t r = chunks[ci].first; r < chunks[ci].second; ++r) {
-      hCt[order[r]].lds_k = ckl[ci];
-      hCt[order[r]].lds_state = csl[ci];
-    }
-  }
+  std::vector<int> ckl, csl;
+  std::vector<size_t> clds;
+  place_teams(tp, hP, hCt, prec, std::min<size_t>(prop.sharedMemPerBlock, 160 * 1024), cus, ckl, csl, clds);
   HIPCHK(hipMemcpyAsync(Bd + oP, hP, (size_t)B * sizeof(ffo::DevProblem), hipMemcpyHostToDevice, hs));
   HIPCHK(hipMemcpyAsync(Bd + oS, hS, (size_t)B * sizeof(ffo::DevState), hipMemcpyHostToDevice, hs));
   HIPCHK(hipMemcpyAsync(Bd + oCt, hCt, (size_t)B * sizeof(ffo::DevControl), hipMemcpyHostToDevice, hs));
   HIPCHK(hipEventRecord(ws->ev[1], hs));
-
-  // ---- one cooperative launch per chunk ----
-  for (size_t ci = 0; ci < chunks.size(); ++ci) {
-    int* ht = (int*)(Hb + hteam_o) + ci * W;
-    int* hr = (int*)(Hb + hrank_o) + ci * W;
-    int nb = 0;
-    const size_t lds = clds[ci];
-    for (int64_t r = chunks[ci].first; r < chunks[ci].second; ++r) {
-      const int64_t b = order[r];
-      for (int w = 0; w < g[b]; ++w) { ht[nb] = (int)b; hr[nb] = w; ++nb; }
-    }
-    // the device team tables are rewritten in stream order, after the previous launch
-    HIPCHK(hipMemcpyAsync(Bd + oteam, ht, (size_t)nb * 4, hipMemcpyHostToDevice, hs));
-    HIPCHK(hipMemcpyAsync(Bd + orank, hr, (size_t)nb * 4, hipMemcpyHostToDevice, hs));
-    if (int e = ffo::launch_solve_batch((const ffo::DevProblem*)(Bd + oP), (const ffo::DevState*)(Bd + oS),
-                                        (const ffo::DevControl*)(Bd + oCt), (const int*)(Bd + oteam),
-                                        (const int*)(Bd + orank), nb, ckl[ci], csl[ci], prec, stream, lds))
-      return fail(FFO_EDEVICE, std::string("cooperative launch of the batched solve kernel failed: ") +
-                                   hipGetErrorString((hipError_t)e));
-  }
+  if (ffo_status st = launch_teams(tp, W, ckl, csl, clds, prec, (const ffo::DevProblem*)(Bd + oP),
+                                   (const ffo::DevState*)(Bd + oS), (const ffo::DevControl*)(Bd + oCt),
+                                   (int*)(Bd + oteam), (int*)(Bd + orank), (int*)(Hb + hteam_o),
+                                   (int*)(Hb + hrank_o), stream))
+    return st;
   HIPCHK(hipEventRecord(ws->ev[2], hs));
   double* hinfo = (double*)(Hb + hinfo_o);
   int32_t* hstat = (int32_t*)(Hb + hstat_o);
@@ -1530,46 +1611,211 @@ ffo_status ffo_solve_batched(int64_t B, const int64_t* n_b, int64_t n_max, int64
   float ms_setup = 0.f, ms_iter = 0.f;
   hipEventElapsedTime(&ms_setup, ws->ev[0], ws->ev[1]);
   hipEventElapsedTime(&ms_iter, ws->ev[1], ws->ev[2]);
-  ffo_status worst = FFO_OK;
-  auto rank = [](ffo_status x) {
-    return x == FFO_EDEVICE ? 5 : x == FFO_NUMERIC ? 4 : x == FFO_INFEASIBLE ? 3 : x == FFO_TIMEOUT ? 2
-           : x == FFO_NOT_CONVERGED ? 1 : 0;
-  };
-  for (int64_t b = 0; b < B; ++b) {
-    const ffo_status st = status_of(hstat[b]);
-    fill_info(&infos[b], st, hinfo + (size_t)b * ffo::INFO_LEN, ms_setup, ms_iter);
-    if (rank(st) > rank(worst)) worst = st;
-  }
-  if (opt.verbose) {
+  if (opt.verbose)
     std::fprintf(stderr,
                  "[ffo batch] B %lld launches %zu resident %d (occupancy %d) lds %zu | first launch: slice in LDS %d, "
                  "state in LDS %d, %zu bytes | setup %.3f ms solve %.3f ms\n",
                  (long long)B, chunks.size(), W, occ, lds_cap, ckl[0], csl[0], clds[0], ms_setup, ms_iter);
-    int64_t slow = 0;
-    for (int64_t b = 1; b < B; ++b)
-      if (hinfo[(size_t)b * ffo::INFO_LEN + ffo::IX_T_ITER] > hinfo[(size_t)slow * ffo::INFO_LEN + ffo::IX_T_ITER]) slow = b;
-    auto show = [&](const char* what, int64_t b) {
-      const double* h = hinfo + (size_t)b * ffo::INFO_LEN;
-      std::fprintf(stderr,
-                   "[ffo batch] %s instance %lld: n %lld team %d xmode %d iters %.0f spec_miss %.0f exchanges %.0f "
-                   "| t_iter %.3f ms t_check %.3f ms t_wait %.3f ms | A %.3f B %.3f C %.3f D %.3f pre %.3f read %.3f "
-                   "| B1 %.3f (stats %.3f) B2 %.3f B3 %.3f ms\n",
-                   what, (long long)b, (long long)n_b[b], hCt[b].nwg, hCt[b].xmode, h[ffo::IX_ITERS],
-                   h[ffo::IX_SPEC_MISS], h[ffo::IX_EXCHANGES], h[ffo::IX_T_ITER] * 1e3, h[ffo::IX_T_CHECK] * 1e3,
-                   h[ffo::IX_T_WAIT] * 1e3, h[ffo::IX_T_PHA] * 1e3, h[ffo::IX_T_PHB] * 1e3, h[ffo::IX_T_PHC] * 1e3,
-                   h[ffo::IX_T_PHD] * 1e3, h[ffo::IX_T_PRE] * 1e3, h[ffo::IX_T_READ] * 1e3, h[ffo::IX_T_B1] * 1e3,
-                   h[ffo::IX_T_B1S] * 1e3, h[ffo::IX_T_B2] * 1e3, h[ffo::IX_T_B3] * 1e3);
-    };
-    show("slowest", slow);
-    if (opt.verbose >= 2)
-      for (int64_t b = 0; b < B; ++b) show("every", b);
+  return collect_teams(B, n_b, hinfo, hstat, ms_setup, ms_iter, hCt, opt.verbose, infos);
+}
+
+ffo_status ffo_solve_many(int64_t B, const int64_t* n, int64_t k, int64_t m, const double* const* alpha,
+                          const double* const* F, const double* const* Omega, const double* const* delta,
+                          const double* const* s, const double* const* q, const double* const* A,
+                          const double* const* L, const double* const* U, const double* const* w0, double d,
+                          double GMV, double lambda1, double lambda2, double lambda3, const ffo_options* opt_in,
+                          void* stream, double* const* w_out, ffo_info* infos) {
+  g_err.clear();
+  ffo_options opt;
+  ffo_default_options(&opt);
+  if (opt_in) opt = *opt_in;
+  // ---- host-only validation (no device work before this point) ----
+  if (B < 1 || B > (1 << 16)) return fail(FFO_EINVAL, "B must lie in [1, 2^16]");
+  if (!n || !alpha || !delta || !s || !q || !w0 || !w_out || !infos)
+    return fail(FFO_EINVAL, "null host array (n, alpha, delta, s, q, w0, w_out or infos)");
+  if (k > 0 && (!F || !Omega)) return fail(FFO_EINVAL, "F and Omega are required when k > 0");
+  if (m > 0 && (!A || !L || !U)) return fail(FFO_EINVAL, "A, L and U are required when m > 0");
+  for (int64_t b = 0; b < B; ++b) {
+    if (ffo_status st = check_problem_args(n[b], k, m, 0, alpha[b], k ? F[b] : nullptr, k ? Omega[b] : nullptr,
+                                           delta[b], s[b], q[b], d, m ? A[b] : nullptr, m ? L[b] : nullptr,
+                                           m ? U[b] : nullptr, w0[b], GMV, lambda1, lambda2, lambda3, nullptr))
+      return fail(st, "instance " + std::to_string(b) + ": " + g_err);
+    if (!w_out[b]) return fail(FFO_EINVAL, "instance " + std::to_string(b) + ": null w_out");
+    if (n[b] > (1 << 24)) return fail(FFO_EINVAL, "instance " + std::to_string(b) + ": n must be <= 2^24");
   }
-  if (worst == FFO_NOT_CONVERGED) g_err = "iteration limit reached for at least one instance";
-  else if (worst == FFO_TIMEOUT) g_err = "time limit reached for at least one instance";
-  else if (worst == FFO_NUMERIC) g_err = "NaN or Inf in an FP64 check of at least one instance";
-  else if (worst == FFO_INFEASIBLE) g_err = "at least one instance is infeasible";
-  else if (worst == FFO_EDEVICE) g_err = "a team ended without a result (bounded wait expired)";
-  return worst;
+  if (ffo_status st = check_options(opt)) return st;
+  if (opt.precision != FFO_FP64 && opt.precision != FFO_FP32)
+    return fail(FFO_EINVAL, "ffo_solve_many takes FFO_FP64 or FFO_FP32");
+
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  hipDeviceProp_t prop;
+  HIPCHK(hipGetDeviceProperties(&prop, dev));
+  int wall_khz = 0;
+  if (hipDeviceGetAttribute(&wall_khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess || wall_khz <= 0)
+    wall_khz = 100000;
+  const int cus = std::max(1, prop.multiProcessorCount);
+  const int nr = (int)(m + k);
+  const int prec = opt.precision == FFO_FP32 ? ffo::PREC_FP32 : ffo::PREC_FP64;
+
+  // ---- control and team sizing, as in the team form of ffo_solve_batched ----
+  ffo::DevProblem p0{};
+  p0.k = (int)k; p0.m = (int)m; p0.P = 1; p0.Tp = 1; p0.nr = nr; p0.multi = 0; p0.kscaled = 1;
+  ffo::DevControl c0{};
+  c0.tol = opt.tol_rel_kkt; c0.time_limit_s = opt.time_limit_s;
+  c0.r_suff = opt.restart_suff; c0.r_nec = opt.restart_nec; c0.r_art = opt.restart_art;
+  c0.rho = opt.reflection; c0.eta_safety = 0.95; c0.max_iter = opt.max_iter; c0.check_every = opt.check_every;
+  c0.npow = 40; c0.verbose = opt.verbose; c0.spin_limit = 1u << 26; c0.wall_hz = (double)wall_khz * 1e3;
+  c0.prec = prec; c0.spec = 1; c0.lds_k = 0; c0.lds_state = 0; c0.infeas = opt.infeasibility_check ? 1 : 0;
+  c0.vmax = ffo::solve_vmax(p0);
+  const int NW_MAX = 2048, NW_MIN = 128;   // as in the team form of ffo_solve_batched
+  size_t lds_cap = 0;
+  {
+    ffo::DevProblem pp = p0;
+    ffo::DevControl cc = c0;
+    pp.n = NW_MAX; cc.nw = NW_MAX; cc.nwg = 1; cc.xmode = ffo::XM_LOCAL;
+    lds_cap = ffo::solve_lds_bytes(pp, cc);
+  }
+  const size_t lds_lim = std::min<size_t>(prop.sharedMemPerBlock, 160 * 1024);
+  if (lds_cap > lds_lim) return fail(FFO_EINVAL, "m + k too large for the batched working set");
+  const int occ = ffo::solve_batch_occupancy(0, 0, prec, lds_cap);
+  if (occ < 1) return fail(FFO_EDEVICE, "the batched solve kernel cannot be resident");
+  const int W = occ * cus;
+  const TeamPlan tp = plan_teams(B, n, W, NW_MAX, NW_MIN);
+
+  // ---- workspace: each instance's scaled rows, scales, costs and state, as ffo_solve's ----
+  struct Inst {
+    int ldk;
+    size_t K, Kf, dr, dc, drC, ar, cv, ca, cb, bF, cr, C, st[9];
+  };
+  std::vector<Inst> io(B);
+  size_t off = 0;
+  auto carve = [&](size_t cnt, size_t elt) { const size_t o = off; off = align_up(off + cnt * elt); return o; };
+  for (int64_t b = 0; b < B; ++b) {
+    Inst& r = io[b];
+    const size_t nb = (size_t)n[b];
+    r.ldk = (int)((n[b] + 63) / 64 * 64);
+    r.K = carve((size_t)std::max(nr, 1) * r.ldk, 8);
+    r.Kf = carve(prec == ffo::PREC_FP32 ? (size_t)std::max(nr, 1) * r.ldk : 1, 4);
+    r.dr = carve(std::max(nr, 1), 8); r.dc = carve(nb, 8); r.drC = carve(nb, 8); r.ar = carve(nb, 8);
+    r.cv = carve(nb, 8); r.ca = carve(nb, 8); r.cb = carve(nb, 8);
+    r.bF = carve(std::max<int64_t>(k, 1), 8); r.cr = carve(1, 8); r.C = carve(std::max<int64_t>(k * k, 1), 8);
+    for (auto& o : r.st) o = carve(nb, 8);
+  }
+  const size_t oxb = carve((size_t)B * 3 * c0.vmax, 8), obar = carve(B, 8);
+  const size_t oinfo = carve((size_t)B * ffo::INFO_LEN, 8), ostat = carve(B, 4), oflag = carve(1, 4);
+  const size_t oP = carve(B, sizeof(ffo::DevProblem)), oS = carve(B, sizeof(ffo::DevState));
+  const size_t oCt = carve(B, sizeof(ffo::DevControl)), oteam = carve(W, 4), orank = carve(W, 4);
+  const size_t total = off;
+  const size_t kk = (size_t)std::max<int64_t>(k * k, 1);
+  size_t hoff = 0;
+  auto hcarve = [&](size_t bytes) { const size_t o = hoff; hoff = align_up(hoff + bytes); return o; };
+  const size_t hOm_o = hcarve((size_t)B * kk * 8), hC_o = hcarve(kk * 8), hWk_o = hcarve(2 * kk * 8);
+  const size_t hflag_o = hcarve(4), hinfo_o = hcarve((size_t)B * ffo::INFO_LEN * 8), hstat_o = hcarve((size_t)B * 4);
+  const size_t hP_o = hcarve((size_t)B * sizeof(ffo::DevProblem)), hS_o = hcarve((size_t)B * sizeof(ffo::DevState));
+  const size_t hCt_o = hcarve((size_t)B * sizeof(ffo::DevControl));
+  const size_t hteam_o = hcarve((size_t)W * 4 * tp.chunks.size()), hrank_o = hcarve((size_t)W * 4 * tp.chunks.size());
+  const size_t host_bytes = hoff;
+
+  Workspace* ws = nullptr;
+  if (ffo_status st = get_workspace(dev, stream, total, host_bytes, &ws, 5)) return st;
+  char* Bd = (char*)ws->base;
+  char* Hb = (char*)ws->host;
+  auto D = [&](size_t o) { return (double*)(Bd + o); };
+  hipStream_t hs = (hipStream_t)stream;
+  int* hflag = (int*)(Hb + hflag_o);
+
+  // ---- device value checks of every instance, and the Omegas to the host (one synchronisation) ----
+  HIPCHK(hipEventRecord(ws->ev[0], hs));
+  HIPCHK(fill(Bd + oflag, 4, 0u, hs));
+  for (int64_t b = 0; b < B; ++b) {
+    hipLaunchKernelGGL(k_validate, dim3(64), dim3(256), 0, hs, n[b], n[b], n[b], n[b] * k, m, alpha[b],
+                       k ? F[b] : nullptr, delta[b], s[b], q[b], m ? L[b] : nullptr, m ? U[b] : nullptr, w0[b],
+                       (const double*)nullptr, (int*)(Bd + oflag));
+    if (k > 0)
+      HIPCHK(hipMemcpyAsync(Hb + hOm_o + (size_t)b * kk * 8, Omega[b], (size_t)k * k * 8, hipMemcpyDeviceToHost, hs));
+  }
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipMemcpyAsync(hflag, Bd + oflag, 4, hipMemcpyDeviceToHost, hs));
+  HIPCHK(hipStreamSynchronize(hs));
+  if (*hflag) return fail(FFO_EINVAL, bad_values(*hflag));
+
+  // ---- setup of every instance (ffo_solve's kernels), problem, state and control records ----
+  const double g1 = lambda1 * GMV, g2 = lambda2, g3 = lambda3;
+  ffo::DevProblem* hP = (ffo::DevProblem*)(Hb + hP_o);
+  ffo::DevState* hS = (ffo::DevState*)(Hb + hS_o);
+  ffo::DevControl* hCt = (ffo::DevControl*)(Hb + hCt_o);
+  for (int64_t b = 0; b < B; ++b) {
+    const Inst& r = io[b];
+    if (k > 0) {
+      double* hC = (double*)(Hb + hC_o);
+      if (!factor_omega((int)k, (double*)(Hb + hOm_o + (size_t)b * kk * 8), hC, (double*)(Hb + hWk_o)))
+        return fail(FFO_EINVAL, "instance " + std::to_string(b) + ": Omega must be symmetric positive semidefinite");
+      // the copy reads the host staging at once (pageable order: the stream waits for it)
+      HIPCHK(hipMemcpyAsync(D(r.C), hC, (size_t)k * k * 8, hipMemcpyHostToDevice, hs));
+      HIPCHK(hipStreamSynchronize(hs));
+    }
+    if (ffo::launch_setup(n[b], k, m, 1, 1, r.ldk, k ? F[b] : nullptr, D(r.C), m ? A[b] : nullptr, delta[b], s[b],
+                          q[b], nullptr, g1, g2, g3, D(r.K), D(r.dr), D(r.dc), D(r.drC), D(r.ar), D(r.cv), D(r.ca),
+                          D(r.cb), D(r.bF), D(r.cr), stream))
+      return fail(FFO_EDEVICE, "setup kernel launch failed");
+    if (prec == ffo::PREC_FP32 && ffo::launch_to_float(D(r.K), (float*)(Bd + r.Kf), (int64_t)nr * r.ldk, stream))
+      return fail(FFO_EDEVICE, "setup kernel launch failed");
+    ffo::DevProblem p = p0;
+    p.n = (int)n[b]; p.ldk = r.ldk;
+    p.K = D(r.K); p.Kf = prec == ffo::PREC_FP32 ? (const float*)(Bd + r.Kf) : nullptr;
+    p.dr = D(r.dr); p.dc = D(r.dc); p.drC = D(r.drC); p.alpha = alpha[b]; p.arisk = D(r.ar); p.cvec = D(r.cv);
+    p.ca = D(r.ca); p.cb = D(r.cb); p.w0 = w0[b]; p.wT = nullptr;
+    p.L = m ? L[b] : nullptr; p.U = m ? U[b] : nullptr;
+    p.bF = D(r.bF); p.crisk = D(r.cr); p.g1 = g1; p.d = d; p.g2 = g2;
+    hP[b] = p;
+    ffo::DevState sv{};
+    sv.xs = D(r.st[0]); sv.x0s = D(r.st[1]); sv.Txs = D(r.st[2]);
+    sv.bb = D(r.st[3]); sv.aa = D(r.st[4]); sv.vpow = D(r.st[5]);
+    sv.ysC = D(r.st[6]); sv.ys0C = D(r.st[7]); sv.TysC = D(r.st[8]);
+    sv.xbuf = D(oxb) + (size_t)b * 3 * c0.vmax; sv.bar = (unsigned long long*)(Bd + obar) + b;
+    sv.info = D(oinfo) + (size_t)b * ffo::INFO_LEN; sv.status = (int32_t*)(Bd + ostat) + b;
+    sv.w_out = w_out[b]; sv.y_out = nullptr;
+    hS[b] = sv;
+    ffo::DevControl c = c0;
+    c.nwg = tp.g[b];
+    c.nw = (int)((n[b] + tp.g[b] - 1) / tp.g[b]);
+    c.xmode = tp.g[b] == 1 ? ffo::XM_LOCAL : ffo::XM_ATOMIC;
+    hCt[b] = c;
+  }
+  HIPCHK(fill(Bd + oxb, (size_t)B * 3 * c0.vmax * 8, 0u, hs));
+  HIPCHK(fill(Bd + obar, (size_t)B * 8, 0u, hs));
+  HIPCHK(fill(Bd + oinfo, (size_t)B * ffo::INFO_LEN * 8, 0u, hs));
+  HIPCHK(fill(Bd + ostat, (size_t)B * 4, 0xffffffffu, hs));
+
+  // ---- LDS placement, records to the device, one cooperative launch per chunk ----
+  std::vector<int> ckl, csl;
+  std::vector<size_t> clds;
+  place_teams(tp, hP, hCt, prec, lds_lim, cus, ckl, csl, clds);
+  HIPCHK(hipMemcpyAsync(Bd + oP, hP, (size_t)B * sizeof(ffo::DevProblem), hipMemcpyHostToDevice, hs));
+  HIPCHK(hipMemcpyAsync(Bd + oS, hS, (size_t)B * sizeof(ffo::DevState), hipMemcpyHostToDevice, hs));
+  HIPCHK(hipMemcpyAsync(Bd + oCt, hCt, (size_t)B * sizeof(ffo::DevControl), hipMemcpyHostToDevice, hs));
+  HIPCHK(hipEventRecord(ws->ev[1], hs));
+  if (ffo_status st = launch_teams(tp, W, ckl, csl, clds, prec, (const ffo::DevProblem*)(Bd + oP),
+                                   (const ffo::DevState*)(Bd + oS), (const ffo::DevControl*)(Bd + oCt),
+                                   (int*)(Bd + oteam), (int*)(Bd + orank), (int*)(Hb + hteam_o),
+                                   (int*)(Hb + hrank_o), stream))
+    return st;
+  HIPCHK(hipEventRecord(ws->ev[2], hs));
+  double* hinfo = (double*)(Hb + hinfo_o);
+  int32_t* hstat = (int32_t*)(Hb + hstat_o);
+  HIPCHK(hipMemcpyAsync(hinfo, Bd + oinfo, (size_t)B * ffo::INFO_LEN * 8, hipMemcpyDeviceToHost, hs));
+  HIPCHK(hipMemcpyAsync(hstat, Bd + ostat, (size_t)B * 4, hipMemcpyDeviceToHost, hs));
+  HIPCHK(hipStreamSynchronize(hs));
+  float ms_setup = 0.f, ms_iter = 0.f;
+  hipEventElapsedTime(&ms_setup, ws->ev[0], ws->ev[1]);
+  hipEventElapsedTime(&ms_iter, ws->ev[1], ws->ev[2]);
+  if (opt.verbose)
+    std::fprintf(stderr,
+                 "[ffo many] B %lld launches %zu resident %d (occupancy %d) | first launch: slice in LDS %d, state in "
+                 "LDS %d, %zu bytes | setup %.3f ms solve %.3f ms\n",
+                 (long long)B, tp.chunks.size(), W, occ, ckl[0], csl[0], clds[0], ms_setup, ms_iter);
+  return collect_teams(B, n, hinfo, hstat, ms_setup, ms_iter, hCt, opt.verbose, infos);
 }
 
 // Extra diagnostics of the last solve on this thread's (device, stream): not part of the

@@ -138,6 +138,51 @@ def test_batched_rejects_invalid_arguments(kw, needle):
     assert needle in msg, msg
 
 
+def _call_many(B=3, n=(5, 7, 9), k=2, m=1, d=1.5, precision=0, null=(), null_at=None):
+    """ffo_solve_many with fake device pointers in real host pointer arrays; invalid
+    arguments must be rejected before any device pointer is touched.  null: arrays passed
+    as NULL; null_at: (name, b) sets one instance's pointer to NULL."""
+    import numpy as np
+    fake = 0x1000
+    nn = np.ascontiguousarray(np.asarray(n, dtype=np.int64))
+    arrays = {}
+    for name in ("alpha", "F", "Omega", "delta", "s", "q", "A", "L", "U", "w0", "w_out"):
+        a = (ctypes.c_void_p * max(B, 1))(*([fake] * max(B, 1)))
+        if null_at and null_at[0] == name:
+            a[null_at[1]] = None
+        arrays[name] = None if name in null else ctypes.cast(a, ctypes.c_void_p)
+        arrays[name + "_keep"] = a
+    infos = (ff._Info * max(B, 1))()
+    o = ff.default_options()
+    o.precision = precision
+    lib = ff.lib()
+    g = arrays
+    rc = lib.ffo_solve_many(B, nn.ctypes.data_as(ctypes.c_void_p), k, m, g["alpha"], g["F"], g["Omega"], g["delta"],
+                            g["s"], g["q"], g["A"], g["L"], g["U"], g["w0"], d, 1e9, 1e-9, 1.0, 1.0,
+                            ctypes.byref(o), None, g["w_out"], infos)
+    return rc, lib.ffo_last_error().decode()
+
+
+@pytest.mark.parametrize("kw,needle", [
+    (dict(B=0, n=()), "B must"),
+    (dict(n=(5, 0, 9)), "n must"),
+    (dict(k=129), "k must"),
+    (dict(m=-1), "m must"),
+    (dict(d=1.0), "d must"),
+    (dict(precision=2), "FFO_FP64 or FFO_FP32"),
+    (dict(null=("alpha",)), "null host array"),
+    (dict(null=("w_out",)), "null host array"),
+    (dict(null=("F",)), "F and Omega"),
+    (dict(null=("L",)), "A, L and U"),
+    (dict(null_at=("s", 1)), "instance 1"),
+    (dict(null_at=("w_out", 2)), "instance 2"),
+])
+def test_many_rejects_invalid_arguments(kw, needle):
+    rc, msg = _call_many(**kw)
+    assert rc == 1, (rc, msg)
+    assert needle in msg, msg
+
+
 @pytest.mark.parametrize("omega", [-1.0, float("nan"), float("inf")])
 def test_warm_start_rejects_bad_primal_weight(omega):
     lib = ff.lib()

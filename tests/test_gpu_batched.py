@@ -10,7 +10,7 @@ import pytest
 
 import oracle
 from oracle.problem import normalize, objective
-from synth import make_batch, batch_instance, make_config
+from synth import make_batch, batch_instance, make_config, make_single
 
 pytestmark = pytest.mark.gpu
 
@@ -250,3 +250,40 @@ def test_lockstep_at_its_row_limit(autotune):
     over = make_batch(2, 61, 100, seed=29, n_lo=200, n_hi=300, n_max=300)
     with pytest.raises(ff.FolioError):
         ff.solve_batched(over, tol=1e-6, form="lockstep")
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_many_unrelated_markets_against_the_oracle(precision):
+    """ffo_solve_many: four unrelated markets (each its own n, F, Omega, delta, exposure rows
+    and bounds; k = 8 and m = 6 shared), from a single-workgroup team (n = 60) to teams of
+    several workgroups (n = 1100), in one launch: each against the oracle (paper eq. 1-3)
+    at the bars of the other batched forms, and against the plain solver."""
+    ff = _gpu()
+    tol, w_tol = BARS[precision]
+    insts = [make_single(n, 8, 6, seed=sd) for n, sd in ((300, 1), (1100, 2), (60, 3), (700, 4))]
+    print(f"[case] many n={[i['n'] for i in insts]} {precision}", flush=True)
+    Ws, infos = ff.solve_many(insts, tol=tol, precision=precision, time_limit_s=60.0)
+    torch.cuda.synchronize()
+    for inst, W, info in zip(insts, Ws, infos):
+        w = W.cpu().numpy()
+        assert info.status == 0 and info.rel_kkt <= tol, info
+        ref = oracle.solve(inst, tol=1e-10)
+        assert np.max(np.abs(w - ref.W)) <= w_tol, np.max(np.abs(w - ref.W))
+        pb = normalize(inst)
+        assert abs(objective(pb, w) - ref.phi) <= 1e-6 * abs(ref.phi)
+        Wp, ip = ff.solve_instance(inst, tol=tol, precision=precision)
+        assert np.max(np.abs(w - Wp.cpu().numpy())) <= w_tol
+
+
+def test_many_runs_the_benchmark_markets():
+    """The benchmark's own markets (n = 5000, k = 60, m = 80, seeds 1-3: three unrelated
+    universes) in one ffo_solve_many launch against the plain solver on each, both to
+    relative KKT 1e-8."""
+    ff = _gpu()
+    insts = [make_config(1, seed=sd) for sd in (1, 2, 3)]
+    Ws, infos = ff.solve_many(insts, tol=1e-8, time_limit_s=60.0)
+    torch.cuda.synchronize()
+    for inst, W, info in zip(insts, Ws, infos):
+        Wp, ip = ff.solve_instance(inst, tol=1e-8)
+        assert info.status == 0 and ip.status == 0 and info.rel_kkt <= 1e-8
+        assert np.max(np.abs(W.cpu().numpy() - Wp.cpu().numpy())) <= 1e-5
