@@ -583,6 +583,24 @@ def main():
             leg["rel_obj_max"] = max(e[1] for e in cerr)
         out["contract_accuracy_fp64"] = leg
         out["comparisons"] = comparisons(ff, torch, dev, dev_insts, a.tol, value)
+        # the same ten markets (ten unrelated universes) in one ffo_solve_many launch of the
+        # team form, FP64 and FP32, at the benchmark's tolerance, each result against the
+        # oracle's certified solution
+        for prec in ("fp64", "fp32"):
+            ff.solve_many(dev_insts, tol=a.tol, precision=prec)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            Wm, minfos = ff.solve_many(dev_insts, tol=a.tol, precision=prec)
+            torch.cuda.synchronize()
+            dtm = time.perf_counter() - t0
+            merr = [result_error(inst, W, golden("c1", inst["seed"])) for inst, W in zip(insts, Wm)
+                    if golden("c1", inst["seed"]) is not None]
+            out["comparisons"][f"many_n5000_seeds_1_10_{prec}_teams"] = {
+                "solves_per_s": len(minfos) / dtm, "batch_ms": dtm * 1e3, "vs_plain_fp64": (len(minfos) / dtm) / value,
+                "iters_max": int(max(i.iters for i in minfos)), "all_ok": all(i.status == 0 for i in minfos),
+                "w_inf_max_vs_oracle": max(e[0] for e in merr) if merr else None,
+                "rel_obj_max_vs_oracle": max(e[1] for e in merr) if merr else None,
+                "note": "the ten benchmark markets (seeds 1-10, each its own universe) in one ffo_solve_many launch"}
     if not a.no_cpu:
         out["cpu_baseline"] = cpu_baseline(insts[0], a.tol, a.cpu_max_iter)
     print(json.dumps(out), flush=True)
