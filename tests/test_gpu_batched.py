@@ -287,3 +287,35 @@ def test_many_runs_the_benchmark_markets():
         Wp, ip = ff.solve_instance(inst, tol=1e-8)
         assert info.status == 0 and ip.status == 0 and info.rel_kkt <= 1e-8
         assert np.max(np.abs(W.cpu().numpy() - Wp.cpu().numpy())) <= 1e-5
+
+
+def test_many_tiny_markets_against_the_oracle():
+    """ffo_solve_many on single-asset and tiny markets (n = 1, 2, 5; one workgroup each,
+    exchanging through LDS) against the oracle."""
+    ff = _gpu()
+    insts = [make_single(n, 2, 1, seed=sd) for n, sd in ((1, 5), (2, 6), (5, 7))]
+    Ws, infos = ff.solve_many(insts, tol=1e-9, time_limit_s=60.0)
+    torch.cuda.synchronize()
+    for inst, W, info in zip(insts, Ws, infos):
+        w = W.cpu().numpy()
+        assert info.status == 0 and info.rel_kkt <= 1e-9, info
+        ref = oracle.solve(inst, tol=1e-10)
+        assert np.max(np.abs(w - ref.W)) <= 1e-5
+        assert abs(objective(normalize(inst), w) - ref.phi) <= 1e-8 * abs(ref.phi)
+
+
+def test_many_markets_beyond_the_resident_grid():
+    """300 small unrelated markets, more than the resident workgroups: ffo_solve_many cuts
+    them into several launches (largest first); every instance converges, and a spread of
+    them agrees with the plain solver."""
+    ff = _gpu()
+    rng = np.random.default_rng(31)
+    sizes = rng.integers(20, 120, size=300)
+    insts = [make_single(int(n), 3, 2, seed=1000 + i) for i, n in enumerate(sizes)]
+    Ws, infos = ff.solve_many(insts, tol=1e-9, time_limit_s=60.0)
+    torch.cuda.synchronize()
+    assert all(i.status == 0 and i.rel_kkt <= 1e-9 for i in infos)
+    for b in range(0, 300, 37):
+        Wp, ip = ff.solve_instance(insts[b], tol=1e-9)
+        assert ip.status == 0
+        assert np.max(np.abs(Ws[b].cpu().numpy() - Wp.cpu().numpy())) <= 1e-5
