@@ -284,18 +284,22 @@ ffo_status ffo_solve_batched(int64_t B, const int64_t* n_b, int64_t n_max, int64
                              double lambda1, double lambda2, double lambda3, const ffo_options* opt,
                              void* stream, double* w_out, ffo_info* infos);
 
-/* Many unrelated single-period markets in one launch (paper Section 2.1, eq. 1-3, per
- * instance): instance b has its own n[b] assets, loadings, factor covariance, specific
- * vols, costs, exposure rows and bounds, with k factors and m exposure rows shared by all.
- * Each instance gets ffo_solve's setup (its own scaled rows and scales), then one team of
- * workgroups runs the solve kernel's loop for it, as in ffo_solve_batched's team form:
- * teams sized to n[b] (spare resident workgroups go to the teams with the most assets per
- * workgroup, down to 128 assets each), constraint slice and state in LDS when every team
- * of a launch fits, several launches when the minimal teams exceed the resident grid.
- * Host: n [B] (1 <= n[b] <= 2^24), infos [B], and the arrays of B device pointers
- *   alpha, delta, s, q, w0, w_out: [n[b]] each;  F: [n[b]][k];  Omega: [k][k];
- *   A: [m][n[b]];  L, U: [m]   (F, Omega may be NULL when k = 0; A, L, U when m = 0).
- * d, GMV, lambda1..3 as in ffo_solve, shared.  1 <= B <= 2^16.
+/* Many unrelated markets in one launch (paper Section 2.1, eq. 1-3, and Section 2.2,
+ * eq. 4-6, per instance): instance b has its own n[b] assets, loadings, factor covariance,
+ * specific vols, costs, exposure rows, bounds and (T > 0) terminal target, with k factors,
+ * m exposure rows and T shared by all.  Each instance gets ffo_solve's setup (its own
+ * scaled rows and scales), then one team of workgroups runs the solve kernel's loop for
+ * it, as in ffo_solve_batched's team form: teams sized to n[b] (spare resident workgroups
+ * go to the teams with the most assets per workgroup, down to 128 assets each; at most
+ * 2048 assets per workgroup, fewer when T periods of staging would not fit in LDS),
+ * constraint slice and state in LDS when every team of a launch fits, several launches
+ * when the minimal teams exceed the resident grid.
+ * Host: n [B] (1 <= n[b] <= 2^24), infos [B], and the arrays of B device pointers, with
+ * P = T - 1 decisions and T trades (P = T = 1 when T = 0):
+ *   alpha: [P][n[b]];  s, q: [T][n[b]];  delta, w0: [n[b]];  F: [n[b]][k];  Omega: [k][k];
+ *   A: [m][n[b]];  L, U: [m];  w_target: [n[b]] (w_target itself NULL iff T == 0);
+ *   w_out: [P][n[b]]   (F, Omega may be NULL when k = 0; A, L, U when m = 0).
+ * d, GMV, lambda1..3 as in ffo_solve, shared.  1 <= B <= 2^16; T = 0 or 2 <= T <= 4096.
  * opt->precision: FFO_FP64 or FFO_FP32; opt->workgroups and opt->batched_form are
  * ignored; statuses as in ffo_solve.  Every instance stops at its own relative KKT
  * tolerance; infos[b] holds its record.
@@ -305,12 +309,13 @@ ffo_status ffo_solve_batched(int64_t B, const int64_t* n_b, int64_t n_max, int64
  * and after the one value check for non-finite values, L > U or an Omega that is not
  * positive semidefinite.
  */
-ffo_status ffo_solve_many(int64_t B, const int64_t* n, int64_t k, int64_t m, const double* const* alpha,
+ffo_status ffo_solve_many(int64_t B, const int64_t* n, int64_t k, int64_t m, int64_t T, const double* const* alpha,
                           const double* const* F, const double* const* Omega, const double* const* delta,
                           const double* const* s, const double* const* q, const double* const* A,
-                          const double* const* L, const double* const* U, const double* const* w0, double d,
-                          double GMV, double lambda1, double lambda2, double lambda3, const ffo_options* opt,
-                          void* stream, double* const* w_out, ffo_info* infos);
+                          const double* const* L, const double* const* U, const double* const* w0,
+                          const double* const* w_target, double d, double GMV, double lambda1, double lambda2,
+                          double lambda3, const ffo_options* opt, void* stream, double* const* w_out,
+                          ffo_info* infos);
 
 /*
  * Risk-model construction (paper Section 3.2): the inputs S = beta Sigma_f beta^T + D of

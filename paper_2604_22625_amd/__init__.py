@@ -99,7 +99,7 @@ def lib() -> ctypes.CDLL:
         L.ffo_solve_batched.argtypes = [_I64, _P, _I64, _I64, _I64, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P,
                                         _D, _D, _D, _D, _D, ctypes.POINTER(_Options), _P, _P, _P]
         L.ffo_solve_batched.restype = ctypes.c_int
-        L.ffo_solve_many.argtypes = [_I64, _P, _I64, _I64, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P,
+        L.ffo_solve_many.argtypes = [_I64, _P, _I64, _I64, _I64, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P,
                                      _D, _D, _D, _D, _D, ctypes.POINTER(_Options), _P, _P, _P]
         L.ffo_solve_many.restype = ctypes.c_int
         L.ffo_adjoint.argtypes = [_I64, _I64, _I64, _I64, _P, _P, _P, _P, _P, _P, _D, _P, _P, _P, _P,
@@ -321,10 +321,11 @@ def solve_batched(batch: dict, *, tol: float = 1e-6, max_iter: int = 1_000_000, 
 def solve_many(insts, *, tol: float = 1e-6, max_iter: int = 1_000_000, time_limit_s: float = 360.0,
                check_every: int = 64, restart=(0.2, 0.8, 0.36), reflection: float = 1.0, verbose: int = 0,
                precision="fp64", raise_on_failure: bool = True, device=None, stream=None):
-    """Solve unrelated single-period instances (dicts in the layout of ``synth.make_single``,
-    each with its own n, F, Omega, delta, A, L, U and vectors; k, m, d, GMV and the lambdas
-    shared) in one launch of the team form (ffo_solve_many).  Returns (list of W [1][n_b]
-    float64 CUDA tensors, list of Info)."""
+    """Solve unrelated instances (dicts in the layout of ``synth.make_single`` or
+    ``synth.make_multi``, each with its own n, F, Omega, delta, A, L, U, vectors and target;
+    k, m, T, d, GMV and the lambdas shared) in one launch of the team form
+    (ffo_solve_many).  Returns (list of W [P][n_b] float64 CUDA tensors, P = T - 1 or 1,
+    list of Info)."""
     torch = _torch()
     if not torch.cuda.is_available():
         raise FolioError(3, "no GPU visible to PyTorch: the solver has no CPU path")
@@ -333,13 +334,13 @@ def solve_many(insts, *, tol: float = 1e-6, max_iter: int = 1_000_000, time_limi
         raise ValueError("solve_many needs at least one instance")
     dev = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
     first = insts[0]
-    k, m = int(first["k"]), int(first["m"])
+    k, m, T = int(first["k"]), int(first["m"]), int(first.get("T", 0) or 0)
+    P, Tp = (T - 1, T) if T else (1, 1)
     shared = ("d", "GMV", "lambda1", "lambda2", "lambda3")
     for inst in insts:
-        if int(inst.get("T", 0) or 0) != 0:
-            raise ValueError("solve_many takes single-period instances (T = 0)")
-        if int(inst["k"]) != k or int(inst["m"]) != m or any(float(inst[x]) != float(first[x]) for x in shared):
-            raise ValueError("solve_many needs the same k, m, d, GMV and lambdas in every instance")
+        if (int(inst["k"]) != k or int(inst["m"]) != m or int(inst.get("T", 0) or 0) != T
+                or any(float(inst[x]) != float(first[x]) for x in shared)):
+            raise ValueError("solve_many needs the same k, m, T, d, GMV and lambdas in every instance")
     B = len(insts)
     keep = []   # device tensors that must outlive the call
 
@@ -354,17 +355,18 @@ def solve_many(insts, *, tol: float = 1e-6, max_iter: int = 1_000_000, time_limi
         return ptrs
 
     n = np.ascontiguousarray(np.array([int(inst["n"]) for inst in insts], dtype=np.int64))
-    a = arr("alpha", lambda i: (int(i["n"]),))
+    a = arr("alpha", lambda i: (P, int(i["n"])))
     Fp = arr("F", lambda i: (int(i["n"]), k)) if k else None
     Op = arr("Omega", lambda i: (k, k)) if k else None
     dp = arr("delta", lambda i: (int(i["n"]),))
-    sp = arr("s", lambda i: (int(i["n"]),))
-    qp = arr("q", lambda i: (int(i["n"]),))
+    sp = arr("s", lambda i: (Tp, int(i["n"])))
+    qp = arr("q", lambda i: (Tp, int(i["n"])))
     Ap = arr("A", lambda i: (m, int(i["n"]))) if m else None
     Lp = arr("L", lambda i: (m,)) if m else None
     Up = arr("U", lambda i: (m,)) if m else None
     wp = arr("w0", lambda i: (int(i["n"]),))
-    Ws = [torch.empty(int(inst["n"]), dtype=torch.float64, device=dev) for inst in insts]
+    tp = arr("w_target", lambda i: (int(i["n"]),)) if T else None
+    Ws = [torch.empty((P, int(inst["n"])), dtype=torch.float64, device=dev) for inst in insts]
     wo = (ctypes.c_void_p * B)(*[w.data_ptr() for w in Ws])
     o = default_options()
     o.tol_rel_kkt = float(tol)
@@ -379,14 +381,15 @@ def solve_many(insts, *, tol: float = 1e-6, max_iter: int = 1_000_000, time_limi
     st = torch.cuda.current_stream(dev) if stream is None else stream
     vp = lambda x: ctypes.cast(x, ctypes.c_void_p) if x is not None else ctypes.c_void_p(0)
     with torch.cuda.device(dev):
-        rc = lib().ffo_solve_many(B, n.ctypes.data_as(ctypes.c_void_p), k, m, vp(a), vp(Fp), vp(Op), vp(dp), vp(sp),
-                                  vp(qp), vp(Ap), vp(Lp), vp(Up), vp(wp), float(first["d"]), float(first["GMV"]),
+        rc = lib().ffo_solve_many(B, n.ctypes.data_as(ctypes.c_void_p), k, m, T, vp(a), vp(Fp), vp(Op), vp(dp),
+                                  vp(sp), vp(qp), vp(Ap), vp(Lp), vp(Up), vp(wp), vp(tp), float(first["d"]),
+                                  float(first["GMV"]),
                                   float(first["lambda1"]), float(first["lambda2"]), float(first["lambda3"]),
                                   ctypes.byref(o), ctypes.c_void_p(st.cuda_stream), vp(wo), infos)
     out_infos = [Info(**{f[0]: getattr(i, f[0]) for f in _Info._fields_}) for i in infos]
     if rc == 1 or (rc in (2, 3)) or (rc != 0 and raise_on_failure):
         raise FolioError(rc, lib().ffo_last_error().decode())
-    return [w.reshape(1, -1) for w in Ws], out_infos
+    return Ws, out_infos
 
 
 def adjoint(inst: dict, W, Y, grad_w, *, omega: float = 0.0, tol: float = 1e-9, max_iter: int = 1_000_000,

@@ -1619,12 +1619,13 @@ ffo_status ffo_solve_batched(int64_t B, const int64_t* n_b, int64_t n_max, int64
   return collect_teams(B, n_b, hinfo, hstat, ms_setup, ms_iter, hCt, opt.verbose, infos);
 }
 
-ffo_status ffo_solve_many(int64_t B, const int64_t* n, int64_t k, int64_t m, const double* const* alpha,
+ffo_status ffo_solve_many(int64_t B, const int64_t* n, int64_t k, int64_t m, int64_t T, const double* const* alpha,
                           const double* const* F, const double* const* Omega, const double* const* delta,
                           const double* const* s, const double* const* q, const double* const* A,
-                          const double* const* L, const double* const* U, const double* const* w0, double d,
-                          double GMV, double lambda1, double lambda2, double lambda3, const ffo_options* opt_in,
-                          void* stream, double* const* w_out, ffo_info* infos) {
+                          const double* const* L, const double* const* U, const double* const* w0,
+                          const double* const* w_target, double d, double GMV, double lambda1, double lambda2,
+                          double lambda3, const ffo_options* opt_in, void* stream, double* const* w_out,
+                          ffo_info* infos) {
   g_err.clear();
   ffo_options opt;
   ffo_default_options(&opt);
@@ -1635,10 +1636,13 @@ ffo_status ffo_solve_many(int64_t B, const int64_t* n, int64_t k, int64_t m, con
     return fail(FFO_EINVAL, "null host array (n, alpha, delta, s, q, w0, w_out or infos)");
   if (k > 0 && (!F || !Omega)) return fail(FFO_EINVAL, "F and Omega are required when k > 0");
   if (m > 0 && (!A || !L || !U)) return fail(FFO_EINVAL, "A, L and U are required when m > 0");
+  if (!(T == 0 || (T >= 2 && T <= 4096))) return fail(FFO_EINVAL, "T must be 0 (single-period) or in [2, 4096]");
+  if ((T > 0) != (w_target != nullptr)) return fail(FFO_EINVAL, "w_target must be NULL iff T == 0");
   for (int64_t b = 0; b < B; ++b) {
-    if (ffo_status st = check_problem_args(n[b], k, m, 0, alpha[b], k ? F[b] : nullptr, k ? Omega[b] : nullptr,
+    if (ffo_status st = check_problem_args(n[b], k, m, T, alpha[b], k ? F[b] : nullptr, k ? Omega[b] : nullptr,
                                            delta[b], s[b], q[b], d, m ? A[b] : nullptr, m ? L[b] : nullptr,
-                                           m ? U[b] : nullptr, w0[b], GMV, lambda1, lambda2, lambda3, nullptr))
+                                           m ? U[b] : nullptr, w0[b], GMV, lambda1, lambda2, lambda3,
+                                           T ? w_target[b] : nullptr))
       return fail(st, "instance " + std::to_string(b) + ": " + g_err);
     if (!w_out[b]) return fail(FFO_EINVAL, "instance " + std::to_string(b) + ": null w_out");
     if (n[b] > (1 << 24)) return fail(FFO_EINVAL, "instance " + std::to_string(b) + ": n must be <= 2^24");
@@ -1657,10 +1661,12 @@ ffo_status ffo_solve_many(int64_t B, const int64_t* n, int64_t k, int64_t m, con
   const int cus = std::max(1, prop.multiProcessorCount);
   const int nr = (int)(m + k);
   const int prec = opt.precision == FFO_FP32 ? ffo::PREC_FP32 : ffo::PREC_FP64;
+  const int64_t P = T == 0 ? 1 : T - 1, Tp = T == 0 ? 1 : T;
 
   // ---- control and team sizing, as in the team form of ffo_solve_batched ----
   ffo::DevProblem p0{};
-  p0.k = (int)k; p0.m = (int)m; p0.P = 1; p0.Tp = 1; p0.nr = nr; p0.multi = 0; p0.kscaled = 1;
+  p0.k = (int)k; p0.m = (int)m; p0.P = (int)P; p0.Tp = (int)Tp; p0.nr = nr; p0.multi = T > 0 ? 1 : 0;
+  p0.kscaled = 1;
   ffo::DevControl c0{};
   c0.tol = opt.tol_rel_kkt; c0.time_limit_s = opt.time_limit_s;
   c0.r_suff = opt.restart_suff; c0.r_nec = opt.restart_nec; c0.r_art = opt.restart_art;
@@ -1668,16 +1674,20 @@ ffo_status ffo_solve_many(int64_t B, const int64_t* n, int64_t k, int64_t m, con
   c0.npow = 40; c0.verbose = opt.verbose; c0.spin_limit = 1u << 26; c0.wall_hz = (double)wall_khz * 1e3;
   c0.prec = prec; c0.spec = 1; c0.lds_k = 0; c0.lds_state = 0; c0.infeas = opt.infeasibility_check ? 1 : 0;
   c0.vmax = ffo::solve_vmax(p0);
-  const int NW_MAX = 2048, NW_MIN = 128;   // as in the team form of ffo_solve_batched
+  // assets per workgroup at most: 2048 as in the team form of ffo_solve_batched, halved
+  // while a workgroup's staging for P periods does not fit in LDS (multi-period)
+  const int NW_MIN = 128;
+  const size_t lds_lim = std::min<size_t>(prop.sharedMemPerBlock, 160 * 1024);
+  int NW_MAX = 2048;
   size_t lds_cap = 0;
-  {
+  for (;; NW_MAX /= 2) {
     ffo::DevProblem pp = p0;
     ffo::DevControl cc = c0;
     pp.n = NW_MAX; cc.nw = NW_MAX; cc.nwg = 1; cc.xmode = ffo::XM_LOCAL;
     lds_cap = ffo::solve_lds_bytes(pp, cc);
+    if (lds_cap <= lds_lim || NW_MAX <= 16) break;
   }
-  const size_t lds_lim = std::min<size_t>(prop.sharedMemPerBlock, 160 * 1024);
-  if (lds_cap > lds_lim) return fail(FFO_EINVAL, "m + k too large for the batched working set");
+  if (lds_cap > lds_lim) return fail(FFO_EINVAL, "m + k or T too large for the batched working set");
   const int occ = ffo::solve_batch_occupancy(0, 0, prec, lds_cap);
   if (occ < 1) return fail(FFO_EDEVICE, "the batched solve kernel cannot be resident");
   const int W = occ * cus;
@@ -1697,10 +1707,10 @@ ffo_status ffo_solve_many(int64_t B, const int64_t* n, int64_t k, int64_t m, con
     r.ldk = (int)((n[b] + 63) / 64 * 64);
     r.K = carve((size_t)std::max(nr, 1) * r.ldk, 8);
     r.Kf = carve(prec == ffo::PREC_FP32 ? (size_t)std::max(nr, 1) * r.ldk : 1, 4);
-    r.dr = carve(std::max(nr, 1), 8); r.dc = carve(nb, 8); r.drC = carve(nb, 8); r.ar = carve(nb, 8);
-    r.cv = carve(nb, 8); r.ca = carve(nb, 8); r.cb = carve(nb, 8);
+    r.dr = carve(std::max(nr, 1), 8); r.dc = carve(nb, 8); r.drC = carve(Tp * nb, 8); r.ar = carve(nb, 8);
+    r.cv = carve(nb, 8); r.ca = carve(Tp * nb, 8); r.cb = carve(Tp * nb, 8);
     r.bF = carve(std::max<int64_t>(k, 1), 8); r.cr = carve(1, 8); r.C = carve(std::max<int64_t>(k * k, 1), 8);
-    for (auto& o : r.st) o = carve(nb, 8);
+    for (int j = 0; j < 9; ++j) r.st[j] = carve((j < 6 ? P : Tp) * nb, 8);   // 6 primal [P][n], 3 trade [T][n]
   }
   const size_t oxb = carve((size_t)B * 3 * c0.vmax, 8), obar = carve(B, 8);
   const size_t oinfo = carve((size_t)B * ffo::INFO_LEN, 8), ostat = carve(B, 4), oflag = carve(1, 4);
@@ -1729,9 +1739,9 @@ ffo_status ffo_solve_many(int64_t B, const int64_t* n, int64_t k, int64_t m, con
   HIPCHK(hipEventRecord(ws->ev[0], hs));
   HIPCHK(fill(Bd + oflag, 4, 0u, hs));
   for (int64_t b = 0; b < B; ++b) {
-    hipLaunchKernelGGL(k_validate, dim3(64), dim3(256), 0, hs, n[b], n[b], n[b], n[b] * k, m, alpha[b],
+    hipLaunchKernelGGL(k_validate, dim3(64), dim3(256), 0, hs, n[b], P * n[b], Tp * n[b], n[b] * k, m, alpha[b],
                        k ? F[b] : nullptr, delta[b], s[b], q[b], m ? L[b] : nullptr, m ? U[b] : nullptr, w0[b],
-                       (const double*)nullptr, (int*)(Bd + oflag));
+                       T ? w_target[b] : (const double*)nullptr, (int*)(Bd + oflag));
     if (k > 0)
       HIPCHK(hipMemcpyAsync(Hb + hOm_o + (size_t)b * kk * 8, Omega[b], (size_t)k * k * 8, hipMemcpyDeviceToHost, hs));
   }
@@ -1755,9 +1765,9 @@ ffo_status ffo_solve_many(int64_t B, const int64_t* n, int64_t k, int64_t m, con
       HIPCHK(hipMemcpyAsync(D(r.C), hC, (size_t)k * k * 8, hipMemcpyHostToDevice, hs));
       HIPCHK(hipStreamSynchronize(hs));
     }
-    if (ffo::launch_setup(n[b], k, m, 1, 1, r.ldk, k ? F[b] : nullptr, D(r.C), m ? A[b] : nullptr, delta[b], s[b],
-                          q[b], nullptr, g1, g2, g3, D(r.K), D(r.dr), D(r.dc), D(r.drC), D(r.ar), D(r.cv), D(r.ca),
-                          D(r.cb), D(r.bF), D(r.cr), stream))
+    if (ffo::launch_setup(n[b], k, m, P, Tp, r.ldk, k ? F[b] : nullptr, D(r.C), m ? A[b] : nullptr, delta[b], s[b],
+                          q[b], T ? w_target[b] : nullptr, g1, g2, g3, D(r.K), D(r.dr), D(r.dc), D(r.drC), D(r.ar),
+                          D(r.cv), D(r.ca), D(r.cb), D(r.bF), D(r.cr), stream))
       return fail(FFO_EDEVICE, "setup kernel launch failed");
     if (prec == ffo::PREC_FP32 && ffo::launch_to_float(D(r.K), (float*)(Bd + r.Kf), (int64_t)nr * r.ldk, stream))
       return fail(FFO_EDEVICE, "setup kernel launch failed");
@@ -1765,7 +1775,7 @@ ffo_status ffo_solve_many(int64_t B, const int64_t* n, int64_t k, int64_t m, con
     p.n = (int)n[b]; p.ldk = r.ldk;
     p.K = D(r.K); p.Kf = prec == ffo::PREC_FP32 ? (const float*)(Bd + r.Kf) : nullptr;
     p.dr = D(r.dr); p.dc = D(r.dc); p.drC = D(r.drC); p.alpha = alpha[b]; p.arisk = D(r.ar); p.cvec = D(r.cv);
-    p.ca = D(r.ca); p.cb = D(r.cb); p.w0 = w0[b]; p.wT = nullptr;
+    p.ca = D(r.ca); p.cb = D(r.cb); p.w0 = w0[b]; p.wT = T ? w_target[b] : nullptr;
     p.L = m ? L[b] : nullptr; p.U = m ? U[b] : nullptr;
     p.bF = D(r.bF); p.crisk = D(r.cr); p.g1 = g1; p.d = d; p.g2 = g2;
     hP[b] = p;

@@ -138,7 +138,7 @@ def test_batched_rejects_invalid_arguments(kw, needle):
     assert needle in msg, msg
 
 
-def _call_many(B=3, n=(5, 7, 9), k=2, m=1, d=1.5, precision=0, null=(), null_at=None):
+def _call_many(B=3, n=(5, 7, 9), k=2, m=1, T=0, d=1.5, precision=0, null=(), null_at=None, with_target=None):
     """ffo_solve_many with fake device pointers in real host pointer arrays; invalid
     arguments must be rejected before any device pointer is touched.  null: arrays passed
     as NULL; null_at: (name, b) sets one instance's pointer to NULL."""
@@ -146,20 +146,21 @@ def _call_many(B=3, n=(5, 7, 9), k=2, m=1, d=1.5, precision=0, null=(), null_at=
     fake = 0x1000
     nn = np.ascontiguousarray(np.asarray(n, dtype=np.int64))
     arrays = {}
-    for name in ("alpha", "F", "Omega", "delta", "s", "q", "A", "L", "U", "w0", "w_out"):
+    for name in ("alpha", "F", "Omega", "delta", "s", "q", "A", "L", "U", "w0", "w_target", "w_out"):
         a = (ctypes.c_void_p * max(B, 1))(*([fake] * max(B, 1)))
         if null_at and null_at[0] == name:
             a[null_at[1]] = None
-        arrays[name] = None if name in null else ctypes.cast(a, ctypes.c_void_p)
+        skip = name in null or (name == "w_target" and not (T > 0 if with_target is None else with_target))
+        arrays[name] = None if skip else ctypes.cast(a, ctypes.c_void_p)
         arrays[name + "_keep"] = a
     infos = (ff._Info * max(B, 1))()
     o = ff.default_options()
     o.precision = precision
     lib = ff.lib()
     g = arrays
-    rc = lib.ffo_solve_many(B, nn.ctypes.data_as(ctypes.c_void_p), k, m, g["alpha"], g["F"], g["Omega"], g["delta"],
-                            g["s"], g["q"], g["A"], g["L"], g["U"], g["w0"], d, 1e9, 1e-9, 1.0, 1.0,
-                            ctypes.byref(o), None, g["w_out"], infos)
+    rc = lib.ffo_solve_many(B, nn.ctypes.data_as(ctypes.c_void_p), k, m, T, g["alpha"], g["F"], g["Omega"],
+                            g["delta"], g["s"], g["q"], g["A"], g["L"], g["U"], g["w0"], g["w_target"], d, 1e9,
+                            1e-9, 1.0, 1.0, ctypes.byref(o), None, g["w_out"], infos)
     return rc, lib.ffo_last_error().decode()
 
 
@@ -176,6 +177,10 @@ def _call_many(B=3, n=(5, 7, 9), k=2, m=1, d=1.5, precision=0, null=(), null_at=
     (dict(null=("L",)), "A, L and U"),
     (dict(null_at=("s", 1)), "instance 1"),
     (dict(null_at=("w_out", 2)), "instance 2"),
+    (dict(T=1), "T must"),
+    (dict(T=0, with_target=True), "w_target"),
+    (dict(T=3, with_target=False), "w_target"),
+    (dict(T=3, null_at=("w_target", 0)), "instance 0"),
 ])
 def test_many_rejects_invalid_arguments(kw, needle):
     rc, msg = _call_many(**kw)

@@ -11,6 +11,7 @@ import pytest
 import oracle
 from oracle.problem import normalize, objective
 from synth import make_batch, batch_instance, make_config, make_single
+from synth.markets import make_multi
 
 pytestmark = pytest.mark.gpu
 
@@ -319,3 +320,25 @@ def test_many_markets_beyond_the_resident_grid():
         Wp, ip = ff.solve_instance(insts[b], tol=1e-9)
         assert ip.status == 0
         assert np.max(np.abs(Ws[b].cpu().numpy() - Wp.cpu().numpy())) <= 1e-5
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_many_multi_period_markets_against_the_oracle(precision):
+    """ffo_solve_many on unrelated multi-period markets (T = 4: three decisions and four
+    trades, each market its own n, data and terminal target; paper eq. 4-6) in one launch,
+    each against the oracle at the batched bars and against the plain solver."""
+    ff = _gpu()
+    tol, w_tol = BARS[precision]
+    insts = [make_multi(4, n, 4, 3, seed=sd) for n, sd in ((150, 1), (400, 2), (60, 3))]
+    print(f"[case] many multi-period n={[i['n'] for i in insts]} {precision}", flush=True)
+    Ws, infos = ff.solve_many(insts, tol=tol, precision=precision, time_limit_s=60.0)
+    torch.cuda.synchronize()
+    for inst, W, info in zip(insts, Ws, infos):
+        w = W.cpu().numpy()
+        assert w.shape == (3, inst["n"])
+        assert info.status == 0 and info.rel_kkt <= tol, info
+        ref = oracle.solve(inst, tol=1e-10)
+        assert np.max(np.abs(w - ref.W)) <= w_tol, np.max(np.abs(w - ref.W))
+        assert abs(objective(normalize(inst), w) - ref.phi) <= 1e-6 * abs(ref.phi)
+        Wp, ip = ff.solve_instance(inst, tol=tol, precision=precision)
+        assert np.max(np.abs(w - Wp.cpu().numpy())) <= w_tol
