@@ -342,3 +342,12 @@ def test_many_multi_period_markets_against_the_oracle(precision):
         assert abs(objective(normalize(inst), w) - ref.phi) <= 1e-6 * abs(ref.phi)
         Wp, ip = ff.solve_instance(inst, tol=tol, precision=precision)
         assert np.max(np.abs(w - Wp.cpu().numpy())) <= w_tol
+
+
+def test_many_refuses_a_working_set_beyond_lds():
+    """T = 20 with 100 rows: even 16 assets per workgroup need more LDS than a CU has, so
+    ffo_solve_many refuses the shape (FFO_EINVAL) before any solve."""
+    ff = _gpu()
+    with pytest.raises(ff.FolioError) as e:
+        ff.solve_many([make_config(2, seed=20), make_config(2, seed=21)], tol=1e-6)
+    assert e.value.status == 1 and "too large" in str(e.value)
