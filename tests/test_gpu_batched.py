@@ -351,3 +351,17 @@ def test_many_refuses_a_working_set_beyond_lds():
     with pytest.raises(ff.FolioError) as e:
         ff.solve_many([make_config(2, seed=20), make_config(2, seed=21)], tol=1e-6)
     assert e.value.status == 1 and "too large" in str(e.value)
+
+
+def test_many_runs_the_differentiation_markets():
+    """The T = 10, n = 2000 markets (k = 40, m = 40; seeds 40 and 41, each its own universe)
+    in one ffo_solve_many launch, at most 256 assets per workgroup, against the plain solver
+    on each, both to relative KKT 1e-8."""
+    ff = _gpu()
+    insts = [make_config(4, seed=sd) for sd in (40, 41)]
+    Ws, infos = ff.solve_many(insts, tol=1e-8, time_limit_s=60.0)
+    torch.cuda.synchronize()
+    for inst, W, info in zip(insts, Ws, infos):
+        Wp, ip = ff.solve_instance(inst, tol=1e-8)
+        assert info.status == 0 and ip.status == 0 and info.rel_kkt <= 1e-8
+        assert np.max(np.abs(W.cpu().numpy() - Wp.cpu().numpy())) <= 1e-5
