@@ -601,6 +601,25 @@ def main():
                 "w_inf_max_vs_oracle": max(e[0] for e in merr) if merr else None,
                 "rel_obj_max_vs_oracle": max(e[1] for e in merr) if merr else None,
                 "note": "the ten benchmark markets (seeds 1-10, each its own universe) in one ffo_solve_many launch"}
+        # ten multi-period markets of the differentiation shape (T = 10, n = 2000, k = 40,
+        # m = 40, seeds 40-49): one ffo_solve_many launch against the plain kernel on each
+        c4s = [make_config(4, seed=sd) for sd in range(40, 50)]
+        for d in c4s:
+            for kk in keys:
+                if d.get(kk) is not None:
+                    d[kk] = torch.as_tensor(d[kk], dtype=torch.float64, device=dev).contiguous()
+        plain4 = lambda: [ff.solve_instance(d, tol=a.tol) for d in c4s]
+        plain4()
+        dt4, r4 = _timed(torch, plain4, 1)
+        for prec in ("fp64", "fp32"):
+            ff.solve_many(c4s, tol=a.tol, precision=prec)
+            dtm, (Wm, minfos) = _timed(torch, lambda: ff.solve_many(c4s, tol=a.tol, precision=prec), 1)
+            out["comparisons"][f"many_T10_n2000_seeds_40_49_{prec}_teams"] = {
+                "solves_per_s": 10 / dtm, "batch_ms": dtm * 1e3, "plain_fp64_ms": dt4 * 1e3,
+                "speedup_vs_plain_fp64": dt4 / dtm, "iters_max": int(max(i.iters for i in minfos)),
+                "all_ok": all(i.status == 0 for i in minfos),
+                "w_max_abs_diff_vs_plain_fp64": float(max(float(torch.max(torch.abs(W - r[0]))) for W, r in zip(Wm, r4))),
+                "note": "ten T=10 n=2000 k=40 m=40 markets (seeds 40-49, each its own universe) in one ffo_solve_many launch"}
     if not a.no_cpu:
         out["cpu_baseline"] = cpu_baseline(insts[0], a.tol, a.cpu_max_iter)
     print(json.dumps(out), flush=True)

@@ -1672,7 +1672,10 @@ ffo_status ffo_solve_many(int64_t B, const int64_t* n, int64_t k, int64_t m, int
   c0.r_suff = opt.restart_suff; c0.r_nec = opt.restart_nec; c0.r_art = opt.restart_art;
   c0.rho = opt.reflection; c0.eta_safety = 0.95; c0.max_iter = opt.max_iter; c0.check_every = opt.check_every;
   c0.npow = 40; c0.verbose = opt.verbose; c0.spin_limit = 1u << 26; c0.wall_hz = (double)wall_khz * 1e3;
-  c0.prec = prec; c0.spec = 1; c0.lds_k = 0; c0.lds_state = 0; c0.infeas = opt.infeasibility_check ? 1 : 0;
+  // the speculative single exchange as in ffo_solve: on for single-period problems by
+  // default, off for multi-period ones, unless opt->speculative says otherwise
+  c0.spec = opt.speculative < 0 ? (P == 1 ? 1 : 0) : (opt.speculative ? 1 : 0);
+  c0.prec = prec; c0.lds_k = 0; c0.lds_state = 0; c0.infeas = opt.infeasibility_check ? 1 : 0;
   c0.vmax = ffo::solve_vmax(p0);
   // assets per workgroup at most: 2048 as in the team form of ffo_solve_batched, halved
   // while a workgroup's staging for P periods does not fit in LDS (multi-period)
