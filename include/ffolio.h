@@ -300,14 +300,15 @@ ffo_status ffo_solve_batched(int64_t B, const int64_t* n_b, int64_t n_max, int64
  *   A: [m][n[b]];  L, U: [m];  w_target: [n[b]] (w_target itself NULL iff T == 0);
  *   w_out: [P][n[b]]   (F, Omega may be NULL when k = 0; A, L, U when m = 0).
  * d, GMV, lambda1..3 as in ffo_solve, shared.  1 <= B <= 2^16; T = 0 or 2 <= T <= 4096.
- * opt->precision: FFO_FP64 or FFO_FP32; opt->workgroups and opt->batched_form are
- * ignored; statuses as in ffo_solve.  Every instance stops at its own relative KKT
+ * opt->precision: FFO_FP64 or FFO_FP32; opt->speculative as in ffo_solve (by default on
+ * for T = 0, off otherwise); opt->workgroups, opt->batched_form and opt->breakpoint_lists
+ * are ignored; statuses as in ffo_solve.  Every instance stops at its own relative KKT
  * tolerance; infos[b] holds its record.
  * Returns FFO_OK if every instance converged, else the most severe instance status
  * (FFO_EDEVICE > FFO_NUMERIC > FFO_INFEASIBLE > FFO_TIMEOUT > FFO_NOT_CONVERGED).
  * FFO_EINVAL is returned before any device work for bad sizes, null pointers or options,
- * and after the one value check for non-finite values, L > U or an Omega that is not
- * positive semidefinite.
+ * or a working set beyond LDS, and after the one value check for non-finite values,
+ * L > U or an Omega that is not positive semidefinite.
  */
 ffo_status ffo_solve_many(int64_t B, const int64_t* n, int64_t k, int64_t m, int64_t T, const double* const* alpha,
                           const double* const* F, const double* const* Omega, const double* const* delta,

@@ -320,7 +320,8 @@ def solve_batched(batch: dict, *, tol: float = 1e-6, max_iter: int = 1_000_000, 
 
 def solve_many(insts, *, tol: float = 1e-6, max_iter: int = 1_000_000, time_limit_s: float = 360.0,
                check_every: int = 64, restart=(0.2, 0.8, 0.36), reflection: float = 1.0, verbose: int = 0,
-               precision="fp64", raise_on_failure: bool = True, device=None, stream=None):
+               precision="fp64", speculative: int = -1, raise_on_failure: bool = True, device=None,
+               stream=None):
     """Solve unrelated instances (dicts in the layout of ``synth.make_single`` or
     ``synth.make_multi``, each with its own n, F, Omega, delta, A, L, U, vectors and target;
     k, m, T, d, GMV and the lambdas shared) in one launch of the team form
@@ -377,6 +378,7 @@ def solve_many(insts, *, tol: float = 1e-6, max_iter: int = 1_000_000, time_limi
     o.reflection = float(reflection)
     o.verbose = int(verbose)
     o.precision = PRECISION[precision] if isinstance(precision, str) else int(precision)
+    o.speculative = int(speculative)
     infos = (_Info * B)()
     st = torch.cuda.current_stream(dev) if stream is None else stream
     vp = lambda x: ctypes.cast(x, ctypes.c_void_p) if x is not None else ctypes.c_void_p(0)
